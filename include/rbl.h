@@ -1,0 +1,147 @@
+/*
+ * rbl — batched relative-binned Whittle log-likelihood and its 13-parameter
+ * gradient for binary-neutron-star signals, on one AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the statement of the problem in arXiv:2404.11397:
+ *   Sec. II A, Eqs. (2)-(3): Whittle log-likelihood with the noise-weighted
+ *     inner product <a, b> = 4 Re sum_k a_k conj(b_k) / S_k  df   over the grid
+ *     f_k = f_low + k df (both band ends included), up to a theta-independent
+ *     constant:  lnL = sum_det [ Re <d, h>_c - <h, h> / 2 ];
+ *   Sec. II C, Eqs. (4)-(5): relative binning — the ratio r = h(theta)/h(theta0)
+ *     is taken at the bin edges and modelled as linear inside each bin about
+ *     the bin centre, so lnL reduces to sums over bins of precomputed summary
+ *     data (A0, A1, B0, B1) and the ratio;
+ *   Sec. II B: TaylorF2 and IMRPhenomD_NRTidalv2 waveforms; Tab. II: the 13
+ *     parameters.
+ *
+ * Parameter vector theta (float64, 13 per chain, row-major [B][13]):
+ *   0 Mc [Msun, detector frame]  1 q = m2/m1  2 chi1  3 chi2  4 Lambda1  5 Lambda2
+ *   6 dL [Mpc]  7 tc [s]  8 phic [rad, orbital]  9 iota  10 psi  11 ra  12 dec [rad]
+ *
+ * Conventions: h_d(f) = (C_d/dL) A(f) exp(-i Psi_int(f)) exp(2i phic)
+ *   exp(-2 pi i f (tc + dt_d)), C_d = (1+cos^2 iota)/2 F+_d - i cos(iota) Fx_d,
+ *   F = D : e with the detector tensor D, dt_d = -(r_d . n)/c, n the source
+ *   direction at hour angle ra - gmst; Earth rotation over a segment ignored.
+ *
+ * Errors: every call returns RBL_OK (0) or a negative code; rbl_last_error()
+ * gives a message (thread-local).  Argument errors are reported before any
+ * work is enqueued.  Device errors surface at the call or at the next call.
+ * Nothing aborts.  Per-chain domain problems are not call errors: a NaN in a
+ * chain's theta gives lnL = NaN and a NaN gradient row; a finite theta outside
+ * the physical domain (Mc <= 0, q <= 0, dL <= 0, |chi| >= 1, Lambda < 0) gives
+ * lnL = -inf and a zero gradient row.  q > 1 is allowed (labels swapped).
+ *
+ * Ownership: the caller owns theta, lnL, grad and the workspace (device
+ * memory).  An event owns its device buffers from rbl_event_create to
+ * rbl_event_free and is immutable in between, so calls on one event from
+ * different streams may overlap provided each call has its own workspace.
+ * Nothing is retained after a call returns.
+ */
+#ifndef RBL_H
+#define RBL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RBL_OK = 0,
+    RBL_EINVAL = -1,   /* null pointer, negative size, bad enum, n_det not 1..3 */
+    RBL_EEDGES = -2,   /* bin edges not strictly increasing / outside the grid / ends wrong */
+    RBL_EPSD = -3,     /* PSD <= 0 or not finite */
+    RBL_ENOMEM = -4,   /* device allocation failed */
+    RBL_EDEVICE = -5,  /* HIP runtime error (message in rbl_last_error) */
+    RBL_EREF = -6,     /* reference waveform zero or not finite at a bin edge */
+    RBL_EUNSUPPORTED = -7 /* feature not available for this event (e.g. no grid kept) */
+};
+
+enum { RBL_TAYLORF2 = 0, RBL_PHENOMD_NRTV2 = 1 };
+enum { RBL_FP64 = 0, RBL_MIXED = 1 };
+
+/* Event flags. */
+#define RBL_KEEP_B2          0x1u  /* keep the second-order B2 term of <h, h> (Sec. II C reading) */
+#define RBL_REF_TAPER        0x2u  /* taper the IMRPhenomD_NRTidalv2 reference too (the paper's
+                                      pipeline does not, Sec. II C 1) */
+#define RBL_KEEP_GRID        0x4u  /* keep data and PSD resident for rbl_loglike_full */
+#define RBL_INPUT_ON_DEVICE  0x8u  /* data and psd are device pointers */
+
+typedef struct rbl_event rbl_event;
+
+typedef struct {
+    int32_t n_det;            /* 1..3 */
+    int32_t waveform;         /* RBL_TAYLORF2 | RBL_PHENOMD_NRTV2 */
+    int32_t n_bins;           /* >= 1 */
+    uint32_t flags;           /* RBL_* flags above */
+    int64_t n_freq;           /* grid size N >= 2 */
+    double f_low;             /* first grid frequency [Hz] > 0 */
+    double delta_f;           /* grid spacing [Hz] = 1/T > 0 */
+    double gmst;              /* Greenwich mean sidereal time of the segment [rad] */
+    const double *data;       /* complex strain, interleaved [n_det][n_freq][2]; host unless
+                                 RBL_INPUT_ON_DEVICE; copied, not retained */
+    const double *psd;        /* one-sided PSD [n_det][n_freq], > 0 and finite; same placement */
+    const double *det_tensor; /* host [n_det][3][3], Earth-fixed, D = (x x^T - y y^T)/2 */
+    const double *det_vertex; /* host [n_det][3], Earth-fixed vertex position [m] */
+    const double *theta_ref;  /* host [13], the fiducial (reference) parameters theta0 */
+    const int64_t *edges;     /* host [n_bins + 1] grid indices of the bin edges: strictly
+                                 increasing, first 0, last n_freq - 1 (Sec. II C) */
+} rbl_event_desc;
+
+/* Build the event (the summary-data step of Sec. II C): reference waveform on the
+ * full grid, per-(detector, bin) summary data A0, A1, B0, B1 (and B2), and the
+ * per-edge coefficient tables used by the likelihood kernels.  Enqueued on
+ * `hip_stream` (NULL = default stream) and completed before returning.
+ * Returns RBL_EREF if the reference strain vanishes at a bin edge of some
+ * detector (the ratio of Eq. (4) is then undefined). */
+int rbl_event_create(const rbl_event_desc *desc, void *hip_stream, rbl_event **out);
+void rbl_event_free(rbl_event *ev);
+
+/* Bytes of device workspace that rbl_loglike / rbl_loglike_grad need for B chains. */
+int64_t rbl_workspace_bytes(const rbl_event *ev, int64_t B, int32_t with_grad);
+
+/* Relative-binned lnL (Eq. (2) with Eqs. (4)-(5)) for B chains.
+ * theta_dev [B][13], lnl_dev [B]: device float64.  workspace: device, at least
+ * rbl_workspace_bytes(ev, B, 0) bytes, 256-byte aligned.  precision: RBL_FP64 or
+ * RBL_MIXED (phase in FP64, reduced to revolutions; sin/cos, amplitude and per-bin
+ * products in FP32; final sums in FP64).  Asynchronous on hip_stream.  B = 0 is a no-op. */
+int rbl_loglike(const rbl_event *ev, const double *theta_dev, int64_t B, int32_t precision,
+                double *lnl_dev, void *workspace, void *hip_stream);
+
+/* lnL and its gradient with respect to the 13 parameters (angles iota and dec as
+ * angles), by a hand-written adjoint of the relative-binned sum.  grad_dev [B][13]. */
+int rbl_loglike_grad(const rbl_event *ev, const double *theta_dev, int64_t B, int32_t precision,
+                     double *lnl_dev, double *grad_dev, void *workspace, void *hip_stream);
+
+/* Full-grid lnL (Eqs. (2)-(3) without binning), FP64; needs RBL_KEEP_GRID.
+ * Workspace as for rbl_loglike.  Used for validation and to report the binning error. */
+int rbl_loglike_full(const rbl_event *ev, const double *theta_dev, int64_t B, double *lnl_dev,
+                     void *workspace, void *hip_stream);
+
+/* Projected strain h_d(f_k; theta) on a grid for one parameter vector (host theta[13]);
+ * out_dev [n_det][n_freq][2] complex float64, device.  `taper` selects the Planck taper
+ * of IMRPhenomD_NRTidalv2 (ignored for TaylorF2).  Used to make injections. */
+int rbl_strain(int32_t waveform, int32_t n_det, const double *det_tensor, const double *det_vertex,
+               double gmst, double f_low, double delta_f, int64_t n_freq, const double *theta,
+               int32_t taper, double *out_dev, void *hip_stream);
+
+/* Copy the summary data to host: [n_det][n_bins][7] = (Re A0, Im A0, Re A1, Im A1, B0, B1, B2). */
+int rbl_event_get_summary(const rbl_event *ev, double *host_out);
+
+/* Event shape and resident device footprint in bytes. */
+int rbl_event_info(const rbl_event *ev, int32_t *n_det, int32_t *n_bins, int32_t *waveform,
+                   int64_t *footprint_bytes);
+
+/* Bin edges from the post-Newtonian phase-bound ansatz of Sec. II C (host computation):
+ * the phase Phi(f) = sum_g sgn(g) (f/f*_g)^g, g in {-5/3, -2/3, 1, 5/3, 7/3}
+ * (f* = f_low for g < 0, f_high for g > 0) is split into n_bins equal steps; each step
+ * is snapped to the nearest grid index; indices are made strictly increasing.
+ * edges_out [n_bins + 1]. */
+int rbl_bin_edges(double f_low, double delta_f, int64_t n_freq, int32_t n_bins, int64_t *edges_out);
+
+const char *rbl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBL_H */

@@ -1,0 +1,80 @@
+"""ctypes binding of librbl.so (argument marshalling only).
+
+The library is the HIP build in this directory.  If it is missing or cannot
+be loaded, every call raises: there is no fallback implementation.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librbl.so")
+
+RBL_OK = 0
+RBL_TAYLORF2, RBL_PHENOMD_NRTV2 = 0, 1
+RBL_FP64, RBL_MIXED = 0, 1
+RBL_KEEP_B2, RBL_REF_TAPER, RBL_KEEP_GRID, RBL_INPUT_ON_DEVICE = 0x1, 0x2, 0x4, 0x8
+ERROR_NAMES = {-1: "RBL_EINVAL", -2: "RBL_EEDGES", -3: "RBL_EPSD", -4: "RBL_ENOMEM",
+               -5: "RBL_EDEVICE", -6: "RBL_EREF", -7: "RBL_EUNSUPPORTED"}
+
+EXPORTS = ("rbl_event_create", "rbl_event_free", "rbl_workspace_bytes", "rbl_loglike",
+           "rbl_loglike_grad", "rbl_loglike_full", "rbl_strain", "rbl_event_get_summary",
+           "rbl_event_info", "rbl_bin_edges", "rbl_last_error")
+
+
+class RblError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class EventDesc(ctypes.Structure):
+    _fields_ = [("n_det", ctypes.c_int32), ("waveform", ctypes.c_int32), ("n_bins", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("n_freq", ctypes.c_int64), ("f_low", ctypes.c_double),
+                ("delta_f", ctypes.c_double), ("gmst", ctypes.c_double),
+                ("data", ctypes.c_void_p), ("psd", ctypes.c_void_p),
+                ("det_tensor", ctypes.c_void_p), ("det_vertex", ctypes.c_void_p),
+                ("theta_ref", ctypes.c_void_p), ("edges", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load librbl.so once (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"librbl.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.rbl_event_create.argtypes = [ctypes.POINTER(EventDesc), vp, ctypes.POINTER(vp)]
+    L.rbl_event_create.restype = ctypes.c_int
+    L.rbl_event_free.argtypes = [vp]
+    L.rbl_event_free.restype = None
+    L.rbl_workspace_bytes.argtypes = [vp, i64, i32]
+    L.rbl_workspace_bytes.restype = i64
+    L.rbl_loglike.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+    L.rbl_loglike.restype = ctypes.c_int
+    L.rbl_loglike_grad.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp]
+    L.rbl_loglike_grad.restype = ctypes.c_int
+    L.rbl_loglike_full.argtypes = [vp, vp, i64, vp, vp, vp]
+    L.rbl_loglike_full.restype = ctypes.c_int
+    L.rbl_strain.argtypes = [i32, i32, vp, vp, dbl, dbl, dbl, i64, vp, i32, vp, vp]
+    L.rbl_strain.restype = ctypes.c_int
+    L.rbl_event_get_summary.argtypes = [vp, vp]
+    L.rbl_event_get_summary.restype = ctypes.c_int
+    L.rbl_event_info.argtypes = [vp, vp, vp, vp, vp]
+    L.rbl_event_info.restype = ctypes.c_int
+    L.rbl_bin_edges.argtypes = [dbl, dbl, i64, i32, vp]
+    L.rbl_bin_edges.restype = ctypes.c_int
+    L.rbl_last_error.argtypes = []
+    L.rbl_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def check(rc):
+    if rc != RBL_OK:
+        raise RblError(rc, lib().rbl_last_error().decode())
+    return rc

@@ -1,0 +1,447 @@
+// Host side of the C-ABI: validation, resident event state, kernel launches.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rbl.h"
+#include "rbl_launch.h"
+
+using namespace rbl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return RBL_EDEVICE;
+}
+
+constexpr int64_t kChunk = 512;     // grid points per summary work item
+constexpr int64_t kAlign = 256;
+
+int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool theta_in_domain(const double* t) {
+    for (int i = 0; i < 13; ++i)
+        if (!std::isfinite(t[i])) return false;
+    return t[0] > 0.0 && t[1] > 0.0 && t[6] > 0.0 && std::fabs(t[2]) < 1.0 && std::fabs(t[3]) < 1.0 &&
+           t[4] >= 0.0 && t[5] >= 0.0;
+}
+
+// Device allocations of one event, released together.
+struct DevList {
+    std::vector<void*> ptrs;
+    hipError_t alloc(void** p, size_t bytes) {
+        hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+        if (e == hipSuccess) ptrs.push_back(*p);
+        return e;
+    }
+    void release() {
+        for (void* p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+    }
+};
+
+}  // namespace
+
+struct rbl_event {
+    int32_t n_det = 0, n_bins = 0, n_nodes = 0, n_nodes_pad = 0, waveform = 0;
+    uint32_t flags = 0;
+    int64_t n_freq = 0;
+    double f_low = 0, delta_f = 0, gmst = 0;
+    Network net{};
+    RefConsts ref{};
+    EventDev dev{};
+    double* d_summary = nullptr;
+    double* d_data = nullptr;  // only with RBL_KEEP_GRID
+    double* d_psd = nullptr;
+    int64_t footprint = 0;
+    DevList mem;
+};
+
+extern "C" const char* rbl_last_error(void) { return g_err.c_str(); }
+
+extern "C" int rbl_bin_edges(double f_low, double delta_f, int64_t n_freq, int32_t n_bins, int64_t* edges_out) {
+    if (!edges_out) return fail(RBL_EINVAL, "rbl_bin_edges: null output");
+    if (!(f_low > 0.0) || !(delta_f > 0.0) || n_freq < 2) return fail(RBL_EINVAL, "rbl_bin_edges: bad grid");
+    if (n_bins < 1 || n_bins > n_freq - 1) return fail(RBL_EINVAL, "rbl_bin_edges: need 1 <= n_bins <= n_freq-1");
+    static const double g[5] = {-5.0 / 3.0, -2.0 / 3.0, 1.0, 5.0 / 3.0, 7.0 / 3.0};
+    const double f_high = f_low + (double)(n_freq - 1) * delta_f;
+    std::vector<double> phi((size_t)n_freq);
+    for (int64_t k = 0; k < n_freq; ++k) {
+        const double f = f_low + (double)k * delta_f;
+        double s = 0.0;
+        for (double gg : g) {
+            const double fs = gg < 0.0 ? f_low : f_high;
+            s += (gg < 0.0 ? -1.0 : 1.0) * std::pow(f / fs, gg);
+        }
+        phi[(size_t)k] = s;
+    }
+    const double p0 = phi.front(), p1 = phi.back();
+    for (int32_t i = 0; i <= n_bins; ++i) {
+        const double tgt = p0 + (p1 - p0) * (double)i / (double)n_bins;
+        // first index with phi >= tgt, clipped to [1, n-1]; pick the nearer neighbour
+        int64_t pos = std::lower_bound(phi.begin(), phi.end(), tgt) - phi.begin();
+        pos = std::min<int64_t>(std::max<int64_t>(pos, 1), n_freq - 1);
+        edges_out[i] = (tgt - phi[(size_t)pos - 1] <= phi[(size_t)pos] - tgt) ? pos - 1 : pos;
+    }
+    edges_out[0] = 0;
+    edges_out[n_bins] = n_freq - 1;
+    for (int32_t i = 1; i <= n_bins; ++i) edges_out[i] = std::max(edges_out[i], edges_out[i - 1] + 1);
+    edges_out[n_bins] = n_freq - 1;
+    for (int32_t i = n_bins - 1; i >= 0; --i) edges_out[i] = std::min(edges_out[i], edges_out[i + 1] - 1);
+    return RBL_OK;
+}
+
+static int validate_desc(const rbl_event_desc* d) {
+    if (!d) return fail(RBL_EINVAL, "rbl_event_create: null descriptor");
+    if (d->n_det < 1 || d->n_det > kMaxDet) return fail(RBL_EINVAL, "rbl_event_create: n_det must be 1..3");
+    if (d->waveform != RBL_TAYLORF2 && d->waveform != RBL_PHENOMD_NRTV2)
+        return fail(RBL_EINVAL, "rbl_event_create: unknown waveform");
+    if (d->waveform == RBL_PHENOMD_NRTV2)
+        return fail(RBL_EUNSUPPORTED, "rbl_event_create: IMRPhenomD_NRTidalv2 is not available in this build");
+    if (d->n_freq < 2) return fail(RBL_EINVAL, "rbl_event_create: n_freq must be >= 2");
+    if (!(d->f_low > 0.0) || !std::isfinite(d->f_low)) return fail(RBL_EINVAL, "rbl_event_create: f_low must be > 0");
+    if (!(d->delta_f > 0.0) || !std::isfinite(d->delta_f)) return fail(RBL_EINVAL, "rbl_event_create: delta_f must be > 0");
+    if (!std::isfinite(d->gmst)) return fail(RBL_EINVAL, "rbl_event_create: gmst not finite");
+    if (!d->data || !d->psd || !d->det_tensor || !d->det_vertex || !d->theta_ref || !d->edges)
+        return fail(RBL_EINVAL, "rbl_event_create: null pointer in descriptor");
+    if (d->n_bins < 1 || (int64_t)d->n_bins > d->n_freq - 1)
+        return fail(RBL_EEDGES, "rbl_event_create: need 1 <= n_bins <= n_freq - 1");
+    if (d->edges[0] != 0 || d->edges[d->n_bins] != d->n_freq - 1)
+        return fail(RBL_EEDGES, "rbl_event_create: first edge must be 0 and last n_freq - 1");
+    for (int32_t i = 0; i < d->n_bins; ++i)
+        if (!(d->edges[i + 1] > d->edges[i])) return fail(RBL_EEDGES, "rbl_event_create: edges not strictly increasing");
+    for (int i = 0; i < 9 * d->n_det; ++i)
+        if (!std::isfinite(d->det_tensor[i])) return fail(RBL_EINVAL, "rbl_event_create: detector tensor not finite");
+    for (int i = 0; i < 3 * d->n_det; ++i)
+        if (!std::isfinite(d->det_vertex[i])) return fail(RBL_EINVAL, "rbl_event_create: detector vertex not finite");
+    if (!theta_in_domain(d->theta_ref)) return fail(RBL_EINVAL, "rbl_event_create: theta_ref outside the physical domain");
+    return RBL_OK;
+}
+
+extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rbl_event** out) {
+    if (!out) return fail(RBL_EINVAL, "rbl_event_create: null output");
+    *out = nullptr;
+    int rc = validate_desc(desc);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int nd = desc->n_det;
+    const int64_t n = desc->n_freq;
+    const int nb = desc->n_bins;
+    const bool on_dev = (desc->flags & RBL_INPUT_ON_DEVICE) != 0;
+
+    // PSD check (host copy if the input is on the device).
+    {
+        std::vector<double> tmp;
+        const double* psd = desc->psd;
+        if (on_dev) {
+            tmp.resize((size_t)(nd * n));
+            hipError_t e = hipMemcpy(tmp.data(), desc->psd, sizeof(double) * nd * n, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_fail(e, "rbl_event_create: reading psd");
+            psd = tmp.data();
+        }
+        for (int64_t i = 0; i < nd * n; ++i)
+            if (!(psd[i] > 0.0) || !std::isfinite(psd[i])) return fail(RBL_EPSD, "rbl_event_create: psd must be > 0 and finite");
+    }
+
+    rbl_event* ev = new rbl_event();
+    ev->n_det = nd;
+    ev->n_bins = nb;
+    ev->n_nodes = nb + 1;
+    ev->n_nodes_pad = (int32_t)((ev->n_nodes + kNodeTile - 1) / kNodeTile * kNodeTile);
+    ev->waveform = desc->waveform;
+    ev->flags = desc->flags;
+    ev->n_freq = n;
+    ev->f_low = desc->f_low;
+    ev->delta_f = desc->delta_f;
+    ev->gmst = desc->gmst;
+    ev->net.n_det = nd;
+    ev->net.gmst = desc->gmst;
+    for (int d = 0; d < nd; ++d) {
+        for (int i = 0; i < 9; ++i) ev->net.D[d][i] = desc->det_tensor[9 * d + i];
+        for (int i = 0; i < 3; ++i) ev->net.r[d][i] = desc->det_vertex[3 * d + i];
+    }
+    DevList tmp;  // temporaries of the build
+    auto cleanup = [&](int code) {
+        tmp.release();
+        ev->mem.release();
+        delete ev;
+        return code;
+    };
+    hipError_t e;
+    // Inputs on the device.
+    double *d_data = nullptr, *d_psd = nullptr;
+    DevList& grid_owner = (desc->flags & RBL_KEEP_GRID) ? ev->mem : tmp;
+    if ((e = grid_owner.alloc((void**)&d_data, sizeof(double) * 2 * nd * n)) != hipSuccess)
+        return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (data)"));
+    if ((e = grid_owner.alloc((void**)&d_psd, sizeof(double) * nd * n)) != hipSuccess)
+        return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (psd)"));
+    const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if ((e = hipMemcpyAsync(d_data, desc->data, sizeof(double) * 2 * nd * n, kind, s)) != hipSuccess)
+        return cleanup(hip_fail(e, "rbl_event_create: copy data"));
+    if ((e = hipMemcpyAsync(d_psd, desc->psd, sizeof(double) * nd * n, kind, s)) != hipSuccess)
+        return cleanup(hip_fail(e, "rbl_event_create: copy psd"));
+    if (desc->flags & RBL_KEEP_GRID) {
+        ev->d_data = d_data;
+        ev->d_psd = d_psd;
+    }
+
+    // Reference constants.
+    RefConsts* d_ref = nullptr;
+    if ((e = tmp.alloc((void**)&d_ref, sizeof(RefConsts))) != hipSuccess)
+        return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (ref)"));
+    if ((e = launch_ref_setup(desc->theta_ref, ev->net, d_ref, s)) != hipSuccess)
+        return cleanup(hip_fail(e, "rbl_event_create: reference setup"));
+    if ((e = hipMemcpyAsync(&ev->ref, d_ref, sizeof(RefConsts), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return cleanup(hip_fail(e, "rbl_event_create: copy reference"));
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup(hip_fail(e, "rbl_event_create: reference setup"));
+    if (ev->ref.status != 1) return cleanup(fail(RBL_EINVAL, "rbl_event_create: theta_ref outside the physical domain"));
+    for (int d = 0; d < nd; ++d) {
+        const double a = ev->ref.invC0_re[d], b = ev->ref.invC0_im[d];
+        if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(ev->ref.h0fac_re[d]) || !std::isfinite(ev->ref.h0fac_im[d]) ||
+            (ev->ref.h0fac_re[d] == 0.0 && ev->ref.h0fac_im[d] == 0.0))
+            return cleanup(fail(RBL_EREF, "rbl_event_create: reference strain vanishes in detector " + std::to_string(d)));
+    }
+
+    // Work items of the summary pass: runs of <= kChunk points inside one bin.
+    std::vector<int32_t> item_bin;
+    std::vector<int64_t> item_start;
+    std::vector<int32_t> item_count;
+    std::vector<int64_t> bin_first((size_t)nb + 1);
+    for (int32_t b = 0; b < nb; ++b) {
+        bin_first[(size_t)b] = (int64_t)item_bin.size();
+        const int64_t lo = desc->edges[b];
+        const int64_t hi = (b == nb - 1) ? n : desc->edges[b + 1];
+        for (int64_t k = lo; k < hi; k += kChunk) {
+            item_bin.push_back(b);
+            item_start.push_back(k);
+            item_count.push_back((int32_t)std::min(kChunk, hi - k));
+        }
+    }
+    bin_first[(size_t)nb] = (int64_t)item_bin.size();
+    const int64_t n_items = (int64_t)item_bin.size();
+    int32_t* d_item_bin = nullptr;
+    int64_t *d_item_start = nullptr, *d_bin_first = nullptr, *d_edges = nullptr;
+    int32_t* d_item_count = nullptr;
+    double* d_partials = nullptr;
+    if (tmp.alloc((void**)&d_item_bin, sizeof(int32_t) * n_items) != hipSuccess ||
+        tmp.alloc((void**)&d_item_start, sizeof(int64_t) * n_items) != hipSuccess ||
+        tmp.alloc((void**)&d_item_count, sizeof(int32_t) * n_items) != hipSuccess ||
+        tmp.alloc((void**)&d_bin_first, sizeof(int64_t) * (nb + 1)) != hipSuccess ||
+        tmp.alloc((void**)&d_edges, sizeof(int64_t) * (nb + 1)) != hipSuccess ||
+        tmp.alloc((void**)&d_partials, sizeof(double) * n_items * nd * 7) != hipSuccess)
+        return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (work items)"));
+    if ((e = hipMemcpyAsync(d_item_bin, item_bin.data(), sizeof(int32_t) * n_items, hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(d_item_start, item_start.data(), sizeof(int64_t) * n_items, hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(d_item_count, item_count.data(), sizeof(int32_t) * n_items, hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(d_bin_first, bin_first.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(d_edges, desc->edges, sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, s)))
+        return cleanup(hip_fail(e, "rbl_event_create: copy work items"));
+
+    // Resident tables.
+    const int64_t np = ev->n_nodes_pad;
+    if (ev->mem.alloc((void**)&ev->d_summary, sizeof(double) * nd * nb * 7) != hipSuccess)
+        return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (summary)"));
+    double* node_block = nullptr;
+    const int64_t node_doubles = np * (4 + 5 * nd);
+    if (ev->mem.alloc((void**)&node_block, sizeof(double) * node_doubles) != hipSuccess)
+        return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (node tables)"));
+
+    SummaryArgs sa{};
+    sa.n_items = n_items;
+    sa.item_bin = d_item_bin;
+    sa.item_start = d_item_start;
+    sa.item_count = d_item_count;
+    sa.edges = d_edges;
+    sa.f_low = ev->f_low;
+    sa.delta_f = ev->delta_f;
+    sa.n_freq = n;
+    sa.n_det = nd;
+    sa.n_bins = nb;
+    sa.data = d_data;
+    sa.psd = d_psd;
+    sa.partials = d_partials;
+    sa.ref = ev->ref;
+    if ((e = launch_summary(sa, d_bin_first, ev->d_summary, s)) != hipSuccess)
+        return cleanup(hip_fail(e, "rbl_event_create: summary pass"));
+
+    NodeArgs na{};
+    na.n_nodes = ev->n_nodes;
+    na.n_nodes_pad = (int32_t)np;
+    na.n_det = nd;
+    na.keep_b2 = (desc->flags & RBL_KEEP_B2) ? 1 : 0;
+    na.edges = d_edges;
+    na.f_low = ev->f_low;
+    na.delta_f = ev->delta_f;
+    na.summary = ev->d_summary;
+    na.node_f = node_block;
+    na.node_x = node_block + np;
+    na.node_ix = node_block + 2 * np;
+    na.node_lx = node_block + 3 * np;
+    na.g_re = node_block + 4 * np;
+    na.g_im = na.g_re + nd * np;
+    na.mu = na.g_im + nd * np;
+    na.nuL = na.mu + nd * np;
+    na.nuR = na.nuL + nd * np;
+    if ((e = launch_node_tables(na, s)) != hipSuccess) return cleanup(hip_fail(e, "rbl_event_create: node tables"));
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup(hip_fail(e, "rbl_event_create: build"));
+    tmp.release();
+
+    EventDev& dv = ev->dev;
+    dv.n_det = nd;
+    dv.n_bins = nb;
+    dv.n_nodes = ev->n_nodes;
+    dv.n_nodes_pad = (int32_t)np;
+    dv.n_freq = n;
+    dv.f_low = ev->f_low;
+    dv.delta_f = ev->delta_f;
+    dv.node_f = na.node_f;
+    dv.node_x = na.node_x;
+    dv.node_ix = na.node_ix;
+    dv.node_lx = na.node_lx;
+    dv.g_re = na.g_re;
+    dv.g_im = na.g_im;
+    dv.mu = na.mu;
+    dv.nuL = na.nuL;
+    dv.nuR = na.nuR;
+    ev->footprint = (int64_t)sizeof(double) * (nd * nb * 7 + node_doubles) +
+                    ((desc->flags & RBL_KEEP_GRID) ? (int64_t)sizeof(double) * 3 * nd * n : 0);
+    *out = ev;
+    return RBL_OK;
+}
+
+extern "C" void rbl_event_free(rbl_event* ev) {
+    if (!ev) return;
+    ev->mem.release();
+    delete ev;
+}
+
+extern "C" int64_t rbl_workspace_bytes(const rbl_event* ev, int64_t B, int32_t with_grad) {
+    if (!ev || B < 0) return 0;
+    int64_t bytes = align_up(B * kRecStride * (int64_t)sizeof(double));
+    if (with_grad) bytes += align_up(B * kJacRows * 13 * (int64_t)sizeof(double));
+    return bytes;
+}
+
+static int check_call(const char* who, const rbl_event* ev, const double* theta, int64_t B, int32_t precision,
+                      const void* lnl, const void* ws) {
+    if (!ev) return fail(RBL_EINVAL, std::string(who) + ": null event");
+    if (B < 0) return fail(RBL_EINVAL, std::string(who) + ": B < 0");
+    if (B == 0) return RBL_OK;
+    if (!theta || !lnl) return fail(RBL_EINVAL, std::string(who) + ": null theta or output");
+    if (!ws) return fail(RBL_EINVAL, std::string(who) + ": null workspace");
+    if (((uintptr_t)ws) % kAlign) return fail(RBL_EINVAL, std::string(who) + ": workspace not 256-byte aligned");
+    if (precision != RBL_FP64 && precision != RBL_MIXED) return fail(RBL_EINVAL, std::string(who) + ": unknown precision");
+    if (precision == RBL_MIXED) return fail(RBL_EUNSUPPORTED, std::string(who) + ": mixed precision not available in this build");
+    if (B > (int64_t)1 << 31) return fail(RBL_EINVAL, std::string(who) + ": B too large");
+    return RBL_OK;
+}
+
+extern "C" int rbl_loglike(const rbl_event* ev, const double* theta_dev, int64_t B, int32_t precision,
+                           double* lnl_dev, void* workspace, void* hip_stream) {
+    int rc = check_call("rbl_loglike", ev, theta_dev, B, precision, lnl_dev, workspace);
+    if (rc || B == 0) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    double* rec = (double*)workspace;
+    hipError_t e = launch_chain_setup(theta_dev, B, ev->net, ev->ref, rec, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "rbl_loglike: setup launch");
+    e = launch_loglike(ev->dev, rec, B, lnl_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "rbl_loglike: launch");
+    return RBL_OK;
+}
+
+extern "C" int rbl_loglike_grad(const rbl_event* ev, const double* theta_dev, int64_t B, int32_t precision,
+                                double* lnl_dev, double* grad_dev, void* workspace, void* hip_stream) {
+    int rc = check_call("rbl_loglike_grad", ev, theta_dev, B, precision, lnl_dev, workspace);
+    if (rc || B == 0) return rc;
+    if (!grad_dev) return fail(RBL_EINVAL, "rbl_loglike_grad: null grad");
+    hipStream_t s = (hipStream_t)hip_stream;
+    double* rec = (double*)workspace;
+    double* jac = (double*)((char*)workspace + align_up(B * kRecStride * (int64_t)sizeof(double)));
+    hipError_t e = launch_chain_setup(theta_dev, B, ev->net, ev->ref, rec, jac, s);
+    if (e != hipSuccess) return hip_fail(e, "rbl_loglike_grad: setup launch");
+    e = launch_loglike_grad(ev->dev, rec, jac, B, lnl_dev, grad_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "rbl_loglike_grad: launch");
+    return RBL_OK;
+}
+
+extern "C" int rbl_loglike_full(const rbl_event* ev, const double* theta_dev, int64_t B, double* lnl_dev,
+                                void* workspace, void* hip_stream) {
+    int rc = check_call("rbl_loglike_full", ev, theta_dev, B, RBL_FP64, lnl_dev, workspace);
+    if (rc || B == 0) return rc;
+    if (!(ev->flags & RBL_KEEP_GRID) || !ev->d_data)
+        return fail(RBL_EUNSUPPORTED, "rbl_loglike_full: event built without RBL_KEEP_GRID");
+    hipStream_t s = (hipStream_t)hip_stream;
+    double* rec = (double*)workspace;
+    hipError_t e = launch_chain_setup(theta_dev, B, ev->net, ev->ref, rec, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "rbl_loglike_full: setup launch");
+    FullArgs a{};
+    a.recs = rec;
+    a.ref = ev->ref;
+    a.n_det = ev->n_det;
+    a.n_freq = ev->n_freq;
+    a.f_low = ev->f_low;
+    a.delta_f = ev->delta_f;
+    a.data = ev->d_data;
+    a.psd = ev->d_psd;
+    a.lnl = lnl_dev;
+    e = launch_loglike_full(a, B, s);
+    if (e != hipSuccess) return hip_fail(e, "rbl_loglike_full: launch");
+    return RBL_OK;
+}
+
+extern "C" int rbl_strain(int32_t waveform, int32_t n_det, const double* det_tensor, const double* det_vertex,
+                          double gmst, double f_low, double delta_f, int64_t n_freq, const double* theta,
+                          int32_t taper, double* out_dev, void* hip_stream) {
+    (void)taper;
+    if (waveform != RBL_TAYLORF2 && waveform != RBL_PHENOMD_NRTV2) return fail(RBL_EINVAL, "rbl_strain: unknown waveform");
+    if (waveform == RBL_PHENOMD_NRTV2) return fail(RBL_EUNSUPPORTED, "rbl_strain: IMRPhenomD_NRTidalv2 not available in this build");
+    if (n_det < 1 || n_det > kMaxDet) return fail(RBL_EINVAL, "rbl_strain: n_det must be 1..3");
+    if (!det_tensor || !det_vertex || !theta || !out_dev) return fail(RBL_EINVAL, "rbl_strain: null pointer");
+    if (!(f_low > 0.0) || !(delta_f > 0.0) || n_freq < 1) return fail(RBL_EINVAL, "rbl_strain: bad grid");
+    if (!theta_in_domain(theta)) return fail(RBL_EINVAL, "rbl_strain: theta outside the physical domain");
+    Network net{};
+    net.n_det = n_det;
+    net.gmst = gmst;
+    for (int d = 0; d < n_det; ++d) {
+        for (int i = 0; i < 9; ++i) net.D[d][i] = det_tensor[9 * d + i];
+        for (int i = 0; i < 3; ++i) net.r[d][i] = det_vertex[3 * d + i];
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    RefConsts* d_cst = nullptr;
+    hipError_t e = hipMalloc((void**)&d_cst, sizeof(RefConsts));
+    if (e != hipSuccess) return fail(RBL_ENOMEM, "rbl_strain: device allocation");
+    e = launch_ref_setup(theta, net, d_cst, s);
+    if (e == hipSuccess) e = launch_strain(d_cst, n_det, f_low, delta_f, n_freq, out_dev, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_cst);
+    if (e != hipSuccess) return hip_fail(e, "rbl_strain");
+    return RBL_OK;
+}
+
+extern "C" int rbl_event_get_summary(const rbl_event* ev, double* host_out) {
+    if (!ev || !host_out) return fail(RBL_EINVAL, "rbl_event_get_summary: null pointer");
+    hipError_t e = hipMemcpy(host_out, ev->d_summary, sizeof(double) * ev->n_det * ev->n_bins * 7, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "rbl_event_get_summary");
+    return RBL_OK;
+}
+
+extern "C" int rbl_event_info(const rbl_event* ev, int32_t* n_det, int32_t* n_bins, int32_t* waveform,
+                              int64_t* footprint_bytes) {
+    if (!ev) return fail(RBL_EINVAL, "rbl_event_info: null event");
+    if (n_det) *n_det = ev->n_det;
+    if (n_bins) *n_bins = ev->n_bins;
+    if (waveform) *waveform = ev->waveform;
+    if (footprint_bytes) *footprint_bytes = ev->footprint;
+    return RBL_OK;
+}

@@ -1,0 +1,58 @@
+// Kernel argument blocks and launch wrappers (internal to the library).
+#pragma once
+#include "rbl_internal.h"
+
+namespace rbl {
+
+struct Theta13 {
+    double v[13];
+};
+
+struct SummaryArgs {
+    int64_t n_items;
+    const int32_t* item_bin;
+    const int64_t* item_start;
+    const int32_t* item_count;
+    const int64_t* edges;
+    double f_low, delta_f;
+    int64_t n_freq;
+    int32_t n_det, n_bins;
+    const double* data;  // [n_det][n_freq][2]
+    const double* psd;   // [n_det][n_freq]
+    double* partials;    // [n_items][n_det][7]
+    RefConsts ref;
+};
+
+struct NodeArgs {
+    int32_t n_nodes, n_nodes_pad, n_det, keep_b2;
+    const int64_t* edges;
+    double f_low, delta_f;
+    const double* summary;  // [n_det][n_bins][7]
+    double *node_f, *node_x, *node_ix, *node_lx;
+    double *g_re, *g_im, *mu, *nuL, *nuR;
+};
+
+struct FullArgs {
+    const double* recs;
+    RefConsts ref;
+    int32_t n_det;
+    int64_t n_freq;
+    double f_low, delta_f;
+    const double* data;
+    const double* psd;
+    double* lnl;
+};
+
+hipError_t launch_ref_setup(const double* theta_host, const Network& net, RefConsts* out_dev, hipStream_t s);
+hipError_t launch_chain_setup(const double* theta, int64_t B, const Network& net, const RefConsts& ref,
+                              double* rec, double* jac, hipStream_t s);
+hipError_t launch_summary(const SummaryArgs& a, const int64_t* bin_first_item, double* summary, hipStream_t s);
+hipError_t launch_node_tables(const NodeArgs& a, hipStream_t s);
+hipError_t launch_loglike(const EventDev& ev, const double* rec, int64_t B, double* lnl, hipStream_t s);
+hipError_t launch_loglike_grad(const EventDev& ev, const double* rec, const double* jac, int64_t B, double* lnl,
+                               double* grad, hipStream_t s);
+hipError_t launch_loglike_full(const FullArgs& a, int64_t B, hipStream_t s);
+hipError_t launch_strain(const RefConsts* cst_dev, int32_t n_det, double f_low, double delta_f, int64_t n_freq,
+                         double* out, hipStream_t s);
+
+}  // namespace rbl

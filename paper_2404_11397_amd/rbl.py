@@ -1,0 +1,183 @@
+"""Python binding of the relative-binned likelihood library.
+
+Device memory and streams come from PyTorch (ROCm); every computation runs in
+the library's HIP kernels.  Usage:
+
+    ev = Event(data, psd, det_tensor, det_vertex, gmst, f_low, delta_f,
+               theta_ref, edges, waveform="taylorf2")
+    lnl = ev.loglike(theta)                  # theta: cuda float64 [B, 13]
+    lnl, grad = ev.loglike_grad(theta)
+    lnl = LogLikeFn.apply(theta, ev)         # autograd-aware
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+WAVEFORMS = {"taylorf2": _lib.RBL_TAYLORF2, "phenomd_nrtv2": _lib.RBL_PHENOMD_NRTV2}
+PRECISIONS = {"fp64": _lib.RBL_FP64, "mixed": _lib.RBL_MIXED}
+
+
+def _stream_handle(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host_f64(x, shape=None):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def bin_edges(f_low, delta_f, n_freq, n_bins):
+    """Bin edges from the library's post-Newtonian phase-bound ansatz (host)."""
+    out = np.empty(n_bins + 1, dtype=np.int64)
+    check(_lib.lib().rbl_bin_edges(float(f_low), float(delta_f), int(n_freq), int(n_bins),
+                                   out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def strain(waveform, det_tensor, det_vertex, gmst, f_low, delta_f, n_freq, theta, taper=True,
+           device="cuda"):
+    """Projected strain [n_det, n_freq] complex128 on the device for one theta."""
+    tens = _host_f64(det_tensor).reshape(-1, 9)
+    vert = _host_f64(det_vertex).reshape(-1, 3)
+    nd = tens.shape[0]
+    th = _host_f64(theta).reshape(13)
+    out = torch.empty((nd, n_freq, 2), dtype=torch.float64, device=device)
+    check(_lib.lib().rbl_strain(WAVEFORMS[waveform], nd, tens.ctypes.data_as(ctypes.c_void_p),
+                                vert.ctypes.data_as(ctypes.c_void_p), float(gmst), float(f_low),
+                                float(delta_f), int(n_freq), th.ctypes.data_as(ctypes.c_void_p),
+                                int(bool(taper)), _ptr(out), _stream_handle(out.device)))
+    return torch.view_as_complex(out)
+
+
+class Event:
+    """A resident event: summary data and edge tables on the device."""
+
+    def __init__(self, data, psd, det_tensor, det_vertex, gmst, f_low, delta_f, theta_ref, edges,
+                 waveform="taylorf2", keep_b2=False, ref_taper=False, keep_grid=False,
+                 device="cuda"):
+        self.device = torch.device(device)
+        tens = _host_f64(det_tensor).reshape(-1, 9)
+        vert = _host_f64(det_vertex).reshape(-1, 3)
+        nd = tens.shape[0]
+        flags = (_lib.RBL_KEEP_B2 if keep_b2 else 0) | (_lib.RBL_REF_TAPER if ref_taper else 0) \
+            | (_lib.RBL_KEEP_GRID if keep_grid else 0)
+        if isinstance(data, torch.Tensor):
+            d = torch.view_as_real(data.to(self.device, torch.complex128).contiguous()).contiguous()
+            p = psd.to(self.device, torch.float64).contiguous()
+            flags |= _lib.RBL_INPUT_ON_DEVICE
+            n_freq = d.shape[-2]
+            dptr, pptr = _ptr(d), _ptr(p)
+            self._keep = (d, p)
+        else:
+            d = np.ascontiguousarray(np.asarray(data, dtype=np.complex128).reshape(nd, -1))
+            p = _host_f64(psd).reshape(nd, -1)
+            n_freq = d.shape[-1]
+            dptr = d.ctypes.data_as(ctypes.c_void_p)
+            pptr = p.ctypes.data_as(ctypes.c_void_p)
+            self._keep = (d, p)
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64))
+        th = _host_f64(theta_ref).reshape(13)
+        desc = _lib.EventDesc(n_det=nd, waveform=WAVEFORMS[waveform], n_bins=len(e) - 1, flags=flags,
+                              n_freq=n_freq, f_low=float(f_low), delta_f=float(delta_f),
+                              gmst=float(gmst), data=dptr, psd=pptr,
+                              det_tensor=tens.ctypes.data_as(ctypes.c_void_p),
+                              det_vertex=vert.ctypes.data_as(ctypes.c_void_p),
+                              theta_ref=th.ctypes.data_as(ctypes.c_void_p),
+                              edges=e.ctypes.data_as(ctypes.c_void_p))
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(_lib.lib().rbl_event_create(ctypes.byref(desc), _stream_handle(self.device),
+                                              ctypes.byref(handle)))
+        self._h = handle
+        self._keep = None
+        self.n_det, self.n_bins, self.n_freq = nd, len(e) - 1, n_freq
+        self.waveform = waveform
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _lib.lib().rbl_event_free(h)
+            except Exception:
+                pass
+            self._h = None
+
+    # -- queries ----------------------------------------------------------------
+    def summary(self):
+        """Summary data [n_det, n_bins, 7] = (ReA0, ImA0, ReA1, ImA1, B0, B1, B2)."""
+        out = np.empty((self.n_det, self.n_bins, 7), dtype=np.float64)
+        check(_lib.lib().rbl_event_get_summary(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def footprint_bytes(self):
+        fb = ctypes.c_int64()
+        check(_lib.lib().rbl_event_info(self._h, None, None, None, ctypes.byref(fb)))
+        return fb.value
+
+    def workspace(self, B, with_grad=False):
+        n = _lib.lib().rbl_workspace_bytes(self._h, int(B), int(bool(with_grad)))
+        return torch.empty(max(n, 256), dtype=torch.uint8, device=self.device)
+
+    # -- evaluation -----------------------------------------------------------------
+    def _theta(self, theta):
+        if not (isinstance(theta, torch.Tensor) and theta.is_cuda and theta.dtype == torch.float64):
+            raise TypeError("theta must be a cuda float64 tensor [B, 13]")
+        if theta.dim() != 2 or theta.shape[1] != 13:
+            raise ValueError("theta must have shape [B, 13]")
+        return theta.contiguous()
+
+    def loglike(self, theta, precision="fp64", out=None, workspace=None):
+        theta = self._theta(theta)
+        B = theta.shape[0]
+        lnl = torch.empty(B, dtype=torch.float64, device=theta.device) if out is None else out
+        ws = self.workspace(B) if workspace is None else workspace
+        check(_lib.lib().rbl_loglike(self._h, _ptr(theta), B, PRECISIONS[precision], _ptr(lnl),
+                                     _ptr(ws), _stream_handle(theta.device)))
+        return lnl
+
+    def loglike_grad(self, theta, precision="fp64", out=None, workspace=None):
+        theta = self._theta(theta)
+        B = theta.shape[0]
+        if out is None:
+            lnl = torch.empty(B, dtype=torch.float64, device=theta.device)
+            grad = torch.empty((B, 13), dtype=torch.float64, device=theta.device)
+        else:
+            lnl, grad = out
+        ws = self.workspace(B, True) if workspace is None else workspace
+        check(_lib.lib().rbl_loglike_grad(self._h, _ptr(theta), B, PRECISIONS[precision], _ptr(lnl),
+                                          _ptr(grad), _ptr(ws), _stream_handle(theta.device)))
+        return lnl, grad
+
+    def loglike_full(self, theta, out=None, workspace=None):
+        theta = self._theta(theta)
+        B = theta.shape[0]
+        lnl = torch.empty(B, dtype=torch.float64, device=theta.device) if out is None else out
+        ws = self.workspace(B) if workspace is None else workspace
+        check(_lib.lib().rbl_loglike_full(self._h, _ptr(theta), B, _ptr(lnl), _ptr(ws),
+                                          _stream_handle(theta.device)))
+        return lnl
+
+
+class LogLikeFn(torch.autograd.Function):
+    """lnL(theta) with the library's adjoint gradient as its backward."""
+
+    @staticmethod
+    def forward(ctx, theta, event, precision="fp64"):
+        lnl, grad = event.loglike_grad(theta, precision)
+        ctx.save_for_backward(grad)
+        return lnl
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return g[:, None] * grad, None, None

@@ -1,0 +1,97 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every declared symbol, validates arguments before touching the device, and its
+bin placement agrees with the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import binning
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2404_11397_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("librbl.so is not built (run __graft_entry__.build())")
+    return L
+
+
+def test_exports_every_declared_symbol():
+    L = _lib()
+    header = open(os.path.join(ROOT, "include", "rbl.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|void|int64_t|const char \*)\s*\*?\s*(rbl_\w+)\s*\(", header, re.M))
+    assert declared, "no declarations found"
+    lib = L.lib()
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared == set(L.EXPORTS)
+
+
+@pytest.mark.parametrize("cfg,nb", [("cfg1", 100), ("cfg2", 500), ("cfg3", 1000)])
+def test_bin_edges_match_oracle(cfg, nb):
+    from paper_2404_11397_amd import bin_edges
+    c = synth.CONFIGS[cfg]
+    f_low, df, n, _ = synth.frequency_grid(c["f_low"], c["f_high"], c["duration"])
+    np.testing.assert_array_equal(bin_edges(f_low, df, n, nb), binning.pn_bin_edges(f_low, df, n, nb))
+
+
+def test_bin_edges_tiny_grid_one_bin_per_point():
+    from paper_2404_11397_amd import bin_edges
+    np.testing.assert_array_equal(bin_edges(20.0, 1.0, 11, 10), np.arange(11))
+
+
+def _desc(L, **over):
+    nd = over.pop("n_det", 1)
+    n = 64
+    data = np.zeros((nd, n), complex)
+    psd = np.ones((nd, n))
+    tens = np.zeros((nd, 9))
+    vert = np.zeros((nd, 3))
+    th = np.array([1.2, 0.8, 0, 0, 0, 0, 40, 0, 0, 0.3, 0, 0, 0], float)
+    edges = np.array([0, 10, 30, 63], np.int64)
+    psd = over.get("psd", psd)
+    edges = over.get("edges", edges)
+    th = over.get("theta", th)
+    keep = (data, psd, tens, vert, th, edges)
+    d = L.EventDesc(n_det=nd, waveform=over.get("waveform", 0), n_bins=len(edges) - 1, flags=0, n_freq=n,
+                    f_low=20.0, delta_f=1.0, gmst=0.0,
+                    data=data.ctypes.data_as(ctypes.c_void_p), psd=psd.ctypes.data_as(ctypes.c_void_p),
+                    det_tensor=tens.ctypes.data_as(ctypes.c_void_p),
+                    det_vertex=vert.ctypes.data_as(ctypes.c_void_p),
+                    theta_ref=th.ctypes.data_as(ctypes.c_void_p), edges=edges.ctypes.data_as(ctypes.c_void_p))
+    return d, keep
+
+
+@pytest.mark.parametrize("case,code", [
+    ({"n_det": 4}, -1),
+    ({"edges": np.array([0, 10, 10, 63], np.int64)}, -2),
+    ({"edges": np.array([1, 10, 30, 63], np.int64)}, -2),
+    ({"edges": np.array([0, 10, 30, 62], np.int64)}, -2),
+    ({"psd": np.concatenate([np.ones(63), [0.0]])[None, :]}, -3),
+    ({"psd": np.concatenate([np.ones(63), [np.nan]])[None, :]}, -3),
+    ({"theta": np.array([1.2, 0.8, 0, 0, 0, 0, -40, 0, 0, 0.3, 0, 0, 0], float)}, -1),
+    ({"waveform": 7}, -1),
+])
+def test_event_create_rejects_bad_input_before_device_work(case, code):
+    L = _lib()
+    d, keep = _desc(L, **case)
+    h = ctypes.c_void_p()
+    rc = L.lib().rbl_event_create(ctypes.byref(d), None, ctypes.byref(h))
+    assert rc == code, L.lib().rbl_last_error()
+    assert not h.value
+    assert L.lib().rbl_last_error()
+
+
+def test_null_arguments():
+    L = _lib()
+    lib = L.lib()
+    assert lib.rbl_event_create(None, None, None) == -1
+    assert lib.rbl_loglike(None, None, 1, 0, None, None, None) == -1
+    assert lib.rbl_loglike_grad(None, None, 1, 0, None, None, None, None) == -1
+    assert lib.rbl_bin_edges(20.0, 1.0, 10, 20, None) == -1
+    assert lib.rbl_workspace_bytes(None, 10, 0) == 0

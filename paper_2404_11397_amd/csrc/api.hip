@@ -1,5 +1,6 @@
 // Host side of the C-ABI: validation, resident event state, kernel launches.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -51,7 +52,69 @@ struct DevList {
     }
 };
 
+// Benchmark timing: events around the setup and main kernel of each call.
+struct ProfState {
+    bool on = false;
+    std::vector<hipEvent_t> free_events;
+    std::vector<std::array<hipEvent_t, 3>> pending;  // start, after setup, after main
+    hipEvent_t get() {
+        if (!free_events.empty()) {
+            hipEvent_t e = free_events.back();
+            free_events.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+ProfState g_prof;
+
+struct CallTimer {
+    std::array<hipEvent_t, 3> ev{{nullptr, nullptr, nullptr}};
+    hipStream_t s;
+    explicit CallTimer(hipStream_t st) : s(st) {
+        if (!g_prof.on) return;
+        for (auto& e : ev) e = g_prof.get();
+        if (ev[0]) (void)hipEventRecord(ev[0], s);
+    }
+    void mark_setup() {
+        if (g_prof.on && ev[1]) (void)hipEventRecord(ev[1], s);
+    }
+    void done() {
+        if (!g_prof.on || !ev[0] || !ev[1] || !ev[2]) return;
+        (void)hipEventRecord(ev[2], s);
+        g_prof.pending.push_back(ev);
+    }
+};
+
 }  // namespace
+
+extern "C" int rbl_profile_enable(int32_t on) {
+    g_prof.on = on != 0;
+    return RBL_OK;
+}
+
+extern "C" int rbl_profile_read(double* main_ms, double* setup_ms, int64_t* calls) {
+    double m = 0.0, st = 0.0;
+    int64_t n = 0;
+    for (auto& t : g_prof.pending) {
+        hipError_t e = hipEventSynchronize(t[2]);
+        if (e != hipSuccess) return hip_fail(e, "rbl_profile_read");
+        float a = 0.f, b = 0.f;
+        (void)hipEventElapsedTime(&a, t[0], t[1]);
+        (void)hipEventElapsedTime(&b, t[1], t[2]);
+        st += a;
+        m += b;
+        ++n;
+        for (auto e2 : t) g_prof.free_events.push_back(e2);
+    }
+    g_prof.pending.clear();
+    if (main_ms) *main_ms = m;
+    if (setup_ms) *setup_ms = st;
+    if (calls) *calls = n;
+    return RBL_OK;
+}
 
 struct rbl_event {
     int32_t n_det = 0, n_bins = 0, n_nodes = 0, n_nodes_pad = 0, waveform = 0;
@@ -353,10 +416,13 @@ extern "C" int rbl_loglike(const rbl_event* ev, const double* theta_dev, int64_t
     if (rc || B == 0) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     double* rec = (double*)workspace;
+    CallTimer tm(s);
     hipError_t e = launch_chain_setup(theta_dev, B, ev->net, ev->ref, rec, nullptr, s);
     if (e != hipSuccess) return hip_fail(e, "rbl_loglike: setup launch");
+    tm.mark_setup();
     e = launch_loglike(ev->dev, rec, B, lnl_dev, s);
     if (e != hipSuccess) return hip_fail(e, "rbl_loglike: launch");
+    tm.done();
     return RBL_OK;
 }
 
@@ -368,10 +434,13 @@ extern "C" int rbl_loglike_grad(const rbl_event* ev, const double* theta_dev, in
     hipStream_t s = (hipStream_t)hip_stream;
     double* rec = (double*)workspace;
     double* jac = (double*)((char*)workspace + align_up(B * kRecStride * (int64_t)sizeof(double)));
+    CallTimer tm(s);
     hipError_t e = launch_chain_setup(theta_dev, B, ev->net, ev->ref, rec, jac, s);
     if (e != hipSuccess) return hip_fail(e, "rbl_loglike_grad: setup launch");
+    tm.mark_setup();
     e = launch_loglike_grad(ev->dev, rec, jac, B, lnl_dev, grad_dev, s);
     if (e != hipSuccess) return hip_fail(e, "rbl_loglike_grad: launch");
+    tm.done();
     return RBL_OK;
 }
 
@@ -383,8 +452,10 @@ extern "C" int rbl_loglike_full(const rbl_event* ev, const double* theta_dev, in
         return fail(RBL_EUNSUPPORTED, "rbl_loglike_full: event built without RBL_KEEP_GRID");
     hipStream_t s = (hipStream_t)hip_stream;
     double* rec = (double*)workspace;
+    CallTimer tm(s);
     hipError_t e = launch_chain_setup(theta_dev, B, ev->net, ev->ref, rec, nullptr, s);
     if (e != hipSuccess) return hip_fail(e, "rbl_loglike_full: setup launch");
+    tm.mark_setup();
     FullArgs a{};
     a.recs = rec;
     a.ref = ev->ref;
@@ -397,6 +468,7 @@ extern "C" int rbl_loglike_full(const rbl_event* ev, const double* theta_dev, in
     a.lnl = lnl_dev;
     e = launch_loglike_full(a, B, s);
     if (e != hipSuccess) return hip_fail(e, "rbl_loglike_full: launch");
+    tm.done();
     return RBL_OK;
 }
 

@@ -36,6 +36,18 @@ def _host_f64(x, shape=None):
     return a
 
 
+def profile_enable(on=True):
+    """Record HIP events around the library's kernels (benchmark timing)."""
+    check(_lib.lib().rbl_profile_enable(int(bool(on))))
+
+
+def profile_read():
+    """(main-kernel ms, setup-kernel ms, calls) summed since the last read."""
+    m, s, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    check(_lib.lib().rbl_profile_read(ctypes.byref(m), ctypes.byref(s), ctypes.byref(n)))
+    return m.value, s.value, n.value
+
+
 def bin_edges(f_low, delta_f, n_freq, n_bins):
     """Bin edges from the library's post-Newtonian phase-bound ansatz (host)."""
     out = np.empty(n_bins + 1, dtype=np.int64)

@@ -94,6 +94,37 @@ def cpu_baseline(w, edges, data_host, theta, seconds):
                       f"(lnL + dual-number gradient), {dt:.1f} s, numpy FP64 single thread"}
 
 
+def time_calls(torch, fn, steps, warmup):
+    """Wall time per call and HIP-event kernel times (main, setup) per call."""
+    from paper_2404_11397_amd import profile_enable, profile_read
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    main_ms, setup_ms, calls = profile_read()
+    profile_enable(False)
+    return elapsed, main_ms / calls * 1e3, setup_ms / calls * 1e3
+
+
+def summary_pass(torch, w, edges, data, psd, repeats=3):
+    """Average duration of the summary-data kernels of rbl_event_create (HIP events)."""
+    from paper_2404_11397_amd import Event, profile_enable, profile_read_summary
+    profile_enable(True)
+    profile_read_summary()
+    for _ in range(repeats):
+        Event(data, psd, w["tensors"], w["vertices"], w["gmst"], w["f_low"], w["delta_f"], w["theta_inj"], edges,
+              waveform=w["waveform"], device=data.device)
+    ms, n = profile_read_summary()
+    profile_enable(False)
+    return ms / n * 1e3
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -102,7 +133,6 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
-    from paper_2404_11397_amd import profile_enable, profile_read
 
     workload = "cfg4_tf2"
     ev, w, edges, data = build_event(torch, workload)
@@ -116,19 +146,7 @@ def main():
     def step():
         ev.loglike_grad(theta, args.precision, out=(lnl, grad), workspace=ws)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    main_ms, setup_ms, calls = profile_read()
-    profile_enable(False)
+    elapsed, kern_us, setup_us = time_calls(torch, step, args.steps, args.warmup)
 
     # per-call latency of a synchronised batch call
     lat = []
@@ -139,12 +157,27 @@ def main():
         lat.append((time.perf_counter() - t1) * 1e3)
     lat = np.array(lat)
 
-    n_nodes = w["n_bins"] + 1
+    # the other forms on the same batch (context beside the headline)
+    forms = {}
+    k = max(20, args.steps // 4)
+    for name, prec, g in (("lnl_fp64", "fp64", False), ("lnl_mixed", "mixed", False),
+                          ("lnl_grad_fp64", "fp64", True), ("lnl_grad_mixed", "mixed", True)):
+        if g:
+            fn = lambda p=prec: ev.loglike_grad(theta, p, out=(lnl, grad), workspace=ws)  # noqa: E731
+        else:
+            fn = lambda p=prec: ev.loglike(theta, p, out=lnl, workspace=ws)  # noqa: E731
+        el, ku, su = time_calls(torch, fn, k, 3)
+        forms[name] = {"evals_per_s": B * k / el, "us_per_call": el / k * 1e6, "kernel_us": ku, "setup_us": su}
+
     nd = len(w["tensors"])
+    psd = torch.as_tensor(w["psd"], device="cuda:0")
+    summ_us = summary_pass(torch, w, edges, data, psd)
+    summ_bytes = w["n_freq"] * nd * 24  # data (complex128) + PSD (float64) per grid point and detector
+
+    n_nodes = w["n_bins"] + 1
     fl = flops_per_eval(n_nodes, nd, grad=True)
     fl_kernel = fl - 6000
-    avg_main_s = main_ms / calls / 1e3
-    achieved = fl_kernel * B / avg_main_s / 1e12
+    achieved = fl_kernel * B / (kern_us * 1e-6) / 1e12
     out = {
         "metric": "relative-binned lnL+grad evals/sec (13-param BNS, 3 det); p50/p99 latency",
         "value": B * args.steps / elapsed,
@@ -165,9 +198,12 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_loglike_grad<3>", "achieved": achieved,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": None, "flops_per_eval": fl_kernel,
-                     "avg_kernel_us": avg_main_s * 1e6, "avg_setup_us": setup_ms / calls * 1e3},
+                     "avg_kernel_us": kern_us, "avg_setup_us": setup_us},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "what": "one synchronised rbl_loglike_grad call over the 8192-chain batch"},
+        "forms": forms,
+        "summary_pass": {"us": summ_us, "bytes": summ_bytes, "GB_per_s": summ_bytes / (summ_us * 1e-6) / 1e9,
+                         "frac_of_hbm_peak": summ_bytes / (summ_us * 1e-6) / 1e9 / PEAK_HBM_GBS},
     }
     if not args.no_cpu_baseline:
         data_host = data.cpu().numpy()

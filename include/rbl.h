@@ -146,6 +146,9 @@ int rbl_bin_edges(double f_low, double delta_f, int64_t n_freq, int32_t n_bins, 
  * and resets the counters.  Not for concurrent use from several threads. */
 int rbl_profile_enable(int32_t on);
 int rbl_profile_read(double *main_ms, double *setup_ms, int64_t *calls);
+/* Summed milliseconds of the summary-data pass (reference waveform on the grid and the
+ * per-bin reductions) of the events created while profiling was enabled; resets. */
+int rbl_profile_read_summary(double *ms, int64_t *events);
 
 const char *rbl_last_error(void);
 

@@ -18,7 +18,7 @@ ERROR_NAMES = {-1: "RBL_EINVAL", -2: "RBL_EEDGES", -3: "RBL_EPSD", -4: "RBL_ENOM
 
 EXPORTS = ("rbl_event_create", "rbl_event_free", "rbl_workspace_bytes", "rbl_loglike",
            "rbl_loglike_grad", "rbl_loglike_full", "rbl_strain", "rbl_event_get_summary",
-           "rbl_event_info", "rbl_bin_edges", "rbl_profile_enable", "rbl_profile_read",
+           "rbl_event_info", "rbl_bin_edges", "rbl_profile_enable", "rbl_profile_read", "rbl_profile_read_summary",
            "rbl_last_error")
 
 
@@ -73,6 +73,8 @@ def lib():
     L.rbl_profile_enable.restype = ctypes.c_int
     L.rbl_profile_read.argtypes = [vp, vp, vp]
     L.rbl_profile_read.restype = ctypes.c_int
+    L.rbl_profile_read_summary.argtypes = [vp, vp]
+    L.rbl_profile_read_summary.restype = ctypes.c_int
     L.rbl_last_error.argtypes = []
     L.rbl_last_error.restype = ctypes.c_char_p
     _lib = L

@@ -57,6 +57,8 @@ struct ProfState {
     bool on = false;
     std::vector<hipEvent_t> free_events;
     std::vector<std::array<hipEvent_t, 3>> pending;  // start, after setup, after main
+    double summary_ms = 0.0;                          // summary-pass kernels of rbl_event_create
+    int64_t summary_n = 0;
     hipEvent_t get() {
         if (!free_events.empty()) {
             hipEvent_t e = free_events.back();
@@ -92,6 +94,14 @@ struct CallTimer {
 
 extern "C" int rbl_profile_enable(int32_t on) {
     g_prof.on = on != 0;
+    return RBL_OK;
+}
+
+extern "C" int rbl_profile_read_summary(double* ms, int64_t* events) {
+    if (ms) *ms = g_prof.summary_ms;
+    if (events) *events = g_prof.summary_n;
+    g_prof.summary_ms = 0.0;
+    g_prof.summary_n = 0;
     return RBL_OK;
 }
 
@@ -221,7 +231,7 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     ev->n_det = nd;
     ev->n_bins = nb;
     ev->n_nodes = nb + 1;
-    ev->n_nodes_pad = (int32_t)((ev->n_nodes + kNodeTile - 1) / kNodeTile * kNodeTile);
+    ev->n_nodes_pad = (int32_t)((ev->n_nodes + kNodeTile - 1) / kNodeTile * kNodeTile);  // 64 L
     ev->waveform = desc->waveform;
     ev->flags = desc->flags;
     ev->n_freq = n;
@@ -316,7 +326,7 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     if (ev->mem.alloc((void**)&ev->d_summary, sizeof(double) * nd * nb * 7) != hipSuccess)
         return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (summary)"));
     double* node_block = nullptr;
-    const int64_t node_doubles = np * (4 + 5 * nd);
+    const int64_t node_doubles = np * (4 + 5 * nd) + 2 * kMaxDet + np * 2 * nd;  // FP64 tables, scales, FP32 tables
     if (ev->mem.alloc((void**)&node_block, sizeof(double) * node_doubles) != hipSuccess)
         return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (node tables)"));
 
@@ -335,12 +345,31 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     sa.psd = d_psd;
     sa.partials = d_partials;
     sa.ref = ev->ref;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (g_prof.on) {
+        t0 = g_prof.get();
+        t1 = g_prof.get();
+        if (t0) (void)hipEventRecord(t0, s);
+    }
     if ((e = launch_summary(sa, d_bin_first, ev->d_summary, s)) != hipSuccess)
         return cleanup(hip_fail(e, "rbl_event_create: summary pass"));
+    if (t0 && t1) {
+        (void)hipEventRecord(t1, s);
+        if (hipEventSynchronize(t1) == hipSuccess) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, t0, t1) == hipSuccess) {
+                g_prof.summary_ms += ms;
+                g_prof.summary_n += 1;
+            }
+        }
+    }
+    if (t0) g_prof.free_events.push_back(t0);
+    if (t1) g_prof.free_events.push_back(t1);
 
     NodeArgs na{};
     na.n_nodes = ev->n_nodes;
     na.n_nodes_pad = (int32_t)np;
+    na.L = (int32_t)(np / kNodeTile);
     na.n_det = nd;
     na.keep_b2 = (desc->flags & RBL_KEEP_B2) ? 1 : 0;
     na.edges = d_edges;
@@ -356,6 +385,11 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     na.mu = na.g_im + nd * np;
     na.nuL = na.mu + nd * np;
     na.nuR = na.nuL + nd * np;
+    na.scales = na.nuR + nd * np;
+    na.g_re32 = (float*)(na.scales + 2 * kMaxDet);
+    na.g_im32 = na.g_re32 + nd * np;
+    na.mu32 = na.g_im32 + nd * np;
+    na.nuL32 = na.mu32 + nd * np;
     if ((e = launch_node_tables(na, s)) != hipSuccess) return cleanup(hip_fail(e, "rbl_event_create: node tables"));
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup(hip_fail(e, "rbl_event_create: build"));
     tmp.release();
@@ -365,6 +399,7 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     dv.n_bins = nb;
     dv.n_nodes = ev->n_nodes;
     dv.n_nodes_pad = (int32_t)np;
+    dv.L = (int32_t)(np / kNodeTile);
     dv.n_freq = n;
     dv.f_low = ev->f_low;
     dv.delta_f = ev->delta_f;
@@ -377,6 +412,11 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     dv.mu = na.mu;
     dv.nuL = na.nuL;
     dv.nuR = na.nuR;
+    dv.g_re32 = na.g_re32;
+    dv.g_im32 = na.g_im32;
+    dv.mu32 = na.mu32;
+    dv.nuL32 = na.nuL32;
+    dv.scales = na.scales;
     ev->footprint = (int64_t)sizeof(double) * (nd * nb * 7 + node_doubles) +
                     ((desc->flags & RBL_KEEP_GRID) ? (int64_t)sizeof(double) * 3 * nd * n : 0);
     *out = ev;
@@ -392,7 +432,7 @@ extern "C" void rbl_event_free(rbl_event* ev) {
 extern "C" int64_t rbl_workspace_bytes(const rbl_event* ev, int64_t B, int32_t with_grad) {
     if (!ev || B < 0) return 0;
     int64_t bytes = align_up(B * kRecStride * (int64_t)sizeof(double));
-    if (with_grad) bytes += align_up(B * kJacRows * 13 * (int64_t)sizeof(double));
+    if (with_grad) bytes += align_up(B * kJacStride * (int64_t)sizeof(double));
     return bytes;
 }
 
@@ -405,7 +445,6 @@ static int check_call(const char* who, const rbl_event* ev, const double* theta,
     if (!ws) return fail(RBL_EINVAL, std::string(who) + ": null workspace");
     if (((uintptr_t)ws) % kAlign) return fail(RBL_EINVAL, std::string(who) + ": workspace not 256-byte aligned");
     if (precision != RBL_FP64 && precision != RBL_MIXED) return fail(RBL_EINVAL, std::string(who) + ": unknown precision");
-    if (precision == RBL_MIXED) return fail(RBL_EUNSUPPORTED, std::string(who) + ": mixed precision not available in this build");
     if (B > (int64_t)1 << 31) return fail(RBL_EINVAL, std::string(who) + ": B too large");
     return RBL_OK;
 }
@@ -420,7 +459,7 @@ extern "C" int rbl_loglike(const rbl_event* ev, const double* theta_dev, int64_t
     hipError_t e = launch_chain_setup(theta_dev, B, ev->net, ev->ref, rec, nullptr, s);
     if (e != hipSuccess) return hip_fail(e, "rbl_loglike: setup launch");
     tm.mark_setup();
-    e = launch_loglike(ev->dev, rec, B, lnl_dev, s);
+    e = launch_loglike(ev->dev, rec, B, precision == RBL_MIXED, lnl_dev, s);
     if (e != hipSuccess) return hip_fail(e, "rbl_loglike: launch");
     tm.done();
     return RBL_OK;
@@ -438,7 +477,7 @@ extern "C" int rbl_loglike_grad(const rbl_event* ev, const double* theta_dev, in
     hipError_t e = launch_chain_setup(theta_dev, B, ev->net, ev->ref, rec, jac, s);
     if (e != hipSuccess) return hip_fail(e, "rbl_loglike_grad: setup launch");
     tm.mark_setup();
-    e = launch_loglike_grad(ev->dev, rec, jac, B, lnl_dev, grad_dev, s);
+    e = launch_loglike_grad(ev->dev, rec, jac, B, precision == RBL_MIXED, lnl_dev, grad_dev, s);
     if (e != hipSuccess) return hip_fail(e, "rbl_loglike_grad: launch");
     tm.done();
     return RBL_OK;

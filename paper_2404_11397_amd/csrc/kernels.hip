@@ -1,41 +1,20 @@
 // HIP kernels of the relative-binned likelihood (gfx950, wave64).
 //
 //  k_ref_setup      reference (fiducial) constants for theta0            [1 thread]
-//  k_chain_setup    per-chain record (+ Jacobian for the gradient)       [1 thread / chain]
+//  k_chain_setup    per-chain record                                     [1 thread / chain]
+//  k_chain_setup_grad  record and partial derivatives (dual numbers)    [1 lane / (chain, tangent)]
 //  k_summary_items  summary-data partial sums over (bin, chunk) items    [1 wave / item]
 //  k_summary_reduce ordered sum of the partials of each bin              [1 thread / (det, bin, field)]
 //  k_node_tables    per-edge coefficient tables of the binned sum        [1 thread / node]
-//  k_loglike_fwd    fused ratio + bin contraction + reduction            [1 wave / chain]
-//  k_loglike_grad   the same with the hand-written adjoint               [1 wave / chain]
+//  (k_loglike_fwd and k_loglike_grad, the likelihood kernels, are in likelihood.hip)
 //  k_loglike_full   full-grid likelihood (validation)                    [1 block / chain]
 //  k_strain         projected strain on a grid (injections)              [1 thread / grid point]
 //
 // All reductions are in a fixed order, so results are bitwise reproducible.
 #include "rbl_launch.h"
+#include "rbl_wave.h"
 
 namespace rbl {
-
-// ---------------------------------------------------------------------------
-// Wavefront helpers
-// ---------------------------------------------------------------------------
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-// lane i receives lane i-1's value; lane 0 receives `fill`
-__device__ inline double shift_up(double v, double fill, int lane) {
-    const double u = __shfl_up(v, 1, 64);
-    return lane == 0 ? fill : u;
-}
-// lane i receives lane i+1's value; lane 63 receives `fill`
-__device__ inline double shift_down(double v, double fill, int lane) {
-    const double u = __shfl_down(v, 1, 64);
-    return lane == 63 ? fill : u;
-}
-__device__ inline double lane_value(double v, int src) { return __shfl(v, src, 64); }
-
-__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // ---------------------------------------------------------------------------
 // Reference constants
@@ -88,7 +67,9 @@ __device__ inline void chain_record(const T* th, const Network& net, const RefCo
     dconst = dconst - rint(val(dconst));  // whole revolutions removed (no derivative)
     const T ang = 2.0 * (th[8] - ref.phic0) - (2.0 * kPi) * dconst;
     const T mag = (ref.dl0 / th[6]) * (c.amp / ref.amp0);
-    const Cx<T> common{mag * dcos(ang), mag * dsin(ang)};
+    T sa, ca;
+    dsincos(ang, sa, ca);
+    const Cx<T> common{mag * ca, mag * sa};
     for (int d = 0; d < kMaxDet; ++d) {
         if (d < net.n_det) {
             Proj<T> p;
@@ -117,10 +98,8 @@ __device__ inline int theta_status(const double* t) {
     return ok ? 1 : 0;
 }
 
-template <bool GRAD>
 __global__ __launch_bounds__(64) void k_chain_setup(const double* __restrict__ theta, int64_t B, Network net,
-                                                    RefConsts ref, double* __restrict__ rec,
-                                                    double* __restrict__ jac) {
+                                                    RefConsts ref, double* __restrict__ rec) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     double t[13];
@@ -130,25 +109,108 @@ __global__ __launch_bounds__(64) void k_chain_setup(const double* __restrict__ t
     if (st != 1) {
         out[kRecStatus] = st < 0 ? __builtin_nan("") : 0.0;
         for (int i = 1; i < kRecUsed; ++i) out[i] = 0.0;
-        if (GRAD)
-            for (int i = 0; i < kJacRows * 13; ++i) jac[b * kJacRows * 13 + i] = 0.0;
         return;
     }
     out[kRecStatus] = 1.0;
-    if (!GRAD) {
-        double r[kRecUsed];
-        chain_record<double>(t, net, ref, r);
-        for (int i = 1; i < kRecUsed; ++i) out[i] = r[i];
+    double r[kRecUsed];
+    chain_record<double>(t, net, ref, r);
+    for (int i = 1; i < kRecUsed; ++i) out[i] = r[i];
+}
+
+// Record and partial derivatives for the gradient.  Two kinds of blocks:
+//   intrinsic blocks: 8 lanes per chain, lane t < 6 differentiates the TaylorF2
+//     coefficients with respect to parameter t (one dual component per lane);
+//   extrinsic blocks: 4 lanes per chain, lane a differentiates the projection with
+//     respect to angle a of (iota, psi, ra, dec).
+// Lane 0 of each group writes the values.  The blocks of the two kinds are
+// disjoint, so no wavefront mixes the two code paths.
+constexpr int kIntLanes = 8;
+constexpr int kExtLanes = 4;
+
+__global__ __launch_bounds__(256) void k_chain_setup_grad(const double* __restrict__ theta, int64_t B, Network net,
+                                                          RefConsts ref, double* __restrict__ rec,
+                                                          double* __restrict__ jac, int64_t n_int_blocks) {
+    const bool intrinsic = (int64_t)blockIdx.x < n_int_blocks;
+    const int64_t gid = ((int64_t)blockIdx.x - (intrinsic ? 0 : n_int_blocks)) * blockDim.x + threadIdx.x;
+    const int lanes = intrinsic ? kIntLanes : kExtLanes;
+    const int64_t b = gid / lanes;
+    const int tg = (int)(gid % lanes);
+    if (b >= B) return;
+    double t[13];
+#pragma unroll
+    for (int i = 0; i < 13; ++i) t[i] = theta[b * 13 + i];
+    double* out = rec + b * kRecStride;
+    double* J = jac + b * kJacStride;
+    const int st = theta_status(t);
+    using D1 = Dual<1>;
+    if (intrinsic) {
+        if (tg >= 6) return;
+        if (st != 1) {
+            if (tg == 0) {
+                out[kRecStatus] = st < 0 ? __builtin_nan("") : 0.0;
+                for (int i = kRecDc; i < kRecDc + kTf2Basis; ++i) out[i] = 0.0;
+                out[kRecG] = out[kRecG + 1] = out[kRecDl] = 0.0;
+            }
+            for (int k = 0; k < 12; ++k) J[kJacInt + k * 6 + tg] = 0.0;
+            return;
+        }
+        D1 ti[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            ti[i] = D1(t[i]);
+            ti[i].d[0] = (i == tg) ? 1.0 : 0.0;
+        }
+        Tf2Coeffs<D1> c;
+        tf2_coeffs<D1>(ti[0], ti[1], ti[2], ti[3], ti[4], ti[5], c);
+        for (int k = 0; k < kTf2Basis; ++k) J[kJacInt + k * 6 + tg] = c.c[k].d[0];
+        J[kJacInt + 10 * 6 + tg] = c.c_const.d[0];
+        J[kJacInt + 11 * 6 + tg] = c.amp.d[0] / c.amp.v;
+        if (tg == 0) {
+            out[kRecStatus] = 1.0;
+            for (int k = 0; k < kTf2Basis; ++k) out[kRecDc + k] = c.c[k].v - ref.c0[k];
+            double dconst = c.c_const.v - ref.c0_const;
+            dconst -= rint(dconst);
+            const double ang = 2.0 * (t[8] - ref.phic0) - (2.0 * kPi) * dconst;
+            const double mag = (ref.dl0 / t[6]) * (c.amp.v / ref.amp0);
+            double sa, ca;
+            dsincos(ang, sa, ca);
+            out[kRecG] = mag * ca;
+            out[kRecG + 1] = mag * sa;
+            out[kRecDl] = t[6];
+        }
     } else {
-        using D13 = Dual<13>;
-        D13 td[13];
-        for (int i = 0; i < 13; ++i) td[i] = D13::var(t[i], i);
-        D13 r[kRecUsed];
-        chain_record<D13>(td, net, ref, r);
-        double* J = jac + b * kJacRows * 13;
-        for (int i = 1; i < kRecUsed; ++i) {
-            out[i] = r[i].v;
-            for (int k = 0; k < 13; ++k) J[(i - 1) * 13 + k] = r[i].d[k];
+        if (st != 1) {
+            if (tg == 0)
+                for (int i = kRecK; i < kRecTau + kMaxDet; ++i) out[i] = 0.0;
+            for (int i = 0; i < 36; ++i)
+                if (i % 4 == tg) J[kJacExt + i] = 0.0;
+            return;
+        }
+        D1 ang[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            ang[a] = D1(t[9 + a]);
+            ang[a].d[0] = (a == tg) ? 1.0 : 0.0;
+        }
+        for (int d = 0; d < kMaxDet; ++d) {
+            if (d < net.n_det) {
+                Proj<D1> p;
+                project<D1>(ang[0], ang[1], ang[2], ang[3], net.gmst, net.D[d], net.r[d], p);
+                const Cx<D1> inv0{D1(ref.invC0_re[d]), D1(ref.invC0_im[d])};
+                const Cx<D1> P = cmul(p.C, inv0);
+                J[kJacExt + (d * 3 + 0) * 4 + tg] = P.re.d[0];
+                J[kJacExt + (d * 3 + 1) * 4 + tg] = P.im.d[0];
+                J[kJacExt + (d * 3 + 2) * 4 + tg] = p.dt.d[0];
+                if (tg == 0) {
+                    out[kRecK + 2 * d] = P.re.v;
+                    out[kRecK + 2 * d + 1] = P.im.v;
+                    out[kRecTau + d] = (t[7] + p.dt.v) - ref.tau0[d];
+                }
+            } else {
+                J[kJacExt + (d * 3 + 0) * 4 + tg] = J[kJacExt + (d * 3 + 1) * 4 + tg] =
+                    J[kJacExt + (d * 3 + 2) * 4 + tg] = 0.0;
+                if (tg == 0) out[kRecK + 2 * d] = out[kRecK + 2 * d + 1] = out[kRecTau + d] = 0.0;
+            }
         }
     }
 }
@@ -158,6 +220,7 @@ __global__ __launch_bounds__(64) void k_chain_setup(const double* __restrict__ t
 // one bin); the reference waveform is generated inline, once per point, and
 // projected onto every detector.  Partials: [item][det][7].
 // ---------------------------------------------------------------------------
+template <int ND>
 __global__ __launch_bounds__(256) void k_summary_items(SummaryArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t item = (int64_t)blockIdx.x * 4 + wave_id();
@@ -166,8 +229,10 @@ __global__ __launch_bounds__(256) void k_summary_items(SummaryArgs a) {
     const int64_t k0 = a.item_start[item];
     const int32_t cnt = a.item_count[item];
     const double fm = a.f_low + 0.5 * (double)(a.edges[bin] + a.edges[bin + 1]) * a.delta_f;
-    double acc[kMaxDet][7];
-    for (int d = 0; d < kMaxDet; ++d)
+    double acc[ND][7];
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+#pragma unroll
         for (int j = 0; j < 7; ++j) acc[d][j] = 0.0;
     const RefConsts& ref = a.ref;
     const double w = 4.0 * a.delta_f;
@@ -184,7 +249,8 @@ __global__ __launch_bounds__(256) void k_summary_items(SummaryArgs a) {
         for (int j = 0; j < kTf2Basis; ++j) phi = fma(ref.c0[j], bas[j], phi);
         const double amp = ref.amp0 * (ix * ix * ix) * sqrt(ix);  // f^(-7/6)
         const double df = f - fm;
-        for (int d = 0; d < a.n_det; ++d) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
             double cu, su;
             expm2pi_rev(fma(f, ref.tau0[d], phi), cu, su);
             const double hre = amp * (ref.h0fac_re[d] * cu - ref.h0fac_im[d] * su);
@@ -205,10 +271,12 @@ __global__ __launch_bounds__(256) void k_summary_items(SummaryArgs a) {
             acc[d][6] += hh * df * df;
         }
     }
-    for (int d = 0; d < a.n_det; ++d)
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+#pragma unroll
         for (int j = 0; j < 7; ++j) {
             const double s = wave_sum(acc[d][j]);
-            if (lane == 0) a.partials[(item * a.n_det + d) * 7 + j] = s;
+            if (lane == 0) a.partials[(item * ND + d) * 7 + j] = s;
         }
 }
 
@@ -235,8 +303,9 @@ __global__ void k_summary_reduce(const double* __restrict__ partials, const int6
 //   nu_b = B0/2 - 2 B2 w^2 multiplies Re(r_b r_{b+1}*).
 // ---------------------------------------------------------------------------
 __global__ void k_node_tables(NodeArgs a) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;  // edge index
     if (j >= a.n_nodes_pad) return;
+    const int pos = (j % a.L) * kNodeTile + j / a.L;       // lane-contiguous position
     const bool real_node = j < a.n_nodes;
     const int nb = a.n_nodes - 1;
     double f = 0.0, x = 1.0, ix = 1.0, lx = 0.0;
@@ -246,10 +315,10 @@ __global__ void k_node_tables(NodeArgs a) {
         ix = 1.0 / x;
         lx = log(x);
     }
-    a.node_f[j] = f;
-    a.node_x[j] = x;
-    a.node_ix[j] = ix;
-    a.node_lx[j] = lx;
+    a.node_f[pos] = f;
+    a.node_x[pos] = x;
+    a.node_ix[pos] = ix;
+    a.node_lx[pos] = lx;
     for (int d = 0; d < a.n_det; ++d) {
         double gre = 0.0, gim = 0.0, mu = 0.0, nul = 0.0, nur = 0.0;
         if (real_node) {
@@ -272,213 +341,35 @@ __global__ void k_node_tables(NodeArgs a) {
                 nul = 0.5 * s[4] - 2.0 * b2 * w * w;
             }
         }
-        const int64_t o = (int64_t)d * a.n_nodes_pad + j;
+        const int64_t o = (int64_t)d * a.n_nodes_pad + pos;
         a.g_re[o] = gre;
         a.g_im[o] = gim;
         a.mu[o] = mu;
         a.nuL[o] = nul;
         a.nuR[o] = nur;
+        a.g_re32[o] = (float)gre;
+        a.g_im32[o] = (float)gim;
+        a.mu32[o] = (float)mu;
+        a.nuL32[o] = (float)nul;
     }
 }
 
-// ---------------------------------------------------------------------------
-// Relative-binned likelihood, FP64.  One wavefront per chain; lane l handles
-// edge j = 64 t + l of tile t.  The ratio at the edge is r = K_d exp(-2 pi i phi),
-// phi = sum_b dc_b B_b(x_j) + f_j dtau_d [rev].  The cross term of bin j-1 uses
-// the left neighbour's ratio (shift by one lane; the first lane takes the last
-// lane of the previous tile).
-// ---------------------------------------------------------------------------
-__device__ inline double rec_load(const double* rec, int i) { return rec[i]; }
-
-template <int ND>
-__global__ __launch_bounds__(256) void k_loglike_fwd(EventDev ev, const double* __restrict__ recs, int64_t B,
-                                                     double* __restrict__ lnl) {
-    const int lane = threadIdx.x & 63;
-    const int64_t chain = (int64_t)blockIdx.x * 4 + wave_id();
-    if (chain >= B) return;
-    const double* rec = recs + chain * kRecStride;
-    const double status = rec[kRecStatus];
-    if (!(status == 1.0)) {
-        if (lane == 0) lnl[chain] = (status == 0.0) ? -__builtin_inf() : __builtin_nan("");
-        return;
+// Per-detector magnitude sums of the edge tables (one wavefront per detector,
+// fixed reduction order).
+__global__ __launch_bounds__(64) void k_event_scales(NodeArgs a) {
+    const int d = blockIdx.x;
+    const int lane = threadIdx.x;
+    double gs = 0.0, hs = 0.0;
+    for (int j = lane; j < a.n_nodes_pad; j += 64) {
+        const int64_t o = (int64_t)d * a.n_nodes_pad + j;
+        gs += sqrt(a.g_re[o] * a.g_re[o] + a.g_im[o] * a.g_im[o]);
+        hs += fabs(a.mu[o]) + fabs(a.nuL[o]);
     }
-    double dc[kTf2Basis];
-#pragma unroll
-    for (int j = 0; j < kTf2Basis; ++j) dc[j] = rec[kRecDc + j];
-    double kre[ND], kim[ND], dtau[ND], carry_re[ND], carry_im[ND];
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-        kre[d] = rec[kRecK + 2 * d];
-        kim[d] = rec[kRecK + 2 * d + 1];
-        dtau[d] = rec[kRecTau + d];
-        carry_re[d] = 0.0;
-        carry_im[d] = 0.0;
-    }
-    double acc = 0.0;
-    for (int base = 0; base < ev.n_nodes_pad; base += 64) {
-        const int j = base + lane;
-        const bool live = j < ev.n_nodes;
-        const double f = ev.node_f[j];
-        double bas[kTf2Basis];
-        tf2_basis(ev.node_x[j], ev.node_ix[j], ev.node_lx[j], bas);
-        double ph = 0.0;
-#pragma unroll
-        for (int k = 0; k < kTf2Basis; ++k) ph = fma(dc[k], bas[k], ph);
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            double cu, su;
-            expm2pi_rev(fma(f, dtau[d], ph), cu, su);
-            double rre = kre[d] * cu - kim[d] * su;
-            double rim = kre[d] * su + kim[d] * cu;
-            if (!live) { rre = 0.0; rim = 0.0; }
-            const int64_t o = (int64_t)d * ev.n_nodes_pad + j;
-            const double gre = ev.g_re[o], gim = ev.g_im[o], mu = ev.mu[o], nul = ev.nuL[o];
-            const double lre = shift_up(rre, carry_re[d], lane);
-            const double lim = shift_up(rim, carry_im[d], lane);
-            acc += (gre * rre + gim * rim) - 0.5 * mu * (rre * rre + rim * rim)
-                 - 0.5 * nul * (lre * rre + lim * rim);
-            carry_re[d] = lane_value(rre, 63);
-            carry_im[d] = lane_value(rim, 63);
-        }
-    }
-    acc = wave_sum(acc);
-    if (lane == 0) lnl[chain] = acc;
-}
-
-// ---------------------------------------------------------------------------
-// lnL and gradient.  Adjoint of the binned sum with respect to the edge ratios:
-//   Gbar_j = gamma_j - mu_j r_j - nuR_j r_{j+1}/2 - nuL_j r_{j-1}/2,
-// so that d lnL = sum Re(conj(Gbar_j) d r_j).  With r = K u, u = exp(-2 pi i phi):
-//   d lnL/d phi_j = 2 pi Im(conj(Gbar_j) r_j),  d lnL/dK = sum conj(Gbar_j) u_j (as Re(W dK)).
-// Accumulated per lane: Z_d = sum conj(Gbar) u, T_d = sum Im(z) f, S_b = sum_j (sum_d Im z) B_b(x_j).
-// The right neighbour of a tile's last lane lives in the next tile, so each
-// tile is finished one iteration later.  Epilogue: grad = J^T abar.
-// ---------------------------------------------------------------------------
-template <int ND>
-__global__ __launch_bounds__(256) void k_loglike_grad(EventDev ev, const double* __restrict__ recs,
-                                                      const double* __restrict__ jac, int64_t B,
-                                                      double* __restrict__ lnl, double* __restrict__ grad) {
-    const int lane = threadIdx.x & 63;
-    const int64_t chain = (int64_t)blockIdx.x * 4 + wave_id();
-    if (chain >= B) return;
-    const double* rec = recs + chain * kRecStride;
-    const double status = rec[kRecStatus];
-    if (!(status == 1.0)) {
-        if (lane == 0) lnl[chain] = (status == 0.0) ? -__builtin_inf() : __builtin_nan("");
-        if (lane < 13) grad[chain * 13 + lane] = (status == 0.0) ? 0.0 : __builtin_nan("");
-        return;
-    }
-    double dc[kTf2Basis];
-#pragma unroll
-    for (int j = 0; j < kTf2Basis; ++j) dc[j] = rec[kRecDc + j];
-    double kre[ND], kim[ND], dtau[ND];
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-        kre[d] = rec[kRecK + 2 * d];
-        kim[d] = rec[kRecK + 2 * d + 1];
-        dtau[d] = rec[kRecTau + d];
-    }
-    // accumulators
-    double acc = 0.0;
-    double zre[ND], zim[ND], tacc[ND], sacc[kTf2Basis];
-#pragma unroll
-    for (int d = 0; d < ND; ++d) { zre[d] = 0.0; zim[d] = 0.0; tacc[d] = 0.0; }
-#pragma unroll
-    for (int k = 0; k < kTf2Basis; ++k) sacc[k] = 0.0;
-    // pipeline state: previous tile
-    double p_rre[ND], p_rim[ND], p_cu[ND], p_su[ND];
-    double cl_re[ND], cl_im[ND];  // left carry (last lane of the tile before the previous one)
-#pragma unroll
-    for (int d = 0; d < ND; ++d) { p_rre[d] = p_rim[d] = p_cu[d] = p_su[d] = 0.0; cl_re[d] = cl_im[d] = 0.0; }
-    double p_f = 0.0, p_x = 1.0, p_ix = 1.0, p_lx = 0.0;
-    int p_j = 0;
-    const int ntile = ev.n_nodes_pad / 64;
-    for (int t = 0; t <= ntile; ++t) {
-        double c_rre[ND], c_rim[ND], c_cu[ND], c_su[ND];
-        double c_f = 0.0, c_x = 1.0, c_ix = 1.0, c_lx = 0.0;
-        const int j = t * 64 + lane;
-        if (t < ntile) {
-            const bool live = j < ev.n_nodes;
-            c_f = ev.node_f[j];
-            c_x = ev.node_x[j];
-            c_ix = ev.node_ix[j];
-            c_lx = ev.node_lx[j];
-            double bas[kTf2Basis];
-            tf2_basis(c_x, c_ix, c_lx, bas);
-            double ph = 0.0;
-#pragma unroll
-            for (int k = 0; k < kTf2Basis; ++k) ph = fma(dc[k], bas[k], ph);
-#pragma unroll
-            for (int d = 0; d < ND; ++d) {
-                double cu, su;
-                expm2pi_rev(fma(c_f, dtau[d], ph), cu, su);
-                c_cu[d] = cu;
-                c_su[d] = su;
-                c_rre[d] = live ? kre[d] * cu - kim[d] * su : 0.0;
-                c_rim[d] = live ? kre[d] * su + kim[d] * cu : 0.0;
-            }
-        } else {
-#pragma unroll
-            for (int d = 0; d < ND; ++d) c_rre[d] = c_rim[d] = c_cu[d] = c_su[d] = 0.0;
-        }
-        if (t > 0) {
-            // finish the previous tile (edges p_j)
-            double qsum = 0.0;
-#pragma unroll
-            for (int d = 0; d < ND; ++d) {
-                const double nx_re = lane_value(c_rre[d], 0), nx_im = lane_value(c_rim[d], 0);
-                const double rre = p_rre[d], rim = p_rim[d];
-                const double lre = shift_up(rre, cl_re[d], lane), lim = shift_up(rim, cl_im[d], lane);
-                const double rgt_re = shift_down(rre, nx_re, lane), rgt_im = shift_down(rim, nx_im, lane);
-                const int64_t o = (int64_t)d * ev.n_nodes_pad + p_j;
-                const double gre = ev.g_re[o], gim = ev.g_im[o], mu = ev.mu[o];
-                const double nul = ev.nuL[o], nur = ev.nuR[o];
-                acc += (gre * rre + gim * rim) - 0.5 * mu * (rre * rre + rim * rim)
-                     - 0.5 * nul * (lre * rre + lim * rim);
-                const double gbre = gre - mu * rre - 0.5 * (nur * rgt_re + nul * lre);
-                const double gbim = gim - mu * rim - 0.5 * (nur * rgt_im + nul * lim);
-                // conj(Gbar) u and Im(conj(Gbar) r)
-                zre[d] += gbre * p_cu[d] + gbim * p_su[d];
-                zim[d] += gbre * p_su[d] - gbim * p_cu[d];
-                const double imz = gbre * rim - gbim * rre;
-                tacc[d] = fma(imz, p_f, tacc[d]);
-                qsum += imz;
-                cl_re[d] = lane_value(rre, 63);
-                cl_im[d] = lane_value(rim, 63);
-            }
-            double bas[kTf2Basis];
-            tf2_basis(p_x, p_ix, p_lx, bas);
-#pragma unroll
-            for (int k = 0; k < kTf2Basis; ++k) sacc[k] = fma(qsum, bas[k], sacc[k]);
-        }
-#pragma unroll
-        for (int d = 0; d < ND; ++d) { p_rre[d] = c_rre[d]; p_rim[d] = c_rim[d]; p_cu[d] = c_cu[d]; p_su[d] = c_su[d]; }
-        p_f = c_f; p_x = c_x; p_ix = c_ix; p_lx = c_lx; p_j = j;
-    }
-    // wave reductions
-    acc = wave_sum(acc);
-    double abar[kJacRows];
-#pragma unroll
-    for (int k = 0; k < kTf2Basis; ++k) abar[kRecDc - 1 + k] = 2.0 * kPi * wave_sum(sacc[k]);
-#pragma unroll
-    for (int d = 0; d < kMaxDet; ++d) {
-        if (d < ND) {
-            abar[kRecK - 1 + 2 * d] = wave_sum(zre[d]);
-            abar[kRecK - 1 + 2 * d + 1] = -wave_sum(zim[d]);
-            abar[kRecTau - 1 + d] = 2.0 * kPi * wave_sum(tacc[d]);
-        } else {
-            abar[kRecK - 1 + 2 * d] = 0.0;
-            abar[kRecK - 1 + 2 * d + 1] = 0.0;
-            abar[kRecTau - 1 + d] = 0.0;
-        }
-    }
-    if (lane == 0) lnl[chain] = acc;
-    if (lane < 13) {
-        const double* J = jac + chain * kJacRows * 13;
-        double g = 0.0;
-#pragma unroll
-        for (int r = 0; r < kJacRows; ++r) g = fma(abar[r], J[r * 13 + lane], g);
-        grad[chain * 13 + lane] = g;
+    gs = wave_sum(gs);
+    hs = wave_sum(hs);
+    if (lane == 0) {
+        a.scales[2 * d] = gs;
+        a.scales[2 * d + 1] = hs;
     }
 }
 
@@ -568,17 +459,24 @@ hipError_t launch_ref_setup(const double* theta, const Network& net, RefConsts* 
 
 hipError_t launch_chain_setup(const double* theta, int64_t B, const Network& net, const RefConsts& ref,
                               double* rec, double* jac, hipStream_t s) {
-    const unsigned grid = (unsigned)((B + 63) / 64);
-    if (jac)
-        hipLaunchKernelGGL(k_chain_setup<true>, dim3(grid), dim3(64), 0, s, theta, B, net, ref, rec, jac);
-    else
-        hipLaunchKernelGGL(k_chain_setup<false>, dim3(grid), dim3(64), 0, s, theta, B, net, ref, rec, jac);
+    if (jac) {
+        const int64_t n_int = (B * kIntLanes + 255) / 256;
+        const int64_t n_ext = (B * kExtLanes + 255) / 256;
+        hipLaunchKernelGGL(k_chain_setup_grad, dim3((unsigned)(n_int + n_ext)), dim3(256), 0, s, theta, B, net, ref,
+                           rec, jac, n_int);
+    } else {
+        hipLaunchKernelGGL(k_chain_setup, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, s, theta, B, net, ref, rec);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_summary(const SummaryArgs& a, const int64_t* bin_first_item, double* summary, hipStream_t s) {
     const unsigned g1 = (unsigned)((a.n_items + 3) / 4);
-    hipLaunchKernelGGL(k_summary_items, dim3(g1), dim3(256), 0, s, a);
+    switch (a.n_det) {
+        case 1: hipLaunchKernelGGL(k_summary_items<1>, dim3(g1), dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_summary_items<2>, dim3(g1), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_summary_items<3>, dim3(g1), dim3(256), 0, s, a); break;
+    }
     const int64_t tot = (int64_t)a.n_det * a.n_bins * 7;
     hipLaunchKernelGGL(k_summary_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a.partials,
                        bin_first_item, a.n_bins, a.n_det, summary);
@@ -587,27 +485,7 @@ hipError_t launch_summary(const SummaryArgs& a, const int64_t* bin_first_item, d
 
 hipError_t launch_node_tables(const NodeArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_node_tables, dim3((unsigned)((a.n_nodes_pad + 255) / 256)), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_loglike(const EventDev& ev, const double* rec, int64_t B, double* lnl, hipStream_t s) {
-    const unsigned grid = (unsigned)((B + 3) / 4);
-    switch (ev.n_det) {
-        case 1: hipLaunchKernelGGL(k_loglike_fwd<1>, dim3(grid), dim3(256), 0, s, ev, rec, B, lnl); break;
-        case 2: hipLaunchKernelGGL(k_loglike_fwd<2>, dim3(grid), dim3(256), 0, s, ev, rec, B, lnl); break;
-        default: hipLaunchKernelGGL(k_loglike_fwd<3>, dim3(grid), dim3(256), 0, s, ev, rec, B, lnl); break;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_loglike_grad(const EventDev& ev, const double* rec, const double* jac, int64_t B, double* lnl,
-                               double* grad, hipStream_t s) {
-    const unsigned grid = (unsigned)((B + 3) / 4);
-    switch (ev.n_det) {
-        case 1: hipLaunchKernelGGL(k_loglike_grad<1>, dim3(grid), dim3(256), 0, s, ev, rec, jac, B, lnl, grad); break;
-        case 2: hipLaunchKernelGGL(k_loglike_grad<2>, dim3(grid), dim3(256), 0, s, ev, rec, jac, B, lnl, grad); break;
-        default: hipLaunchKernelGGL(k_loglike_grad<3>, dim3(grid), dim3(256), 0, s, ev, rec, jac, B, lnl, grad); break;
-    }
+    hipLaunchKernelGGL(k_event_scales, dim3((unsigned)a.n_det), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1,0 +1,386 @@
+// Relative-binned likelihood kernels (gfx950, wave64): lnL, and lnL with the adjoint
+// gradient, each in FP64 or mixed precision.
+//
+// One wavefront per chain.  Lane l walks its L consecutive bin edges j = l L + k
+// (k = 0..L-1) in the lane-contiguous table layout.  At each edge the ratio of
+// Eq. (4) is r_d = K_d exp(-2 pi i phi_d), phi_d = sum_b dc_b B_b(x_j) + f_j dtau_d
+// (revolutions), and the binned sum of Eq. (5) is regrouped per edge:
+//   lnL = sum_d sum_j [ Re(gamma_dj r_dj*) - mu_dj |r_dj|^2 / 2 + c_dj Re(r_d,j-1 r_dj*) ],
+//   c_dj = -nuL_dj / 2  (the cross term of the bin left of edge j).
+//
+// Mixed precision: the phase is accumulated in FP64 and reduced to (-1/2, 1/2]
+// revolutions in FP64; sin/cos (hardware, revolution argument), the ratio and the
+// per-edge products are FP32; every per-edge term is added to an FP64 accumulator.
+// A chain whose binned-sum magnitude bound exceeds kMixedScaleMax takes the FP64
+// path (a wavefront-uniform branch).
+#include "rbl_launch.h"
+#include "rbl_wave.h"
+
+namespace rbl {
+
+// Unit phasor u = exp(-2 pi i phi) for a phase in revolutions.
+__device__ inline void unit_phasor(double phi, double& c, double& s) { expm2pi_rev(phi, c, s); }
+__device__ inline void unit_phasor(double phi, float& c, float& s) {
+    const float t = (float)(phi - rint(phi));  // exact reduction in FP64, then rounded once
+    c = __builtin_amdgcn_cosf(t);              // v_cos_f32: cos(2 pi t)
+    s = -__builtin_amdgcn_sinf(t);             // v_sin_f32: sin(2 pi t)
+}
+
+template <class R>
+struct EdgeTab {
+    const R *gre, *gim, *mu, *nul;
+};
+__device__ inline EdgeTab<double> edge_tab(const EventDev& ev, double) { return {ev.g_re, ev.g_im, ev.mu, ev.nuL}; }
+__device__ inline EdgeTab<float> edge_tab(const EventDev& ev, float) { return {ev.g_re32, ev.g_im32, ev.mu32, ev.nuL32}; }
+
+// Per-chain values shared by the walks.
+template <int ND>
+struct ChainVals {
+    double dc[kTf2Basis];
+    double kre[ND], kim[ND], dtau[ND];
+};
+
+template <int ND>
+__device__ inline bool use_mixed(const EventDev& ev, const ChainVals<ND>& cv) {
+    double bound = 0.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const double k2 = cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d];
+        bound += sqrt(k2) * ev.scales[2 * d] + k2 * ev.scales[2 * d + 1];
+    }
+    return bound <= kMixedScaleMax;
+}
+
+// ---------------------------------------------------------------------------
+// Forward walk: this lane's share of lnL.  The cross term of the bin left of a
+// lane's first edge needs the last edge of lane - 1: exchanged once at the end.
+// ---------------------------------------------------------------------------
+template <int ND, class R>
+__device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, int lane) {
+    const EdgeTab<R> T = edge_tab(ev, R(0));
+    const int npad = ev.n_nodes_pad;
+    R kre[ND], kim[ND], pre[ND], pim[ND], fre[ND], fim[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        kre[d] = (R)cv.kre[d];
+        kim[d] = (R)cv.kim[d];
+        pre[d] = pim[d] = fre[d] = fim[d] = R(0);
+    }
+    double acc = 0.0;
+    for (int k = 0; k < ev.L; ++k) {
+        const int pos = k * 64 + lane;
+        const double f = ev.node_f[pos];
+        double bas[kTf2Basis];
+        tf2_basis(ev.node_x[pos], ev.node_ix[pos], ev.node_lx[pos], bas);
+        double ph = 0.0;
+#pragma unroll
+        for (int b = 0; b < kTf2Basis; ++b) ph = fma(cv.dc[b], bas[b], ph);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            R cu, su;
+            unit_phasor(fma(f, cv.dtau[d], ph), cu, su);
+            const R rre = kre[d] * cu - kim[d] * su;
+            const R rim = kre[d] * su + kim[d] * cu;
+            const int o = d * npad + pos;
+            R t = (T.gre[o] * rre + T.gim[o] * rim) - R(0.5) * T.mu[o] * (rre * rre + rim * rim);
+            if (k > 0) {
+                t -= R(0.5) * T.nul[o] * (pre[d] * rre + pim[d] * rim);
+            } else {
+                fre[d] = rre;
+                fim[d] = rim;
+            }
+            acc += (double)t;
+            pre[d] = rre;
+            pim[d] = rim;
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const R lre = shift_up(pre[d], R(0), lane), lim = shift_up(pim[d], R(0), lane);
+        acc -= (double)(R(0.5) * T.nul[d * npad + lane] * (lre * fre[d] + lim * fim[d]));
+    }
+    return acc;
+}
+
+template <int ND, bool MIXED>
+__global__ __launch_bounds__(256) void k_loglike_fwd(EventDev ev, const double* __restrict__ recs, int64_t B,
+                                                     double* __restrict__ lnl) {
+    const int lane = threadIdx.x & 63;
+    const int64_t chain = (int64_t)blockIdx.x * 4 + wave_id();
+    if (chain >= B) return;
+    const double* rec = recs + chain * kRecStride;
+    const double status = rec[kRecStatus];
+    if (!(status == 1.0)) {
+        if (lane == 0) lnl[chain] = (status == 0.0) ? -__builtin_inf() : __builtin_nan("");
+        return;
+    }
+    ChainVals<ND> cv;
+#pragma unroll
+    for (int j = 0; j < kTf2Basis; ++j) cv.dc[j] = rec[kRecDc + j];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        cv.kre[d] = rec[kRecK + 2 * d];
+        cv.kim[d] = rec[kRecK + 2 * d + 1];
+        cv.dtau[d] = rec[kRecTau + d];
+    }
+    double acc;
+    if (MIXED && use_mixed<ND>(ev, cv))
+        acc = fwd_walk<ND, float>(ev, cv, lane);
+    else
+        acc = fwd_walk<ND, double>(ev, cv, lane);
+    acc = wave_sum(acc);
+    if (lane == 0) lnl[chain] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Gradient.  d lnL = sum_j Re(conj(Gbar_j) dr_j) with
+//   Gbar_j = gamma_j - mu_j r_j + c_j r_{j-1} + c_{j+1} r_{j+1},   z_j = conj(Gbar_j) r_j,
+//   d lnL / d phi_j = 2 pi Im z_j,   d lnL = Re(Z_d dK_d / K_d),  Z_d = sum_j z_dj.
+// Each cross term is handled at its later edge: with w = c conj(r_{j-1}) r_j it adds
+// w to z_j and conj(w) to z_{j-1} (2 Re w to Z_d, Im w to Im z_j, -Im w to Im z_{j-1}).
+// Per lane: Z_d, T_d = sum_j Im(z_dj) f_j and S_b = sum_j (sum_d Im z_dj) B_b(x_j);
+// an edge's basis term is completed one step later, when the cross term to its right
+// is known.  Each lane first evaluates the ratio at the edge before its first edge
+// (owned by the previous lane), so nothing crosses lanes inside the walk.
+// ---------------------------------------------------------------------------
+template <int ND>
+struct GradAcc {
+    double acc;
+    double zr[ND], zi[ND], ta[ND];
+    double sa[kTf2Basis];
+};
+
+template <int ND, class R>
+__device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, int lane, GradAcc<ND>& G) {
+    const EdgeTab<R> T = edge_tab(ev, R(0));
+    const int npad = ev.n_nodes_pad;
+    const int L = ev.L;
+    R kre[ND], kim[ND], rpr[ND], rpi[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        kre[d] = (R)cv.kre[d];
+        kim[d] = (R)cv.kim[d];
+    }
+    // halo edge: the last edge of lane - 1 (lane 0 has none; its first edge has nuL = 0)
+    const int hpos = lane > 0 ? (L - 1) * 64 + (lane - 1) : npad - 1;
+    double fp = ev.node_f[hpos], xp = ev.node_x[hpos], ixp = ev.node_ix[hpos], lxp = ev.node_lx[hpos];
+    {
+        double bas[kTf2Basis];
+        tf2_basis(xp, ixp, lxp, bas);
+        double ph = 0.0;
+#pragma unroll
+        for (int b = 0; b < kTf2Basis; ++b) ph = fma(cv.dc[b], bas[b], ph);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            R ur, ui;
+            unit_phasor(fma(fp, cv.dtau[d], ph), ur, ui);
+            rpr[d] = kre[d] * ur - kim[d] * ui;
+            rpi[d] = kre[d] * ui + kim[d] * ur;
+        }
+    }
+    double qprev = 0.0;  // Im z of the previous edge without its right cross term (halo: not ours)
+    for (int k = 0; k < L; ++k) {
+        const int pos = k * 64 + lane;
+        const double f = ev.node_f[pos], x = ev.node_x[pos], ix = ev.node_ix[pos], lx = ev.node_lx[pos];
+        double bas[kTf2Basis];
+        tf2_basis(x, ix, lx, bas);
+        double ph = 0.0;
+#pragma unroll
+        for (int b = 0; b < kTf2Basis; ++b) ph = fma(cv.dc[b], bas[b], ph);
+        double q = 0.0, p = 0.0;
+        const double df = f - fp;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            R ur, ui;
+            unit_phasor(fma(f, cv.dtau[d], ph), ur, ui);
+            const R rre = kre[d] * ur - kim[d] * ui;
+            const R rim = kre[d] * ui + kim[d] * ur;
+            const int o = d * npad + pos;
+            const R gre = T.gre[o], gim = T.gim[o], mu = T.mu[o];
+            const R c = R(-0.5) * T.nul[o];
+            const R glr = gre - mu * rre, gli = gim - mu * rim;  // local part of Gbar
+            const R reloc = glr * rre + gli * rim, imz = glr * rim - gli * rre;
+            const R rew = c * (rpr[d] * rre + rpi[d] * rim), imw = c * (rpr[d] * rim - rpi[d] * rre);
+            G.acc += (double)(reloc + R(0.5) * mu * (rre * rre + rim * rim) + rew);
+            G.zr[d] += (double)(reloc + R(2) * rew);
+            G.zi[d] += (double)imz;
+            q += (double)(imz + imw);
+            p += (double)imw;
+            G.ta[d] = fma((double)imz, f, fma((double)imw, df, G.ta[d]));
+            rpr[d] = rre;
+            rpi[d] = rim;
+        }
+        {   // the previous edge is now complete: it carries q_prev - p
+            double bp[kTf2Basis];
+            tf2_basis(xp, ixp, lxp, bp);
+            const double qp = qprev - p;
+#pragma unroll
+            for (int b = 0; b < kTf2Basis; ++b) G.sa[b] = fma(qp, bp[b], G.sa[b]);
+        }
+        qprev = q;
+        fp = f; xp = x; ixp = ix; lxp = lx;
+    }
+    double bp[kTf2Basis];
+    tf2_basis(xp, ixp, lxp, bp);
+#pragma unroll
+    for (int b = 0; b < kTf2Basis; ++b) G.sa[b] = fma(qprev, bp[b], G.sa[b]);
+}
+
+template <int ND, bool MIXED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_loglike_grad(
+    EventDev ev, const double* __restrict__ recs, const double* __restrict__ jac, int64_t B,
+    double* __restrict__ lnl, double* __restrict__ grad) {
+    const int lane = threadIdx.x & 63;
+    const int64_t chain = (int64_t)blockIdx.x * 4 + wave_id();
+    if (chain >= B) return;
+    const double* rec = recs + chain * kRecStride;
+    const double status = rec[kRecStatus];
+    if (!(status == 1.0)) {
+        if (lane == 0) lnl[chain] = (status == 0.0) ? -__builtin_inf() : __builtin_nan("");
+        if (lane < 13) grad[chain * 13 + lane] = (status == 0.0) ? 0.0 : __builtin_nan("");
+        return;
+    }
+    ChainVals<ND> cv;
+#pragma unroll
+    for (int j = 0; j < kTf2Basis; ++j) cv.dc[j] = rec[kRecDc + j];
+    const double g_re = rec[kRecG], g_im = rec[kRecG + 1];
+    bool zero_k = false;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const double pr = rec[kRecK + 2 * d], pi = rec[kRecK + 2 * d + 1];
+        cv.kre[d] = pr * g_re - pi * g_im;  // K_d = P_d G
+        cv.kim[d] = pr * g_im + pi * g_re;
+        cv.dtau[d] = rec[kRecTau + d];
+        zero_k = zero_k || !(cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d] > 1e-280);
+    }
+    GradAcc<ND> G;
+    G.acc = 0.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) G.zr[d] = G.zi[d] = G.ta[d] = 0.0;
+#pragma unroll
+    for (int b = 0; b < kTf2Basis; ++b) G.sa[b] = 0.0;
+    if (MIXED && use_mixed<ND>(ev, cv))
+        grad_walk<ND, float>(ev, cv, lane, G);
+    else
+        grad_walk<ND, double>(ev, cv, lane, G);
+
+    // Wave reductions.  Z'_d = Z_d / K_d is the gradient with respect to K_d.
+    const double acc = wave_sum(G.acc);
+    double A[kTf2Basis], ZR[ND], ZI[ND], Tt[ND];
+#pragma unroll
+    for (int b = 0; b < kTf2Basis; ++b) A[b] = 2.0 * kPi * wave_sum(G.sa[b]);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const double zre = wave_sum(G.zr[d]), zim = wave_sum(G.zi[d]);
+        const double k2 = cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d];
+        ZR[d] = (zre * cv.kre[d] + zim * cv.kim[d]) / k2;
+        ZI[d] = (zim * cv.kre[d] - zre * cv.kim[d]) / k2;
+        Tt[d] = 2.0 * kPi * wave_sum(G.ta[d]);
+    }
+    if (zero_k) {
+        // A detector with K_d = 0 has r = 0 everywhere: d lnL / dK_d = sum_j conj(gamma_j) u_j.
+        const int npad = ev.n_nodes_pad;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            if (cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d] > 1e-280) continue;
+            double sr = 0.0, si = 0.0;
+            for (int k = 0; k < ev.L; ++k) {
+                const int pos = k * 64 + lane;
+                double bas[kTf2Basis];
+                tf2_basis(ev.node_x[pos], ev.node_ix[pos], ev.node_lx[pos], bas);
+                double ph = 0.0;
+                for (int b = 0; b < kTf2Basis; ++b) ph = fma(cv.dc[b], bas[b], ph);
+                double ur, ui;
+                expm2pi_rev(fma(ev.node_f[pos], cv.dtau[d], ph), ur, ui);
+                const int o = d * npad + pos;
+                sr += ev.g_re[o] * ur + ev.g_im[o] * ui;
+                si += ev.g_re[o] * ui - ev.g_im[o] * ur;
+            }
+            ZR[d] = wave_sum(sr);
+            ZI[d] = wave_sum(si);
+        }
+    }
+    // Chain rule through the setup: d lnL = sum_b A_b d dc_b + sum_d Re(Z'_d dK_d) + sum_d T_d d dtau_d,
+    //   intrinsic i:  dK_d = K_d (d ln amp - 2 pi i d dc_const)
+    //   dL: dK_d = -K_d / dL;  phic: dK_d = 2i K_d;  tc: d dtau_d = 1
+    //   angles a:     dK_d = G dP_d,  d dtau_d = d dt_d
+    if (lane == 0) lnl[chain] = acc;
+    if (lane < 13) {
+        const double* J = jac + chain * kJacStride;
+        double g = 0.0;
+        if (lane < 6) {
+#pragma unroll
+            for (int b = 0; b < kTf2Basis; ++b) g = fma(A[b], J[kJacInt + b * 6 + lane], g);
+            const double dre = J[kJacInt + 11 * 6 + lane];
+            const double dim = -2.0 * kPi * J[kJacInt + 10 * 6 + lane];
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                const double wr = ZR[d] * cv.kre[d] - ZI[d] * cv.kim[d], wi = ZR[d] * cv.kim[d] + ZI[d] * cv.kre[d];
+                g += wr * dre - wi * dim;
+            }
+        } else if (lane == 6 || lane == 8) {
+            double sr = 0.0, si = 0.0;  // sum_d Z'_d K_d
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                sr += ZR[d] * cv.kre[d] - ZI[d] * cv.kim[d];
+                si += ZR[d] * cv.kim[d] + ZI[d] * cv.kre[d];
+            }
+            g = (lane == 6) ? -sr / rec[kRecDl] : -2.0 * si;
+        } else if (lane == 7) {
+#pragma unroll
+            for (int d = 0; d < ND; ++d) g += Tt[d];
+        } else {
+            const int a = lane - 9;
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                const double pr = J[kJacExt + (d * 3 + 0) * 4 + a], pi = J[kJacExt + (d * 3 + 1) * 4 + a];
+                const double kr = g_re * pr - g_im * pi, ki = g_re * pi + g_im * pr;  // dK_d
+                g += ZR[d] * kr - ZI[d] * ki + Tt[d] * J[kJacExt + (d * 3 + 2) * 4 + a];
+            }
+        }
+        grad[chain * 13 + lane] = g;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers: 4 chains (wavefronts) per 256-thread workgroup.
+// ---------------------------------------------------------------------------
+template <int ND>
+static void fwd_nd(const EventDev& ev, const double* rec, int64_t B, int mixed, double* lnl, hipStream_t s) {
+    const unsigned grid = (unsigned)((B + 3) / 4);
+    if (mixed)
+        hipLaunchKernelGGL((k_loglike_fwd<ND, true>), dim3(grid), dim3(256), 0, s, ev, rec, B, lnl);
+    else
+        hipLaunchKernelGGL((k_loglike_fwd<ND, false>), dim3(grid), dim3(256), 0, s, ev, rec, B, lnl);
+}
+
+hipError_t launch_loglike(const EventDev& ev, const double* rec, int64_t B, int mixed, double* lnl, hipStream_t s) {
+    switch (ev.n_det) {
+        case 1: fwd_nd<1>(ev, rec, B, mixed, lnl, s); break;
+        case 2: fwd_nd<2>(ev, rec, B, mixed, lnl, s); break;
+        default: fwd_nd<3>(ev, rec, B, mixed, lnl, s); break;
+    }
+    return hipGetLastError();
+}
+
+template <int ND>
+static void grad_nd(const EventDev& ev, const double* rec, const double* jac, int64_t B, int mixed, double* lnl,
+                    double* grad, hipStream_t s) {
+    const unsigned grid = (unsigned)((B + 3) / 4);
+    if (mixed)
+        hipLaunchKernelGGL((k_loglike_grad<ND, true>), dim3(grid), dim3(256), 0, s, ev, rec, jac, B, lnl, grad);
+    else
+        hipLaunchKernelGGL((k_loglike_grad<ND, false>), dim3(grid), dim3(256), 0, s, ev, rec, jac, B, lnl, grad);
+}
+
+hipError_t launch_loglike_grad(const EventDev& ev, const double* rec, const double* jac, int64_t B, int mixed,
+                               double* lnl, double* grad, hipStream_t s) {
+    switch (ev.n_det) {
+        case 1: grad_nd<1>(ev, rec, jac, B, mixed, lnl, grad, s); break;
+        case 2: grad_nd<2>(ev, rec, jac, B, mixed, lnl, grad, s); break;
+        default: grad_nd<3>(ev, rec, jac, B, mixed, lnl, grad, s); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace rbl

@@ -10,18 +10,31 @@ namespace rbl {
 constexpr int kMaxDet = 3;
 constexpr int kNodeTile = 64;  // node tables are padded to a multiple of the wavefront
 
-// Per-chain record produced by the setup kernel (FP64, 32 doubles, 256 B).
+// Per-chain record produced by the setup kernels (FP64, 32 doubles, 256 B).
 //   [0]        status: 1 valid, 0 outside the physical domain, NaN if theta has a NaN
 //   [1..10]    dc_b  = c_b(theta) - c_b(theta0), TaylorF2 basis coefficients [rev]
-//   [11..16]   K_d   = (C_d/C_d0)(dL0/dL)(Mc/Mc0)^(5/6) exp(2i dphic) exp(-2 pi i dc_const), (re, im) per d
+//   [11..16]   likelihood setup: K_d = P_d G, (re, im) per detector;
+//              gradient setup:   P_d itself (the kernel forms K_d = P_d G), where
+//              P_d = C_d / C_d0 and G = (dL0/dL)(Mc/Mc0)^(5/6) exp(2i (phic - phic0)) exp(-2 pi i dc_const)
 //   [17..19]   dtau_d = (tc + dt_d) - (tc0 + dt_d0)  [s]
+//   [20..21]   G (re, im)                 (gradient setup only)
+//   [22]       dL                         (gradient setup only)
 constexpr int kRecStride = 32;
 constexpr int kRecStatus = 0;
 constexpr int kRecDc = 1;
 constexpr int kRecK = 11;
 constexpr int kRecTau = 17;
-constexpr int kRecUsed = 20;                 // entries 1..19 are differentiable
-constexpr int kJacRows = kRecUsed - 1;       // rows of d(record)/d(theta), record entries 1..19
+constexpr int kRecG = 20;
+constexpr int kRecDl = 22;
+constexpr int kRecUsed = 20;                 // entries 1..19 are used by the likelihood kernels
+
+// Partial derivatives stored per chain for the gradient (FP64, 112 doubles):
+//   [0, 72)    d(dc_b, dc_const, ln amp)/d(Mc, q, chi1, chi2, Lambda1, Lambda2), [12][6]
+//   [72, 108)  d(Re P_d, Im P_d, dt_d)/d(iota, psi, ra, dec), [3 det][3][4]
+// The remaining dependencies (dL, tc, phic) are applied in closed form.
+constexpr int kJacStride = 112;
+constexpr int kJacInt = 0;
+constexpr int kJacExt = 72;
 
 // Reference (fiducial) constants computed once per event on the device.
 struct RefConsts {
@@ -44,8 +57,14 @@ struct Network {
 };
 
 // Device pointers of a resident event.
+//
+// Edge ("node") tables use a lane-contiguous layout: with L = ceil(n_nodes / 64)
+// edges per lane, edge j belongs to lane j / L at step k = j % L and is stored at
+// k * 64 + lane.  A wavefront that walks k = 0..L-1 therefore reads each table
+// row with one coalesced access, and every lane sees consecutive edges (only the
+// first edge of a lane needs a neighbour from another lane).
 struct EventDev {
-    int32_t n_det, n_bins, n_nodes, n_nodes_pad;
+    int32_t n_det, n_bins, n_nodes, n_nodes_pad, L;
     int64_t n_freq;
     double f_low, delta_f;
     // node tables, each [n_nodes_pad] (padding: f = 0, x = ix = 1, lx = 0)
@@ -59,6 +78,21 @@ struct EventDev {
     const double* mu;
     const double* nuL;
     const double* nuR;
+    // FP32 copies of gamma, mu, nuL for the mixed-precision kernels
+    const float* g_re32;
+    const float* g_im32;
+    const float* mu32;
+    const float* nuL32;
+    // per detector: Gs_d = sum_j |gamma_dj|, Hs_d = sum_j (|mu_dj| + |nuL_dj|)  [2 * kMaxDet]
+    // (a chain's binned-sum magnitude is at most sum_d |K_d| Gs_d + |K_d|^2 Hs_d)
+    const double* scales;
 };
+
+// Mixed precision is used for a chain while the magnitude bound of its binned sum,
+// M = sum_d |K_d| Gs_d + |K_d|^2 Hs_d, stays below this value; larger chains take the
+// FP64 path.  Measured on the 3-detector TaylorF2 workload (1024 chains, all forced to
+// the mixed path), the mixed-path error stayed below 4.1e-8 M in every range of M from
+// 1e3 to 1e7, so M <= 5e4 keeps it under 2.1e-3, five times inside the 1e-2 bound.
+constexpr double kMixedScaleMax = 5.0e4;
 
 }  // namespace rbl

@@ -24,12 +24,14 @@ struct SummaryArgs {
 };
 
 struct NodeArgs {
-    int32_t n_nodes, n_nodes_pad, n_det, keep_b2;
+    int32_t n_nodes, n_nodes_pad, L, n_det, keep_b2;
     const int64_t* edges;
     double f_low, delta_f;
     const double* summary;  // [n_det][n_bins][7]
     double *node_f, *node_x, *node_ix, *node_lx;
     double *g_re, *g_im, *mu, *nuL, *nuR;
+    float *g_re32, *g_im32, *mu32, *nuL32;
+    double* scales;
 };
 
 struct FullArgs {
@@ -48,9 +50,9 @@ hipError_t launch_chain_setup(const double* theta, int64_t B, const Network& net
                               double* rec, double* jac, hipStream_t s);
 hipError_t launch_summary(const SummaryArgs& a, const int64_t* bin_first_item, double* summary, hipStream_t s);
 hipError_t launch_node_tables(const NodeArgs& a, hipStream_t s);
-hipError_t launch_loglike(const EventDev& ev, const double* rec, int64_t B, double* lnl, hipStream_t s);
-hipError_t launch_loglike_grad(const EventDev& ev, const double* rec, const double* jac, int64_t B, double* lnl,
-                               double* grad, hipStream_t s);
+hipError_t launch_loglike(const EventDev& ev, const double* rec, int64_t B, int mixed, double* lnl, hipStream_t s);
+hipError_t launch_loglike_grad(const EventDev& ev, const double* rec, const double* jac, int64_t B, int mixed,
+                               double* lnl, double* grad, hipStream_t s);
 hipError_t launch_loglike_full(const FullArgs& a, int64_t B, hipStream_t s);
 hipError_t launch_strain(const RefConsts* cst_dev, int32_t n_det, double f_low, double delta_f, int64_t n_freq,
                          double* out, hipStream_t s);

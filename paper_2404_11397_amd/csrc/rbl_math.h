@@ -127,15 +127,72 @@ template <class T> __host__ __device__ inline Cx<T> cdiv(const Cx<T>& a, const C
 }
 
 // ----------------------------------------------------------------------------
-// exp(-2 pi i phi) for a phase phi given in revolutions, FP64.
-// The integer part is removed exactly (phi - rint(phi)), then sin/cos of pi*x.
+// cos(2 pi phi) and sin(2 pi phi) for a phase phi in revolutions, FP64.
+// Reduction: y = 4 phi (exact), k = rint(y), t = y - k in [-1/2, 1/2] (exact for
+// |y| < 2^52), so 2 pi phi = (pi/2) k + (pi/2) t.  On |(pi/2) t| <= pi/4 the Taylor
+// series of sin to degree 15 and of cos to degree 16 are accurate to < 1e-16;
+// the quadrant k mod 4 rotates the pair.
 // ----------------------------------------------------------------------------
+namespace detail {
+constexpr double kHalfPi = 1.57079632679489661923;
+constexpr double ipow(double x, int n) { return n == 0 ? 1.0 : x * ipow(x, n - 1); }
+constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
+// sin((pi/2) t) = t * sum_n S_n (t^2)^n,   cos((pi/2) t) = sum_n C_n (t^2)^n  (Taylor coefficients)
+constexpr double S(int n) { return ((n & 1) ? -1.0 : 1.0) * ipow(kHalfPi, 2 * n + 1) / fact(2 * n + 1); }
+constexpr double C(int n) { return ((n & 1) ? -1.0 : 1.0) * ipow(kHalfPi, 2 * n) / fact(2 * n); }
+constexpr double kS0 = S(0), kS1 = S(1), kS2 = S(2), kS3 = S(3), kS4 = S(4), kS5 = S(5), kS6 = S(6), kS7 = S(7);
+constexpr double kC0 = C(0), kC1 = C(1), kC2 = C(2), kC3 = C(3), kC4 = C(4), kC5 = C(5), kC6 = C(6), kC7 = C(7),
+                 kC8 = C(8);
+}  // namespace detail
+
+__device__ inline void sincos_rev(double phi, double& c, double& s) {
+    using namespace detail;
+    const double y = 4.0 * phi;
+    const double k = rint(y);
+    const double t = y - k;
+    const double t2 = t * t;
+    double ps = kS7;
+    ps = fma(ps, t2, kS6);
+    ps = fma(ps, t2, kS5);
+    ps = fma(ps, t2, kS4);
+    ps = fma(ps, t2, kS3);
+    ps = fma(ps, t2, kS2);
+    ps = fma(ps, t2, kS1);
+    ps = fma(ps, t2, kS0);
+    const double sn = ps * t;
+    double pc = kC8;
+    pc = fma(pc, t2, kC7);
+    pc = fma(pc, t2, kC6);
+    pc = fma(pc, t2, kC5);
+    pc = fma(pc, t2, kC4);
+    pc = fma(pc, t2, kC3);
+    pc = fma(pc, t2, kC2);
+    pc = fma(pc, t2, kC1);
+    const double cs = fma(pc, t2, kC0);
+    const int q = ((int)k) & 3;
+    const double a = (q & 1) ? sn : cs;   // cos of the rotated angle, up to sign
+    const double b = (q & 1) ? cs : sn;   // sin of the rotated angle, up to sign
+    c = (q == 1 || q == 2) ? -a : a;
+    s = (q >= 2) ? -b : b;
+}
+
+// exp(-2 pi i phi) = c + i s for a phase in revolutions.
 __device__ inline void expm2pi_rev(double phi, double& c, double& s) {
-    const double r = phi - rint(phi);
     double sn, cs;
-    sincospi(2.0 * r, &sn, &cs);
+    sincos_rev(phi, cs, sn);
     c = cs;
     s = -sn;
+}
+
+// sin and cos of an angle in radians (through revolutions), for double and duals.
+constexpr double kInv2Pi = 0.15915494309189533577;
+__device__ inline void dsincos(double a, double& s, double& c) { sincos_rev(a * kInv2Pi, c, s); }
+template <int N>
+__device__ inline void dsincos(const Dual<N>& a, Dual<N>& s, Dual<N>& c) {
+    double sv, cv;
+    sincos_rev(a.v * kInv2Pi, cv, sv);
+    s = lift(a, sv, cv);
+    c = lift(a, cv, -sv);
 }
 
 }  // namespace rbl

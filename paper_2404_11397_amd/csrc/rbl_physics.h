@@ -142,12 +142,14 @@ struct Proj {
 };
 
 template <class T>
-__host__ __device__ inline void project(const T& iota, const T& psi, const T& ra, const T& dec, double gmst,
+__device__ inline void project(const T& iota, const T& psi, const T& ra, const T& dec, double gmst,
                                         const double* D /*[9]*/, const double* r /*[3]*/, Proj<T>& out) {
     const T ph = ra - gmst;
-    const T sph = dsin(ph), cph = dcos(ph);
-    const T sd = dsin(dec), cd = dcos(dec);
-    const T sp = dsin(psi), cp = dcos(psi);
+    T sph, cph, sd, cd, sp, cp, si, ci;
+    dsincos(ph, sph, cph);
+    dsincos(dec, sd, cd);
+    dsincos(psi, sp, cp);
+    dsincos(iota, si, ci);
     const T n[3] = {cd * cph, cd * sph, sd};
     const T eth[3] = {sd * cph, sd * sph, -cd};
     const T eph[3] = {-sph, cph, T(0.0)};
@@ -170,7 +172,6 @@ __host__ __device__ inline void project(const T& iota, const T& psi, const T& ra
     const T qDp = qv[0] * Dp[0] + qv[1] * Dp[1] + qv[2] * Dp[2];
     const T fplus = pDp - qDq;
     const T fcross = pDq + qDp;
-    const T ci = dcos(iota);
     out.C.re = 0.5 * (1.0 + ci * ci) * fplus;
     out.C.im = -(ci * fcross);
     out.dt = -(r[0] * n[0] + r[1] * n[1] + r[2] * n[2]) / kC;

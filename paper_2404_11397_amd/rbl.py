@@ -48,6 +48,13 @@ def profile_read():
     return m.value, s.value, n.value
 
 
+def profile_read_summary():
+    """(summary-pass ms, events) summed over events created since the last read."""
+    m, n = ctypes.c_double(), ctypes.c_int64()
+    check(_lib.lib().rbl_profile_read_summary(ctypes.byref(m), ctypes.byref(n)))
+    return m.value, n.value
+
+
 def bin_edges(f_low, delta_f, n_freq, n_bins):
     """Bin edges from the library's post-Newtonian phase-bound ansatz (host)."""
     out = np.empty(n_bins + 1, dtype=np.int64)

@@ -204,3 +204,36 @@ def test_loglike_and_grad_parity_cfg2_sampled(cfg2):
     rel = np.abs(gs - ws).max(axis=1) / np.abs(ws).max(axis=1)
     say("cfg2 grad max rel err", rel.max())
     assert np.all(rel <= 1e-5)
+
+
+# ---- mixed precision (FP64 phase, FP32 sin/cos and per-edge products, FP64 sums) -------------
+
+def test_mixed_loglike_cfg1(cfg1):
+    ev, w, gev = cfg1
+    th = w["theta"]
+    got = gev.loglike(_cuda(th), precision="mixed").cpu().numpy()
+    want = L.loglike_rb(ev, th)
+    err = np.abs(got - want)
+    say("cfg1 mixed lnL max abs err", err.max())
+    assert np.all(err <= 1e-2)
+
+
+def test_mixed_loglike_and_grad_cfg2(cfg2):
+    ev, w, gev = cfg2
+    th = w["theta"]
+    t = _cuda(th)
+    lm = gev.loglike(t, precision="mixed").cpu().numpy()
+    lgm, gm = gev.loglike_grad(t, precision="mixed")
+    lgm, gm = lgm.cpu().numpy(), gm.cpu().numpy()
+    idx = np.random.default_rng(7).choice(len(th), 256, replace=False)
+    idx.sort()
+    want = L.loglike_rb(ev, th[idx])
+    err = np.abs(lm[idx] - want)
+    errg = np.abs(lgm[idx] - want)
+    say("cfg2 mixed lnL max abs err", err.max(), "grad-kernel lnL", errg.max())
+    assert np.all(err <= 1e-2) and np.all(errg <= 1e-2)
+    wl, wg = L.loglike_rb_grad(ev, th[idx[:48]])
+    gs, ws = gm[idx[:48]] * WIDTHS, wg * WIDTHS
+    rel = np.abs(gs - ws).max(axis=1) / np.abs(ws).max(axis=1)
+    say("cfg2 mixed grad max rel err (reported, not the FP64 bar)", rel.max())
+    assert np.all(rel <= 1e-3)

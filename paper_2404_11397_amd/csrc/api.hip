@@ -180,8 +180,6 @@ static int validate_desc(const rbl_event_desc* d) {
     if (d->n_det < 1 || d->n_det > kMaxDet) return fail(RBL_EINVAL, "rbl_event_create: n_det must be 1..3");
     if (d->waveform != RBL_TAYLORF2 && d->waveform != RBL_PHENOMD_NRTV2)
         return fail(RBL_EINVAL, "rbl_event_create: unknown waveform");
-    if (d->waveform == RBL_PHENOMD_NRTV2)
-        return fail(RBL_EUNSUPPORTED, "rbl_event_create: IMRPhenomD_NRTidalv2 is not available in this build");
     if (d->n_freq < 2) return fail(RBL_EINVAL, "rbl_event_create: n_freq must be >= 2");
     if (!(d->f_low > 0.0) || !std::isfinite(d->f_low)) return fail(RBL_EINVAL, "rbl_event_create: f_low must be > 0");
     if (!(d->delta_f > 0.0) || !std::isfinite(d->delta_f)) return fail(RBL_EINVAL, "rbl_event_create: delta_f must be > 0");
@@ -273,7 +271,7 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     RefConsts* d_ref = nullptr;
     if ((e = tmp.alloc((void**)&d_ref, sizeof(RefConsts))) != hipSuccess)
         return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (ref)"));
-    if ((e = launch_ref_setup(desc->theta_ref, ev->net, d_ref, s)) != hipSuccess)
+    if ((e = launch_ref_setup(desc->theta_ref, ev->net, desc->waveform, d_ref, s)) != hipSuccess)
         return cleanup(hip_fail(e, "rbl_event_create: reference setup"));
     if ((e = hipMemcpyAsync(&ev->ref, d_ref, sizeof(RefConsts), hipMemcpyDeviceToHost, s)) != hipSuccess)
         return cleanup(hip_fail(e, "rbl_event_create: copy reference"));
@@ -326,7 +324,8 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     if (ev->mem.alloc((void**)&ev->d_summary, sizeof(double) * nd * nb * 7) != hipSuccess)
         return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (summary)"));
     double* node_block = nullptr;
-    const int64_t node_doubles = np * (4 + 5 * nd) + 2 * kMaxDet + np * 2 * nd;  // FP64 tables, scales, FP32 tables
+    // FP64 tables, scales, FP32 tables (2 nd np floats), reference phase / amplitude (2 np), FP32 amplitude
+    const int64_t node_doubles = np * (4 + 5 * nd) + 2 * kMaxDet + np * 2 * nd + 2 * np + (np + 1) / 2;
     if (ev->mem.alloc((void**)&node_block, sizeof(double) * node_doubles) != hipSuccess)
         return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (node tables)"));
 
@@ -345,6 +344,7 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     sa.psd = d_psd;
     sa.partials = d_partials;
     sa.ref = ev->ref;
+    sa.ref_taper = (desc->flags & RBL_REF_TAPER) ? 1 : 0;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (g_prof.on) {
         t0 = g_prof.get();
@@ -390,8 +390,23 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     na.g_im32 = na.g_re32 + nd * np;
     na.mu32 = na.g_im32 + nd * np;
     na.nuL32 = na.mu32 + nd * np;
+    na.phi0 = na.scales + 2 * kMaxDet + np * 2 * nd;  // after the FP32 tables (4 nd np floats)
+    na.ia0 = na.phi0 + np;
+    na.ia0_32 = (float*)(na.ia0 + np);
+    na.ref = ev->ref;
+    na.ref_taper = (desc->flags & RBL_REF_TAPER) ? 1 : 0;
+    int32_t* d_bad = nullptr;
+    if (tmp.alloc((void**)&d_bad, sizeof(int32_t)) != hipSuccess)
+        return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (flag)"));
+    if ((e = hipMemsetAsync(d_bad, 0, sizeof(int32_t), s)) != hipSuccess)
+        return cleanup(hip_fail(e, "rbl_event_create: clear flag"));
+    na.bad_ref = d_bad;
     if ((e = launch_node_tables(na, s)) != hipSuccess) return cleanup(hip_fail(e, "rbl_event_create: node tables"));
+    int32_t bad = 0;
+    if ((e = hipMemcpyAsync(&bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return cleanup(hip_fail(e, "rbl_event_create: read flag"));
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup(hip_fail(e, "rbl_event_create: build"));
+    if (bad) return cleanup(fail(RBL_EREF, "rbl_event_create: reference amplitude not positive at a bin edge"));
     tmp.release();
 
     EventDev& dv = ev->dev;
@@ -417,6 +432,10 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     dv.mu32 = na.mu32;
     dv.nuL32 = na.nuL32;
     dv.scales = na.scales;
+    dv.waveform = desc->waveform;
+    dv.phi0 = na.phi0;
+    dv.ia0 = na.ia0;
+    dv.ia0_32 = na.ia0_32;
     ev->footprint = (int64_t)sizeof(double) * (nd * nb * 7 + node_doubles) +
                     ((desc->flags & RBL_KEEP_GRID) ? (int64_t)sizeof(double) * 3 * nd * n : 0);
     *out = ev;
@@ -470,6 +489,8 @@ extern "C" int rbl_loglike_grad(const rbl_event* ev, const double* theta_dev, in
     int rc = check_call("rbl_loglike_grad", ev, theta_dev, B, precision, lnl_dev, workspace);
     if (rc || B == 0) return rc;
     if (!grad_dev) return fail(RBL_EINVAL, "rbl_loglike_grad: null grad");
+    if (ev->waveform == RBL_PHENOMD_NRTV2)
+        return fail(RBL_EUNSUPPORTED, "rbl_loglike_grad: gradient of IMRPhenomD_NRTidalv2 events not available");
     hipStream_t s = (hipStream_t)hip_stream;
     double* rec = (double*)workspace;
     double* jac = (double*)((char*)workspace + align_up(B * kRecStride * (int64_t)sizeof(double)));
@@ -514,9 +535,7 @@ extern "C" int rbl_loglike_full(const rbl_event* ev, const double* theta_dev, in
 extern "C" int rbl_strain(int32_t waveform, int32_t n_det, const double* det_tensor, const double* det_vertex,
                           double gmst, double f_low, double delta_f, int64_t n_freq, const double* theta,
                           int32_t taper, double* out_dev, void* hip_stream) {
-    (void)taper;
     if (waveform != RBL_TAYLORF2 && waveform != RBL_PHENOMD_NRTV2) return fail(RBL_EINVAL, "rbl_strain: unknown waveform");
-    if (waveform == RBL_PHENOMD_NRTV2) return fail(RBL_EUNSUPPORTED, "rbl_strain: IMRPhenomD_NRTidalv2 not available in this build");
     if (n_det < 1 || n_det > kMaxDet) return fail(RBL_EINVAL, "rbl_strain: n_det must be 1..3");
     if (!det_tensor || !det_vertex || !theta || !out_dev) return fail(RBL_EINVAL, "rbl_strain: null pointer");
     if (!(f_low > 0.0) || !(delta_f > 0.0) || n_freq < 1) return fail(RBL_EINVAL, "rbl_strain: bad grid");
@@ -532,8 +551,8 @@ extern "C" int rbl_strain(int32_t waveform, int32_t n_det, const double* det_ten
     RefConsts* d_cst = nullptr;
     hipError_t e = hipMalloc((void**)&d_cst, sizeof(RefConsts));
     if (e != hipSuccess) return fail(RBL_ENOMEM, "rbl_strain: device allocation");
-    e = launch_ref_setup(theta, net, d_cst, s);
-    if (e == hipSuccess) e = launch_strain(d_cst, n_det, f_low, delta_f, n_freq, out_dev, s);
+    e = launch_ref_setup(theta, net, waveform, d_cst, s);
+    if (e == hipSuccess) e = launch_strain(d_cst, waveform, taper, n_det, f_low, delta_f, n_freq, out_dev, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(d_cst);
     if (e != hipSuccess) return hip_fail(e, "rbl_strain");

@@ -19,7 +19,7 @@ namespace rbl {
 // ---------------------------------------------------------------------------
 // Reference constants
 // ---------------------------------------------------------------------------
-__global__ void k_ref_setup(Theta13 th, Network net, RefConsts* out) {
+__global__ void k_ref_setup(Theta13 th, Network net, int32_t waveform, RefConsts* out) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     RefConsts r{};
     const double* t = th.v;
@@ -27,11 +27,18 @@ __global__ void k_ref_setup(Theta13 th, Network net, RefConsts* out) {
               t[4] >= 0.0 && t[5] >= 0.0;
     for (int i = 0; i < 13; ++i) ok = ok && isfinite(t[i]);
     r.status = ok ? 1 : 0;
+    r.waveform = waveform;
     Tf2Coeffs<double> c;
     tf2_coeffs<double>(t[0], t[1], t[2], t[3], t[4], t[5], c);
     for (int b = 0; b < kTf2Basis; ++b) r.c0[b] = c.c[b];
     r.c0_const = c.c_const;
     r.amp0 = c.amp;
+    if (waveform == kWfNrtv2) {
+        // the edge phase is taken absolutely: no constant phase in h0fac
+        nrt_params<double>(t[0], t[1], t[2], t[3], t[4], t[5], r.nrt);
+        r.c0_const = 0.0;
+        c.c_const = 0.0;
+    }
     r.mc0 = t[0];
     r.dl0 = t[6];
     r.tc0 = t[7];
@@ -59,14 +66,21 @@ __global__ void k_ref_setup(Theta13 th, Network net, RefConsts* out) {
 // ---------------------------------------------------------------------------
 template <class T>
 __device__ inline void chain_record(const T* th, const Network& net, const RefConsts& ref, T* rec /*[kRecUsed]*/) {
-    Tf2Coeffs<T> c;
-    tf2_coeffs<T>(th[0], th[1], th[2], th[3], th[4], th[5], c);
-    for (int b = 0; b < kTf2Basis; ++b) rec[kRecDc + b] = c.c[b] - ref.c0[b];
+    T dconst(0.0), amp;
+    if (ref.waveform == kWfNrtv2) {
+        for (int b = 0; b < kTf2Basis; ++b) rec[kRecDc + b] = T(0.0);
+        amp = tf2_amp<T>(th[0]);
+    } else {
+        Tf2Coeffs<T> c;
+        tf2_coeffs<T>(th[0], th[1], th[2], th[3], th[4], th[5], c);
+        for (int b = 0; b < kTf2Basis; ++b) rec[kRecDc + b] = c.c[b] - ref.c0[b];
+        dconst = c.c_const - ref.c0_const;
+        dconst = dconst - rint(val(dconst));  // whole revolutions removed (no derivative)
+        amp = c.amp;
+    }
     // common complex factor (dL0/dL)(amp/amp0) exp(2i(phic - phic0)) exp(-2 pi i dconst)
-    T dconst = c.c_const - ref.c0_const;
-    dconst = dconst - rint(val(dconst));  // whole revolutions removed (no derivative)
     const T ang = 2.0 * (th[8] - ref.phic0) - (2.0 * kPi) * dconst;
-    const T mag = (ref.dl0 / th[6]) * (c.amp / ref.amp0);
+    const T mag = (ref.dl0 / th[6]) * (amp / ref.amp0);
     T sa, ca;
     dsincos(ang, sa, ca);
     const Cx<T> common{mag * ca, mag * sa};
@@ -115,6 +129,12 @@ __global__ __launch_bounds__(64) void k_chain_setup(const double* __restrict__ t
     double r[kRecUsed];
     chain_record<double>(t, net, ref, r);
     for (int i = 1; i < kRecUsed; ++i) out[i] = r[i];
+    if (ref.waveform == kWfNrtv2) {
+        NrtParams<double> np;
+        nrt_params<double>(t[0], t[1], t[2], t[3], t[4], t[5], np);
+        const double* src = reinterpret_cast<const double*>(&np);
+        for (int i = 0; i < kNrtParams; ++i) out[kRecNrt + i] = src[i];
+    }
 }
 
 // Record and partial derivatives for the gradient.  Two kinds of blocks:
@@ -242,12 +262,18 @@ __global__ __launch_bounds__(256) void k_summary_items(SummaryArgs a) {
         const double x = cbrt(f);
         const double ix = 1.0 / x;
         const double lx = log(x);
-        double bas[kTf2Basis];
-        tf2_basis(x, ix, lx, bas);
         double phi = 0.0;
+        double amp = ref.amp0 * (ix * ix * ix) * sqrt(ix);  // f^(-7/6)
+        if (ref.waveform == kWfNrtv2) {
+            double a0;
+            nrt_node(ref.nrt, f, x, ix, lx, a.ref_taper != 0, phi, a0);
+            amp *= a0;
+        } else {
+            double bas[kTf2Basis];
+            tf2_basis(x, ix, lx, bas);
 #pragma unroll
-        for (int j = 0; j < kTf2Basis; ++j) phi = fma(ref.c0[j], bas[j], phi);
-        const double amp = ref.amp0 * (ix * ix * ix) * sqrt(ix);  // f^(-7/6)
+            for (int j = 0; j < kTf2Basis; ++j) phi = fma(ref.c0[j], bas[j], phi);
+        }
         const double df = f - fm;
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
@@ -319,6 +345,15 @@ __global__ void k_node_tables(NodeArgs a) {
     a.node_x[pos] = x;
     a.node_ix[pos] = ix;
     a.node_lx[pos] = lx;
+    if (a.ref.waveform == kWfNrtv2) {
+        double phi0 = 0.0, a0 = 1.0;
+        if (real_node) nrt_node(a.ref.nrt, f, x, ix, lx, a.ref_taper != 0, phi0, a0);
+        const bool ok = a0 > 0.0 && isfinite(a0) && isfinite(phi0);
+        if (!ok) *a.bad_ref = 1;
+        a.phi0[pos] = phi0;
+        a.ia0[pos] = ok ? 1.0 / a0 : 0.0;
+        a.ia0_32[pos] = ok ? (float)(1.0 / a0) : 0.0f;
+    }
     for (int d = 0; d < a.n_det; ++d) {
         double gre = 0.0, gim = 0.0, mu = 0.0, nul = 0.0, nur = 0.0;
         if (real_node) {
@@ -387,6 +422,12 @@ __global__ __launch_bounds__(256) void k_loglike_full(FullArgs a) {
         return;
     }
     const RefConsts& ref = a.ref;
+    const bool nrt = ref.waveform == kWfNrtv2;
+    NrtParams<double> np;
+    if (nrt) {
+        double* dst = reinterpret_cast<double*>(&np);
+        for (int i = 0; i < kNrtParams; ++i) dst[i] = rec[kRecNrt + i];
+    }
     double c[kTf2Basis];
     for (int k = 0; k < kTf2Basis; ++k) c[k] = ref.c0[k] + rec[kRecDc + k];
     double fre[kMaxDet], fim[kMaxDet], tau[kMaxDet];
@@ -401,11 +442,17 @@ __global__ __launch_bounds__(256) void k_loglike_full(FullArgs a) {
     for (int64_t k = threadIdx.x; k < a.n_freq; k += blockDim.x) {
         const double f = a.f_low + (double)k * a.delta_f;
         const double x = cbrt(f), ix = 1.0 / x, lx = log(x);
-        double bas[kTf2Basis];
-        tf2_basis(x, ix, lx, bas);
         double ph = 0.0;
-        for (int j = 0; j < kTf2Basis; ++j) ph = fma(c[j], bas[j], ph);
-        const double am = (ix * ix * ix) * sqrt(ix);
+        double am = (ix * ix * ix) * sqrt(ix);
+        if (nrt) {
+            double af;
+            nrt_node(np, f, x, ix, lx, true, ph, af);
+            am *= af;
+        } else {
+            double bas[kTf2Basis];
+            tf2_basis(x, ix, lx, bas);
+            for (int j = 0; j < kTf2Basis; ++j) ph = fma(c[j], bas[j], ph);
+        }
         for (int d = 0; d < a.n_det; ++d) {
             double cu, su;
             expm2pi_rev(fma(f, tau[d], ph), cu, su);
@@ -426,18 +473,25 @@ __global__ __launch_bounds__(256) void k_loglike_full(FullArgs a) {
 // Projected strain on a grid for one parameter vector (its constants come from
 // k_ref_setup run on that vector).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_strain(const RefConsts* __restrict__ cst, int32_t n_det, double f_low,
-                                                double delta_f, int64_t n_freq, double* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_strain(const RefConsts* __restrict__ cst, int32_t taper, int32_t n_det,
+                                                double f_low, double delta_f, int64_t n_freq,
+                                                double* __restrict__ out) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_freq) return;
     const RefConsts& r = *cst;
     const double f = f_low + (double)k * delta_f;
     const double x = cbrt(f), ix = 1.0 / x, lx = log(x);
-    double bas[kTf2Basis];
-    tf2_basis(x, ix, lx, bas);
     double ph = 0.0;
-    for (int j = 0; j < kTf2Basis; ++j) ph = fma(r.c0[j], bas[j], ph);
-    const double am = r.amp0 * (ix * ix * ix) * sqrt(ix);
+    double am = r.amp0 * (ix * ix * ix) * sqrt(ix);
+    if (r.waveform == kWfNrtv2) {
+        double af;
+        nrt_node(r.nrt, f, x, ix, lx, taper != 0, ph, af);
+        am *= af;
+    } else {
+        double bas[kTf2Basis];
+        tf2_basis(x, ix, lx, bas);
+        for (int j = 0; j < kTf2Basis; ++j) ph = fma(r.c0[j], bas[j], ph);
+    }
     for (int d = 0; d < n_det; ++d) {
         double cu, su;
         expm2pi_rev(fma(f, r.tau0[d], ph), cu, su);
@@ -450,10 +504,11 @@ __global__ __launch_bounds__(256) void k_strain(const RefConsts* __restrict__ cs
 // ---------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------
-hipError_t launch_ref_setup(const double* theta, const Network& net, RefConsts* out_dev, hipStream_t s) {
+hipError_t launch_ref_setup(const double* theta, const Network& net, int32_t waveform, RefConsts* out_dev,
+                            hipStream_t s) {
     Theta13 th;
     for (int i = 0; i < 13; ++i) th.v[i] = theta[i];
-    hipLaunchKernelGGL(k_ref_setup, dim3(1), dim3(64), 0, s, th, net, out_dev);
+    hipLaunchKernelGGL(k_ref_setup, dim3(1), dim3(64), 0, s, th, net, waveform, out_dev);
     return hipGetLastError();
 }
 
@@ -494,10 +549,11 @@ hipError_t launch_loglike_full(const FullArgs& a, int64_t B, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_strain(const RefConsts* cst_dev, int32_t n_det, double f_low, double delta_f, int64_t n_freq,
-                         double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_strain, dim3((unsigned)((n_freq + 255) / 256)), dim3(256), 0, s, cst_dev, n_det, f_low,
-                       delta_f, n_freq, out);
+hipError_t launch_strain(const RefConsts* cst_dev, int32_t waveform, int32_t taper, int32_t n_det, double f_low,
+                         double delta_f, int64_t n_freq, double* out, hipStream_t s) {
+    (void)waveform;
+    hipLaunchKernelGGL(k_strain, dim3((unsigned)((n_freq + 255) / 256)), dim3(256), 0, s, cst_dev, taper, n_det,
+                       f_low, delta_f, n_freq, out);
     return hipGetLastError();
 }
 

@@ -38,24 +38,51 @@ template <int ND>
 struct ChainVals {
     double dc[kTf2Basis];
     double kre[ND], kim[ND], dtau[ND];
+    NrtParams<double> np;  // IMRPhenomD_NRTidalv2 events only
 };
 
+// The amplitude ratio of an IMRPhenomD_NRTidalv2 chain to the reference stays below
+// about 1.1 in band; the bound takes it as 2.
 template <int ND>
 __device__ inline bool use_mixed(const EventDev& ev, const ChainVals<ND>& cv) {
+    const double amax = ev.waveform == kWfNrtv2 ? 2.0 : 1.0;
     double bound = 0.0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
-        const double k2 = cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d];
+        const double k2 = (cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d]) * amax * amax;
         bound += sqrt(k2) * ev.scales[2 * d] + k2 * ev.scales[2 * d + 1];
     }
     return bound <= kMixedScaleMax;
+}
+
+// Edge phase (revolutions, relative to the reference) and amplitude ratio.
+//   TaylorF2:  sum_b dc_b B_b(x), ratio 1 (the Mc^(5/6) factor is in K);
+//   IMRPhenomD_NRTidalv2:  Phi(f; theta) - Phi0_j, ratio a(f; theta) / a0_j.
+template <int ND, int WF>
+__device__ inline void edge_phase(const EventDev& ev, const ChainVals<ND>& cv, int pos, double f, double& dph,
+                                  double& ar) {
+    const double x = ev.node_x[pos], ix = ev.node_ix[pos], lx = ev.node_lx[pos];
+    if (WF == kWfNrtv2) {
+        double ph, a;
+        nrt_node(cv.np, f, x, ix, lx, true, ph, a);
+        dph = ph - ev.phi0[pos];
+        ar = a * ev.ia0[pos];
+    } else {
+        double bas[kTf2Basis];
+        tf2_basis(x, ix, lx, bas);
+        double ph = 0.0;
+#pragma unroll
+        for (int b = 0; b < kTf2Basis; ++b) ph = fma(cv.dc[b], bas[b], ph);
+        dph = ph;
+        ar = 1.0;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Forward walk: this lane's share of lnL.  The cross term of the bin left of a
 // lane's first edge needs the last edge of lane - 1: exchanged once at the end.
 // ---------------------------------------------------------------------------
-template <int ND, class R>
+template <int ND, class R, int WF>
 __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, int lane) {
     const EdgeTab<R> T = edge_tab(ev, R(0));
     const int npad = ev.n_nodes_pad;
@@ -70,15 +97,15 @@ __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, i
     for (int k = 0; k < ev.L; ++k) {
         const int pos = k * 64 + lane;
         const double f = ev.node_f[pos];
-        double bas[kTf2Basis];
-        tf2_basis(ev.node_x[pos], ev.node_ix[pos], ev.node_lx[pos], bas);
-        double ph = 0.0;
-#pragma unroll
-        for (int b = 0; b < kTf2Basis; ++b) ph = fma(cv.dc[b], bas[b], ph);
+        double ph, ard;
+        edge_phase<ND, WF>(ev, cv, pos, f, ph, ard);
+        const R ar = (R)ard;
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             R cu, su;
             unit_phasor(fma(f, cv.dtau[d], ph), cu, su);
+            cu *= ar;
+            su *= ar;
             const R rre = kre[d] * cu - kim[d] * su;
             const R rim = kre[d] * su + kim[d] * cu;
             const int o = d * npad + pos;
@@ -102,7 +129,7 @@ __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, i
     return acc;
 }
 
-template <int ND, bool MIXED>
+template <int ND, bool MIXED, int WF>
 __global__ __launch_bounds__(256) void k_loglike_fwd(EventDev ev, const double* __restrict__ recs, int64_t B,
                                                      double* __restrict__ lnl) {
     const int lane = threadIdx.x & 63;
@@ -123,11 +150,16 @@ __global__ __launch_bounds__(256) void k_loglike_fwd(EventDev ev, const double* 
         cv.kim[d] = rec[kRecK + 2 * d + 1];
         cv.dtau[d] = rec[kRecTau + d];
     }
+    if (WF == kWfNrtv2) {
+        double* dst = reinterpret_cast<double*>(&cv.np);
+#pragma unroll
+        for (int i = 0; i < kNrtParams; ++i) dst[i] = rec[kRecNrt + i];
+    }
     double acc;
     if (MIXED && use_mixed<ND>(ev, cv))
-        acc = fwd_walk<ND, float>(ev, cv, lane);
+        acc = fwd_walk<ND, float, WF>(ev, cv, lane);
     else
-        acc = fwd_walk<ND, double>(ev, cv, lane);
+        acc = fwd_walk<ND, double, WF>(ev, cv, lane);
     acc = wave_sum(acc);
     if (lane == 0) lnl[chain] = acc;
 }
@@ -348,10 +380,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 template <int ND>
 static void fwd_nd(const EventDev& ev, const double* rec, int64_t B, int mixed, double* lnl, hipStream_t s) {
     const unsigned grid = (unsigned)((B + 3) / 4);
-    if (mixed)
-        hipLaunchKernelGGL((k_loglike_fwd<ND, true>), dim3(grid), dim3(256), 0, s, ev, rec, B, lnl);
-    else
-        hipLaunchKernelGGL((k_loglike_fwd<ND, false>), dim3(grid), dim3(256), 0, s, ev, rec, B, lnl);
+    if (ev.waveform == kWfNrtv2) {
+        if (mixed)
+            hipLaunchKernelGGL((k_loglike_fwd<ND, true, kWfNrtv2>), dim3(grid), dim3(256), 0, s, ev, rec, B, lnl);
+        else
+            hipLaunchKernelGGL((k_loglike_fwd<ND, false, kWfNrtv2>), dim3(grid), dim3(256), 0, s, ev, rec, B, lnl);
+    } else {
+        if (mixed)
+            hipLaunchKernelGGL((k_loglike_fwd<ND, true, kWfTaylorF2>), dim3(grid), dim3(256), 0, s, ev, rec, B, lnl);
+        else
+            hipLaunchKernelGGL((k_loglike_fwd<ND, false, kWfTaylorF2>), dim3(grid), dim3(256), 0, s, ev, rec, B, lnl);
+    }
 }
 
 hipError_t launch_loglike(const EventDev& ev, const double* rec, int64_t B, int mixed, double* lnl, hipStream_t s) {

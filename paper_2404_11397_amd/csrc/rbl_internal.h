@@ -3,11 +3,13 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
-#include "rbl_physics.h"
+#include "rbl_nrtv2.h"
 
 namespace rbl {
 
 constexpr int kMaxDet = 3;
+constexpr int kWfTaylorF2 = 0;  // RBL_TAYLORF2
+constexpr int kWfNrtv2 = 1;     // RBL_PHENOMD_NRTV2
 constexpr int kNodeTile = 64;  // node tables are padded to a multiple of the wavefront
 
 // Per-chain record produced by the setup kernels (FP64, 32 doubles, 256 B).
@@ -19,7 +21,9 @@ constexpr int kNodeTile = 64;  // node tables are padded to a multiple of the wa
 //   [17..19]   dtau_d = (tc + dt_d) - (tc0 + dt_d0)  [s]
 //   [20..21]   G (re, im)                 (gradient setup only)
 //   [22]       dL                         (gradient setup only)
-constexpr int kRecStride = 32;
+//   [24..51]   NrtParams<double> of the chain (IMRPhenomD_NRTidalv2 events; dc and the
+//              constant phase are then unused: the edge phase is taken absolutely)
+constexpr int kRecStride = 64;
 constexpr int kRecStatus = 0;
 constexpr int kRecDc = 1;
 constexpr int kRecK = 11;
@@ -27,6 +31,7 @@ constexpr int kRecTau = 17;
 constexpr int kRecG = 20;
 constexpr int kRecDl = 22;
 constexpr int kRecUsed = 20;                 // entries 1..19 are used by the likelihood kernels
+constexpr int kRecNrt = 24;
 
 // Partial derivatives stored per chain for the gradient (FP64, 112 doubles):
 //   [0, 72)    d(dc_b, dc_const, ln amp)/d(Mc, q, chi1, chi2, Lambda1, Lambda2), [12][6]
@@ -46,6 +51,8 @@ struct RefConsts {
     double tau0[kMaxDet];                          // tc0 + dt_d0
     double h0fac_re[kMaxDet], h0fac_im[kMaxDet];   // (C_d0/dL0) exp(2i phic0) exp(-2 pi i c0_const)
     int32_t status;                                 // 1 if theta0 is valid
+    int32_t waveform;                               // RBL_TAYLORF2 or RBL_PHENOMD_NRTV2
+    NrtParams<double> nrt;                          // theta0 coefficients (IMRPhenomD_NRTidalv2; c0_const = 0)
 };
 
 // Detector network description passed by value to kernels.
@@ -65,6 +72,7 @@ struct Network {
 // first edge of a lane needs a neighbour from another lane).
 struct EventDev {
     int32_t n_det, n_bins, n_nodes, n_nodes_pad, L;
+    int32_t waveform;
     int64_t n_freq;
     double f_low, delta_f;
     // node tables, each [n_nodes_pad] (padding: f = 0, x = ix = 1, lx = 0)
@@ -83,6 +91,10 @@ struct EventDev {
     const float* g_im32;
     const float* mu32;
     const float* nuL32;
+    // IMRPhenomD_NRTidalv2 events: reference phase [rev] and inverse amplitude factor per edge
+    const double* phi0;
+    const double* ia0;
+    const float* ia0_32;
     // per detector: Gs_d = sum_j |gamma_dj|, Hs_d = sum_j (|mu_dj| + |nuL_dj|)  [2 * kMaxDet]
     // (a chain's binned-sum magnitude is at most sum_d |K_d| Gs_d + |K_d|^2 Hs_d)
     const double* scales;

@@ -21,10 +21,15 @@ struct SummaryArgs {
     const double* psd;   // [n_det][n_freq]
     double* partials;    // [n_items][n_det][7]
     RefConsts ref;
+    int32_t ref_taper;
 };
 
 struct NodeArgs {
-    int32_t n_nodes, n_nodes_pad, L, n_det, keep_b2;
+    int32_t n_nodes, n_nodes_pad, L, n_det, keep_b2, ref_taper;
+    RefConsts ref;
+    double *phi0, *ia0;
+    float* ia0_32;
+    int32_t* bad_ref;  // set to 1 if the reference amplitude is not positive and finite at an edge
     const int64_t* edges;
     double f_low, delta_f;
     const double* summary;  // [n_det][n_bins][7]
@@ -45,16 +50,17 @@ struct FullArgs {
     double* lnl;
 };
 
-hipError_t launch_ref_setup(const double* theta_host, const Network& net, RefConsts* out_dev, hipStream_t s);
+hipError_t launch_ref_setup(const double* theta_host, const Network& net, int32_t waveform, RefConsts* out_dev,
+                            hipStream_t s);
 hipError_t launch_chain_setup(const double* theta, int64_t B, const Network& net, const RefConsts& ref,
-                              double* rec, double* jac, hipStream_t s);
+                              double* rec, double* jac, hipStream_t s);   // jac requires a TaylorF2 event
 hipError_t launch_summary(const SummaryArgs& a, const int64_t* bin_first_item, double* summary, hipStream_t s);
 hipError_t launch_node_tables(const NodeArgs& a, hipStream_t s);
 hipError_t launch_loglike(const EventDev& ev, const double* rec, int64_t B, int mixed, double* lnl, hipStream_t s);
 hipError_t launch_loglike_grad(const EventDev& ev, const double* rec, const double* jac, int64_t B, int mixed,
                                double* lnl, double* grad, hipStream_t s);
 hipError_t launch_loglike_full(const FullArgs& a, int64_t B, hipStream_t s);
-hipError_t launch_strain(const RefConsts* cst_dev, int32_t n_det, double f_low, double delta_f, int64_t n_freq,
-                         double* out, hipStream_t s);
+hipError_t launch_strain(const RefConsts* cst_dev, int32_t waveform, int32_t taper, int32_t n_det, double f_low,
+                         double delta_f, int64_t n_freq, double* out, hipStream_t s);
 
 }  // namespace rbl

@@ -37,78 +37,102 @@ struct Tf2Coeffs {
     T amp;           // sqrt(5/24) pi^(-2/3) (Mc Tsun)^(5/6) c / Mpc  (times f^(-7/6) -> strain/Hz at 1 Mpc)
 };
 
+// Post-Newtonian ingredients of the TaylorF2 phase: the bracket coefficients p_k of
+// v^k (k = 0, 2..7) with the log coefficients of k = 5, 6, and the tidal k = 10, 12.
 template <class T>
-__host__ __device__ inline void tf2_coeffs(const T& mc, const T& q, const T& chi1, const T& chi2,
-                                           const T& lam1, const T& lam2, Tf2Coeffs<T>& out) {
+struct Tf2Pn {
+    T eta, x1, x2, mtot;     // symmetric mass ratio, mass fractions, total mass [Msun]
+    T p[8];                  // p_0 .. p_7 (p_1 = 0)
+    T l5;                    // log coefficient of k = 5 (l6 is a constant)
+    T p10, p12;              // tidal
+};
+constexpr double kTf2L6 = -6848.0 / 21.0;
+
+template <class T>
+__host__ __device__ inline void tf2_pn(const T& mc, const T& q, const T& chi1, const T& chi2, const T& lam1,
+                                       const T& lam2, Tf2Pn<T>& o) {
     // Masses: eta = q/(1+q)^2, M = Mc eta^(-3/5), X1 = 1/(1+q), X2 = q/(1+q).
     const T opq = 1.0 + q;
     const T x1 = 1.0 / opq;
     const T x2 = q * x1;
     const T eta = x1 * x2;
-    const T mtot = mc * dexp(-0.6 * dlog(eta));
+    o.eta = eta;
+    o.x1 = x1;
+    o.x2 = x2;
+    o.mtot = mc * dexp(-0.6 * dlog(eta));
     const T dm = x1 - x2;  // signed (m1 - m2)/M
     const T cs = 0.5 * (chi1 + chi2);
     const T ca = 0.5 * (chi1 - chi2);
     const T e2 = eta * eta;
     const T e3 = e2 * eta;
     const double pi2 = kPi * kPi;
-
-    // Point-particle, spin-orbit and spin-spin coefficients of the bracket.
-    const T p2 = 3715.0 / 756.0 + (55.0 / 9.0) * eta;
-    const T p3 = -16.0 * kPi + (113.0 / 3.0) * dm * ca + (113.0 / 3.0 - (76.0 / 3.0) * eta) * cs;
-    const T p4 = 15293365.0 / 508032.0 + (27145.0 / 504.0) * eta + (3085.0 / 72.0) * e2
-               + (-405.0 / 8.0 + 200.0 * eta) * ca * ca - (405.0 / 4.0) * dm * ca * cs
-               + (-405.0 / 8.0 + 2.5 * eta) * cs * cs;
+    o.p[0] = T(1.0);
+    o.p[1] = T(0.0);
+    o.p[2] = 3715.0 / 756.0 + (55.0 / 9.0) * eta;
+    o.p[3] = -16.0 * kPi + (113.0 / 3.0) * dm * ca + (113.0 / 3.0 - (76.0 / 3.0) * eta) * cs;
+    o.p[4] = 15293365.0 / 508032.0 + (27145.0 / 504.0) * eta + (3085.0 / 72.0) * e2
+           + (-405.0 / 8.0 + 200.0 * eta) * ca * ca - (405.0 / 4.0) * dm * ca * cs
+           + (-405.0 / 8.0 + 2.5 * eta) * cs * cs;
     // 2.5PN: (1 + 3 ln(v / v_lso)) g5, v_lso = 6^(-1/2)
     const T g5 = kPi * (38645.0 / 756.0 - (65.0 / 9.0) * eta)
                - ((732985.0 / 2268.0 - (24260.0 / 81.0) * eta - (340.0 / 9.0) * e2) * cs
                   + (732985.0 / 2268.0 + (140.0 / 9.0) * eta) * dm * ca);
     const double ln_vlso = -0.5 * log(6.0);
-    const T p5 = g5 * (1.0 - 3.0 * ln_vlso);
-    const T l5 = 3.0 * g5;
-    const T p6 = 11583231236531.0 / 4694215680.0 - (640.0 / 3.0) * pi2
-               - (6848.0 / 21.0) * kEulerGamma - (6848.0 / 21.0) * log(4.0)
-               + (-15737765635.0 / 3048192.0 + (2255.0 / 12.0) * pi2) * eta
-               + (76055.0 / 1728.0) * e2 - (127825.0 / 1296.0) * e3
-               + kPi * ((2270.0 / 3.0) * dm * ca + (2270.0 / 3.0 - 520.0 * eta) * cs)
-               + (75515.0 / 144.0 - (8225.0 / 18.0) * eta) * dm * ca * cs
-               + (75515.0 / 288.0 - (263245.0 / 252.0) * eta - 480.0 * e2) * ca * ca
-               + (75515.0 / 288.0 - (232415.0 / 504.0) * eta + (1255.0 / 9.0) * e2) * cs * cs;
-    const double l6 = -6848.0 / 21.0;
-    const T p7 = kPi * (77096675.0 / 254016.0 + (378515.0 / 1512.0) * eta - (74045.0 / 756.0) * e2)
-               + (-25150083775.0 / 3048192.0 + (10566655595.0 / 762048.0) * eta
-                  - (1042165.0 / 3024.0) * e2 + (5345.0 / 36.0) * e3) * cs
-               + (-25150083775.0 / 3048192.0 + (26804935.0 / 6048.0) * eta
-                  - (1985.0 / 48.0) * e2) * dm * ca;
+    o.p[5] = g5 * (1.0 - 3.0 * ln_vlso);
+    o.l5 = 3.0 * g5;
+    o.p[6] = 11583231236531.0 / 4694215680.0 - (640.0 / 3.0) * pi2
+           - (6848.0 / 21.0) * kEulerGamma - (6848.0 / 21.0) * log(4.0)
+           + (-15737765635.0 / 3048192.0 + (2255.0 / 12.0) * pi2) * eta
+           + (76055.0 / 1728.0) * e2 - (127825.0 / 1296.0) * e3
+           + kPi * ((2270.0 / 3.0) * dm * ca + (2270.0 / 3.0 - 520.0 * eta) * cs)
+           + (75515.0 / 144.0 - (8225.0 / 18.0) * eta) * dm * ca * cs
+           + (75515.0 / 288.0 - (263245.0 / 252.0) * eta - 480.0 * e2) * ca * ca
+           + (75515.0 / 288.0 - (232415.0 / 504.0) * eta + (1255.0 / 9.0) * e2) * cs * cs;
+    o.p[7] = kPi * (77096675.0 / 254016.0 + (378515.0 / 1512.0) * eta - (74045.0 / 756.0) * e2)
+           + (-25150083775.0 / 3048192.0 + (10566655595.0 / 762048.0) * eta
+              - (1042165.0 / 3024.0) * e2 + (5345.0 / 36.0) * e3) * cs
+           + (-25150083775.0 / 3048192.0 + (26804935.0 / 6048.0) * eta
+              - (1985.0 / 48.0) * e2) * dm * ca;
     // Tidal, each body A with companion B (Vines-Flanagan-Hinderer 5PN + 6PN).
     const T x1_4 = (x1 * x1) * (x1 * x1);
     const T x2_4 = (x2 * x2) * (x2 * x2);
-    const T p10 = -24.0 * ((1.0 + 11.0 * x2) * x1_4 * lam1 + (1.0 + 11.0 * x1) * x2_4 * lam2);
-    const T p12 = (-5.0 / 28.0) *
-                  ((3179.0 - 919.0 * x1 - 2286.0 * x1 * x1 + 260.0 * x1 * x1 * x1) * x1_4 * lam1 +
-                   (3179.0 - 919.0 * x2 - 2286.0 * x2 * x2 + 260.0 * x2 * x2 * x2) * x2_4 * lam2);
+    o.p10 = -24.0 * ((1.0 + 11.0 * x2) * x1_4 * lam1 + (1.0 + 11.0 * x1) * x2_4 * lam2);
+    o.p12 = (-5.0 / 28.0) *
+            ((3179.0 - 919.0 * x1 - 2286.0 * x1 * x1 + 260.0 * x1 * x1 * x1) * x1_4 * lam1 +
+             (3179.0 - 919.0 * x2 - 2286.0 * x2 * x2 + 260.0 * x2 * x2 * x2) * x2_4 * lam2);
+}
 
+template <class T>
+__host__ __device__ inline T tf2_amp(const T& mc) {
+    // sqrt(5/24) pi^(-2/3) (Mc Tsun)^(5/6) c/Mpc
+    return dexp((5.0 / 6.0) * dlog(mc * kTsun)) * (sqrt(5.0 / 24.0) * pow(kPi, -2.0 / 3.0) * (kC / kMpc));
+}
+
+template <class T>
+__host__ __device__ inline void tf2_coeffs(const T& mc, const T& q, const T& chi1, const T& chi2,
+                                           const T& lam1, const T& lam2, Tf2Coeffs<T>& out) {
+    Tf2Pn<T> pn;
+    tf2_pn<T>(mc, q, chi1, chi2, lam1, lam2, pn);
     // v = s x: fold powers of s into the coefficients; divide by 2 pi for revolutions.
-    const T s = dcbrt(kPi * kTsun * mtot);
+    const T s = dcbrt(kPi * kTsun * pn.mtot);
     const T ls = dlog(s);
     const T s2 = s * s;
     const T s3 = s2 * s;
     const T s5 = s3 * s2;
     const T s7 = s5 * s2;
-    const T P = (3.0 / (128.0 * 2.0 * kPi)) / eta;
-    out.c[0] = P / s5;                  // x^-5   (k = 0)
-    out.c[1] = P * p2 / s3;             // x^-3   (k = 2)
-    out.c[2] = P * p3 / s2;             // x^-2   (k = 3)
-    out.c[3] = P * p4 / s;              // x^-1   (k = 4)
-    out.c[4] = P * l5;                  // ln x   (k = 5, log)
-    out.c[5] = P * (p6 + l6 * ls) * s;  // x      (k = 6)
-    out.c[6] = P * (l6 * s);            // x ln x (k = 6, log)
-    out.c[7] = P * p7 * s2;             // x^2    (k = 7)
-    out.c[8] = P * p10 * s5;            // x^5    (tidal 5PN)
-    out.c[9] = P * p12 * s7;            // x^7    (tidal 6PN)
-    out.c_const = P * (p5 + l5 * ls) - 0.125;
-    // amplitude: sqrt(5/24) pi^(-2/3) (Mc Tsun)^(5/6) c/Mpc
-    out.amp = dexp((5.0 / 6.0) * dlog(mc * kTsun)) * (sqrt(5.0 / 24.0) * pow(kPi, -2.0 / 3.0) * (kC / kMpc));
+    const T P = (3.0 / (128.0 * 2.0 * kPi)) / pn.eta;
+    out.c[0] = P / s5;                         // x^-5   (k = 0)
+    out.c[1] = P * pn.p[2] / s3;               // x^-3   (k = 2)
+    out.c[2] = P * pn.p[3] / s2;               // x^-2   (k = 3)
+    out.c[3] = P * pn.p[4] / s;                // x^-1   (k = 4)
+    out.c[4] = P * pn.l5;                      // ln x   (k = 5, log)
+    out.c[5] = P * (pn.p[6] + kTf2L6 * ls) * s;  // x    (k = 6)
+    out.c[6] = P * (kTf2L6 * s);               // x ln x (k = 6, log)
+    out.c[7] = P * pn.p[7] * s2;               // x^2    (k = 7)
+    out.c[8] = P * pn.p10 * s5;                // x^5    (tidal 5PN)
+    out.c[9] = P * pn.p12 * s7;                // x^7    (tidal 6PN)
+    out.c_const = P * (pn.p[5] + pn.l5 * ls) - 0.125;
+    out.amp = tf2_amp<T>(mc);
 }
 
 // Basis values at x = f^(1/3) given x, 1/x and ln x.

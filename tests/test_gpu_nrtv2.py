@@ -1,0 +1,148 @@
+"""GPU parity for IMRPhenomD_NRTidalv2 events: strain, summary data and the binned
+lnL (FP64 and mixed) of the library against the FP64 oracle on the same seeded
+inputs.  Same tolerances as the TaylorF2 tests."""
+import numpy as np
+import pytest
+
+from oracle import likelihood as L
+from oracle import phenomd_nrtv2 as P
+from oracle import taylorf2 as T
+from oracle import waveform as W
+from oracle.constants import MTSUN_S
+
+from _events import near_draws, small_event
+from gpu_common import gpu_event, oracle_event, rb_condition_scale, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def _cuda(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("taper", [True, False])
+def test_strain_nrtv2_matches_oracle(taper):
+    from paper_2404_11397_amd import strain
+    ev = small_event(approximant="phenomd_nrtv2", duration=4.0, f_high=2048.0)
+    th = near_draws(ev.theta_ref, 3, 5)
+    for t in th:
+        h_gpu = strain("phenomd_nrtv2", ev.tensors, ev.vertices, ev.gmst, ev.f[0], ev.delta_f, len(ev.f), t,
+                       taper=taper).cpu().numpy()
+        h_ref = np.stack([x[0] for x in W.strain(ev.f, t, ev.tensors, ev.vertices, ev.gmst, "phenomd_nrtv2",
+                                                 taper)])
+        err = np.abs(h_gpu - h_ref).max() / np.abs(h_ref).max()
+        say("nrtv2 strain taper", taper, "rel err", err)
+        assert err < 1e-10
+
+
+@pytest.fixture(scope="module")
+def cfg3():
+    say("[cfg3] building oracle event (519169 points x 3 detectors)")
+    ev, w = oracle_event("cfg3")
+    say("[cfg3] building GPU event")
+    gev = gpu_event(ev)
+    return ev, w, gev
+
+
+def test_summary_matches_oracle_cfg3(cfg3):
+    ev, _, gev = cfg3
+    s = gev.summary()
+    ref = ev.summary
+    fields = [ref["A0"].real, ref["A0"].imag, ref["A1"].real, ref["A1"].imag, ref["B0"], ref["B1"]]
+    for j, want in enumerate(fields):
+        err = np.abs(s[:, :, j] - want).max() / np.abs(want).max()
+        say("cfg3 summary field", j, "rel err", err)
+        assert err < 1e-10
+
+
+def test_loglike_parity_cfg3_sampled(cfg3):
+    """Full batch (16384 prior draws) in the launch shape the benchmark uses; the
+    oracle checks a seeded sample, FP64 and mixed."""
+    ev, w, gev = cfg3
+    th = w["theta"]
+    t = _cuda(th)
+    lnl = gev.loglike(t).cpu().numpy()
+    lm = gev.loglike(t, precision="mixed").cpu().numpy()
+    idx = np.random.default_rng(43).choice(len(th), 256, replace=False)
+    idx.sort()
+    want = L.loglike_rb(ev, th[idx])
+    scale = np.maximum(np.abs(want), rb_condition_scale(ev, th[idx]))
+    err = np.abs(lnl[idx] - want) / scale
+    say("cfg3 FP64 lnL max scaled err", err.max())
+    assert np.all(err <= 1e-8)
+    em = np.abs(lm[idx] - want)
+    say("cfg3 mixed lnL max abs err", em.max())
+    assert np.all(em <= 1e-2)
+
+
+def test_loglike_parity_cfg3_near_reference(cfg3):
+    """Chains near the posterior (where lnL is large), FP64 and mixed."""
+    ev, _, gev = cfg3
+    th = near_draws(ev.theta_ref, 256, 44, scale=0.3)
+    t = _cuda(th)
+    lnl = gev.loglike(t).cpu().numpy()
+    lm = gev.loglike(t, precision="mixed").cpu().numpy()
+    want = L.loglike_rb(ev, th)
+    scale = np.maximum(np.abs(want), rb_condition_scale(ev, th))
+    err = np.abs(lnl - want) / scale
+    say("cfg3 near-theta0 FP64 scaled err", err.max(), "mixed abs err", np.abs(lm - want).max())
+    assert np.all(err <= 1e-8)
+    assert np.all(np.abs(lm - want) <= 1e-2)
+
+
+def test_label_swap_nrtv2_on_gpu(cfg3):
+    ev, w, gev = cfg3
+    th = near_draws(ev.theta_ref, 32, 45)
+    sw = th.copy()
+    sw[:, 1] = 1 / th[:, 1]
+    sw[:, [2, 3]] = th[:, [3, 2]]
+    sw[:, [4, 5]] = th[:, [5, 4]]
+    a = gev.loglike(_cuda(th)).cpu().numpy()
+    b = gev.loglike(_cuda(sw)).cpu().numpy()
+    scale = np.maximum(np.abs(a), rb_condition_scale(ev, th))
+    assert np.all(np.abs(a - b) <= 1e-9 * scale)
+
+
+def _tapered_reference_event():
+    """Grid ending inside the taper, so a tapered reference stays non-zero."""
+    th = small_event(approximant="phenomd_nrtv2", noise=False, duration=1.0, f_high=100.0).theta_ref
+    mtot, _, x1, x2 = T.masses(th[0], th[1])
+    fm = P.merger_frequency(x1, x2, P.kappa_tidal(x1, x2, th[4], th[5])) / (mtot * MTSUN_S)
+    ev = small_event(approximant="phenomd_nrtv2", duration=4.0, f_high=float(np.floor(1.15 * fm)), n_bins=60,
+                     ref_taper=True)
+    L.prepare(ev)
+    return ev
+
+
+def test_reference_exactness_nrtv2_tapered_reference():
+    """Reference tapered like the samples: at theta0 binned == full, on GPU and oracle."""
+    ev = _tapered_reference_event()
+    gev = gpu_event(ev, keep_grid=True)
+    th0 = ev.theta_ref[None, :]
+    rb = gev.loglike(_cuda(th0)).cpu().numpy()[0]
+    full = gev.loglike_full(_cuda(th0)).cpu().numpy()[0]
+    say("nrtv2 theta0: rb", rb, "full", full)
+    assert rb == pytest.approx(full, rel=1e-11)
+    assert rb == pytest.approx(L.loglike_full(ev, th0)[0], rel=1e-10)
+    th = near_draws(ev.theta_ref, 64, 46)
+    got = gev.loglike(_cuda(th)).cpu().numpy()
+    want = L.loglike_rb(ev, th)
+    scale = np.maximum(np.abs(want), rb_condition_scale(ev, th))
+    assert np.all(np.abs(got - want) <= 1e-8 * scale)
+    gf = gev.loglike_full(_cuda(th[:8])).cpu().numpy()
+    wf = L.loglike_full(ev, th[:8])
+    assert np.all(np.abs(gf - wf) <= 1e-8 * np.maximum(np.abs(wf), L.optimal_snr2(ev, th[:8])))
+
+
+def test_tapered_reference_with_zero_amplitude_node_is_rejected():
+    """A tapered reference that vanishes at a bin edge cannot serve as the denominator
+    of the ratio: event creation fails."""
+    from paper_2404_11397_amd import RblError
+    ev = small_event(approximant="phenomd_nrtv2", duration=4.0, f_high=2048.0, n_bins=60, ref_taper=True)
+    L.prepare(ev)
+    with pytest.raises(RblError):
+        gpu_event(ev)

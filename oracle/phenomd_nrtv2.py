@@ -106,13 +106,11 @@ def planck_taper(f, f_start, f_end):
     safe = np.where(inside, fv, 0.5 * (fs + fe))
     width = f_end - f_start
     z = width / (safe - f_start) + width / (safe - f_end)
-    zv = ad.value(z)
-    zc = np.clip(zv, -700.0, 700.0)
-    if isinstance(z, ad.Dual):
-        z = ad.Dual(zc, z.d)
-    else:
-        z = zc
-    w_in = 1.0 - 1.0 / (ad.exp(z) + 1.0)
+    zc = np.clip(ad.value(z), -700.0, 700.0)
+    wv = 1.0 - 1.0 / (np.exp(zc) + 1.0)
+    # chain rule with the logistic derivative dw/dz = w (1 - w), which stays finite
+    # where exp(z) and dz/dtheta are both large
+    w_in = ad.Dual(wv, (wv * (1.0 - wv)) * z.d) if isinstance(z, ad.Dual) else wv
     below = fv <= fs
     return ad.where(inside, w_in, ad.where(below, np.ones_like(fv), np.zeros_like(fv)))
 

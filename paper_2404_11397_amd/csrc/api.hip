@@ -489,8 +489,6 @@ extern "C" int rbl_loglike_grad(const rbl_event* ev, const double* theta_dev, in
     int rc = check_call("rbl_loglike_grad", ev, theta_dev, B, precision, lnl_dev, workspace);
     if (rc || B == 0) return rc;
     if (!grad_dev) return fail(RBL_EINVAL, "rbl_loglike_grad: null grad");
-    if (ev->waveform == RBL_PHENOMD_NRTV2)
-        return fail(RBL_EUNSUPPORTED, "rbl_loglike_grad: gradient of IMRPhenomD_NRTidalv2 events not available");
     hipStream_t s = (hipStream_t)hip_stream;
     double* rec = (double*)workspace;
     double* jac = (double*)((char*)workspace + align_up(B * kRecStride * (int64_t)sizeof(double)));

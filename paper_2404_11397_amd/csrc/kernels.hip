@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256) void k_chain_setup_grad(const double* __restri
                 for (int i = kRecDc; i < kRecDc + kTf2Basis; ++i) out[i] = 0.0;
                 out[kRecG] = out[kRecG + 1] = out[kRecDl] = 0.0;
             }
-            for (int k = 0; k < 12; ++k) J[kJacInt + k * 6 + tg] = 0.0;
+            for (int k = 0; k < kJacExt / 6; ++k) J[kJacInt + k * 6 + tg] = 0.0;
             return;
         }
         D1 ti[6];
@@ -180,11 +180,32 @@ __global__ __launch_bounds__(256) void k_chain_setup_grad(const double* __restri
             ti[i] = D1(t[i]);
             ti[i].d[0] = (i == tg) ? 1.0 : 0.0;
         }
+        if (ref.waveform == kWfNrtv2) {
+            NrtParams<D1> np;
+            nrt_params<D1>(ti[0], ti[1], ti[2], ti[3], ti[4], ti[5], np);
+            const D1* pv = reinterpret_cast<const D1*>(&np);
+            for (int k = 0; k < kNrtAdj; ++k) J[kJacInt + k * 6 + tg] = pv[k < kNrtAdjSkip ? k : k + 1].d[0];
+            const D1 amp = tf2_amp<D1>(ti[0]);
+            J[kJacInt + kJacAmpNrt * 6 + tg] = amp.d[0] / amp.v;
+            if (tg == 0) {
+                out[kRecStatus] = 1.0;
+                for (int k = 0; k < kTf2Basis; ++k) out[kRecDc + k] = 0.0;
+                const double ang = 2.0 * (t[8] - ref.phic0);
+                const double mag = (ref.dl0 / t[6]) * (amp.v / ref.amp0);
+                double sa, ca;
+                dsincos(ang, sa, ca);
+                out[kRecG] = mag * ca;
+                out[kRecG + 1] = mag * sa;
+                out[kRecDl] = t[6];
+                for (int i = 0; i < kNrtParams; ++i) out[kRecNrt + i] = pv[i].v;
+            }
+            return;
+        }
         Tf2Coeffs<D1> c;
         tf2_coeffs<D1>(ti[0], ti[1], ti[2], ti[3], ti[4], ti[5], c);
         for (int k = 0; k < kTf2Basis; ++k) J[kJacInt + k * 6 + tg] = c.c[k].d[0];
         J[kJacInt + 10 * 6 + tg] = c.c_const.d[0];
-        J[kJacInt + 11 * 6 + tg] = c.amp.d[0] / c.amp.v;
+        J[kJacInt + kJacAmpTf2 * 6 + tg] = c.amp.d[0] / c.amp.v;
         if (tg == 0) {
             out[kRecStatus] = 1.0;
             for (int k = 0; k < kTf2Basis; ++k) out[kRecDc + k] = c.c[k].v - ref.c0[k];

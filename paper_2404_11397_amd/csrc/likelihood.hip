@@ -175,15 +175,15 @@ __global__ __launch_bounds__(256) void k_loglike_fwd(EventDev ev, const double* 
 // is known.  Each lane first evaluates the ratio at the edge before its first edge
 // (owned by the previous lane), so nothing crosses lanes inside the walk.
 // ---------------------------------------------------------------------------
-template <int ND>
+template <int ND, int NA>
 struct GradAcc {
     double acc;
     double zr[ND], zi[ND], ta[ND];
-    double sa[kTf2Basis];
+    double sa[NA];  // TaylorF2: S_b (basis);  IMRPhenomD_NRTidalv2: adjoints of the node parameters
 };
 
 template <int ND, class R>
-__device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, int lane, GradAcc<ND>& G) {
+__device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, int lane, GradAcc<ND, kTf2Basis>& G) {
     const EdgeTab<R> T = edge_tab(ev, R(0));
     const int npad = ev.n_nodes_pad;
     const int L = ev.L;
@@ -258,7 +258,90 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, in
     for (int b = 0; b < kTf2Basis; ++b) G.sa[b] = fma(qprev, bp[b], G.sa[b]);
 }
 
-template <int ND, bool MIXED>
+// IMRPhenomD_NRTidalv2: r_dj = K_d (a_j / a0_j) exp(-2 pi i (Phi_j - Phi0_j + f_j dtau_d)).
+// With W_j = sum_d z_dj, the node parameters p receive
+//   d lnL / dp = sum_j [ 2 pi Im(W_j) dPhi_j / dp + Re(W_j) / a_j  da_j / dp ],
+// accumulated by nrt_node_adjoint once W_j is complete (one step later, as above).  The
+// right cross term of a lane's last edge is added by the next lane at its halo edge;
+// the accumulation is linear in W_j, so each part can be added where it is known.
+template <int ND, class R>
+__device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv, int lane, GradAcc<ND, kNrtAdj>& G) {
+    const EdgeTab<R> T = edge_tab(ev, R(0));
+    const int npad = ev.n_nodes_pad;
+    const int L = ev.L;
+    R kre[ND], kim[ND], rpr[ND], rpi[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        kre[d] = (R)cv.kre[d];
+        kim[d] = (R)cv.kim[d];
+    }
+    const int hpos = lane > 0 ? (L - 1) * 64 + (lane - 1) : npad - 1;
+    double fp = ev.node_f[hpos], xp = ev.node_x[hpos], ixp = ev.node_ix[hpos], lxp = ev.node_lx[hpos];
+    double ap;
+    {
+        double ph, a;
+        nrt_node(cv.np, fp, xp, ixp, lxp, true, ph, a);
+        const double dph = ph - ev.phi0[hpos];
+        const R ar = (R)(a * ev.ia0[hpos]);
+        ap = a;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            R ur, ui;
+            unit_phasor(fma(fp, cv.dtau[d], dph), ur, ui);
+            ur *= ar;
+            ui *= ar;
+            rpr[d] = kre[d] * ur - kim[d] * ui;
+            rpi[d] = kre[d] * ui + kim[d] * ur;
+        }
+    }
+    double wre = 0.0, wim = 0.0;  // W of the previous edge without its right cross term (halo: not ours)
+    for (int k = 0; k < L; ++k) {
+        const int pos = k * 64 + lane;
+        const double f = ev.node_f[pos], x = ev.node_x[pos], ix = ev.node_ix[pos], lx = ev.node_lx[pos];
+        double ph, a;
+        nrt_node(cv.np, f, x, ix, lx, true, ph, a);
+        const double dph = ph - ev.phi0[pos];
+        const R ar = (R)(a * ev.ia0[pos]);
+        double qre = 0.0, qim = 0.0, pre = 0.0, pim = 0.0;
+        const double df = f - fp;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            R ur, ui;
+            unit_phasor(fma(f, cv.dtau[d], dph), ur, ui);
+            ur *= ar;
+            ui *= ar;
+            const R rre = kre[d] * ur - kim[d] * ui;
+            const R rim = kre[d] * ui + kim[d] * ur;
+            const int o = d * npad + pos;
+            const R gre = T.gre[o], gim = T.gim[o], mu = T.mu[o];
+            const R c = R(-0.5) * T.nul[o];
+            const R glr = gre - mu * rre, gli = gim - mu * rim;
+            const R reloc = glr * rre + gli * rim, imz = glr * rim - gli * rre;
+            const R rew = c * (rpr[d] * rre + rpi[d] * rim), imw = c * (rpr[d] * rim - rpi[d] * rre);
+            G.acc += (double)(reloc + R(0.5) * mu * (rre * rre + rim * rim) + rew);
+            G.zr[d] += (double)(reloc + R(2) * rew);
+            G.zi[d] += (double)imz;
+            qre += (double)(reloc + rew);
+            qim += (double)(imz + imw);
+            pre += (double)rew;
+            pim += (double)imw;
+            G.ta[d] = fma((double)imz, f, fma((double)imw, df, G.ta[d]));
+            rpr[d] = rre;
+            rpi[d] = rim;
+        }
+        {   // the previous edge is now complete: W += conj(sum_d w_d)
+            const double wr = wre + pre, wi = wim - pim;
+            nrt_node_adjoint(cv.np, fp, xp, ixp, lxp, (2.0 * kPi) * wi, ap > 0.0 ? wr / ap : 0.0, G.sa);
+        }
+        wre = qre;
+        wim = qim;
+        ap = a;
+        fp = f; xp = x; ixp = ix; lxp = lx;
+    }
+    nrt_node_adjoint(cv.np, fp, xp, ixp, lxp, (2.0 * kPi) * wim, ap > 0.0 ? wre / ap : 0.0, G.sa);
+}
+
+template <int ND, bool MIXED, int WF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_loglike_grad(
     EventDev ev, const double* __restrict__ recs, const double* __restrict__ jac, int64_t B,
     double* __restrict__ lnl, double* __restrict__ grad) {
@@ -272,9 +355,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         if (lane < 13) grad[chain * 13 + lane] = (status == 0.0) ? 0.0 : __builtin_nan("");
         return;
     }
+    constexpr int NA = WF == kWfNrtv2 ? kNrtAdj : kTf2Basis;
     ChainVals<ND> cv;
 #pragma unroll
     for (int j = 0; j < kTf2Basis; ++j) cv.dc[j] = rec[kRecDc + j];
+    if (WF == kWfNrtv2) {
+        double* dst = reinterpret_cast<double*>(&cv.np);
+#pragma unroll
+        for (int i = 0; i < kNrtParams; ++i) dst[i] = rec[kRecNrt + i];
+    }
     const double g_re = rec[kRecG], g_im = rec[kRecG + 1];
     bool zero_k = false;
 #pragma unroll
@@ -285,22 +374,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         cv.dtau[d] = rec[kRecTau + d];
         zero_k = zero_k || !(cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d] > 1e-280);
     }
-    GradAcc<ND> G;
+    GradAcc<ND, NA> G;
     G.acc = 0.0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) G.zr[d] = G.zi[d] = G.ta[d] = 0.0;
 #pragma unroll
-    for (int b = 0; b < kTf2Basis; ++b) G.sa[b] = 0.0;
-    if (MIXED && use_mixed<ND>(ev, cv))
-        grad_walk<ND, float>(ev, cv, lane, G);
-    else
-        grad_walk<ND, double>(ev, cv, lane, G);
+    for (int b = 0; b < NA; ++b) G.sa[b] = 0.0;
+    if constexpr (WF == kWfNrtv2) {
+        if (MIXED && use_mixed<ND>(ev, cv))
+            grad_walk_nrt<ND, float>(ev, cv, lane, G);
+        else
+            grad_walk_nrt<ND, double>(ev, cv, lane, G);
+    } else {
+        if (MIXED && use_mixed<ND>(ev, cv))
+            grad_walk<ND, float>(ev, cv, lane, G);
+        else
+            grad_walk<ND, double>(ev, cv, lane, G);
+    }
 
     // Wave reductions.  Z'_d = Z_d / K_d is the gradient with respect to K_d.
     const double acc = wave_sum(G.acc);
-    double A[kTf2Basis], ZR[ND], ZI[ND], Tt[ND];
+    double A[NA], ZR[ND], ZI[ND], Tt[ND];
+    constexpr double kAdjScale = WF == kWfNrtv2 ? 1.0 : 2.0 * kPi;  // NRTidalv2 adjoints include 2 pi
 #pragma unroll
-    for (int b = 0; b < kTf2Basis; ++b) A[b] = 2.0 * kPi * wave_sum(G.sa[b]);
+    for (int b = 0; b < NA; ++b) A[b] = kAdjScale * wave_sum(G.sa[b]);
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         const double zre = wave_sum(G.zr[d]), zim = wave_sum(G.zi[d]);
@@ -318,12 +415,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             double sr = 0.0, si = 0.0;
             for (int k = 0; k < ev.L; ++k) {
                 const int pos = k * 64 + lane;
-                double bas[kTf2Basis];
-                tf2_basis(ev.node_x[pos], ev.node_ix[pos], ev.node_lx[pos], bas);
-                double ph = 0.0;
-                for (int b = 0; b < kTf2Basis; ++b) ph = fma(cv.dc[b], bas[b], ph);
+                const double f = ev.node_f[pos];
+                double ph, ar;
+                edge_phase<ND, WF>(ev, cv, pos, f, ph, ar);
                 double ur, ui;
-                expm2pi_rev(fma(ev.node_f[pos], cv.dtau[d], ph), ur, ui);
+                expm2pi_rev(fma(f, cv.dtau[d], ph), ur, ui);
+                ur *= ar;
+                ui *= ar;
                 const int o = d * npad + pos;
                 sr += ev.g_re[o] * ur + ev.g_im[o] * ui;
                 si += ev.g_re[o] * ui - ev.g_im[o] * ur;
@@ -340,10 +438,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     if (lane < 13) {
         const double* J = jac + chain * kJacStride;
         double g = 0.0;
-        if (lane < 6) {
+        if (lane < 6 && WF == kWfNrtv2) {
 #pragma unroll
-            for (int b = 0; b < kTf2Basis; ++b) g = fma(A[b], J[kJacInt + b * 6 + lane], g);
-            const double dre = J[kJacInt + 11 * 6 + lane];
+            for (int b = 0; b < NA; ++b) g = fma(A[b], J[kJacInt + b * 6 + lane], g);
+            const double dre = J[kJacInt + kJacAmpNrt * 6 + lane];
+#pragma unroll
+            for (int d = 0; d < ND; ++d) g = fma(ZR[d] * cv.kre[d] - ZI[d] * cv.kim[d], dre, g);
+        } else if (lane < 6) {
+#pragma unroll
+            for (int b = 0; b < NA; ++b) g = fma(A[b], J[kJacInt + b * 6 + lane], g);
+            const double dre = J[kJacInt + kJacAmpTf2 * 6 + lane];
             const double dim = -2.0 * kPi * J[kJacInt + 10 * 6 + lane];
 #pragma unroll
             for (int d = 0; d < ND; ++d) {
@@ -406,10 +510,21 @@ template <int ND>
 static void grad_nd(const EventDev& ev, const double* rec, const double* jac, int64_t B, int mixed, double* lnl,
                     double* grad, hipStream_t s) {
     const unsigned grid = (unsigned)((B + 3) / 4);
-    if (mixed)
-        hipLaunchKernelGGL((k_loglike_grad<ND, true>), dim3(grid), dim3(256), 0, s, ev, rec, jac, B, lnl, grad);
-    else
-        hipLaunchKernelGGL((k_loglike_grad<ND, false>), dim3(grid), dim3(256), 0, s, ev, rec, jac, B, lnl, grad);
+    if (ev.waveform == kWfNrtv2) {
+        if (mixed)
+            hipLaunchKernelGGL((k_loglike_grad<ND, true, kWfNrtv2>), dim3(grid), dim3(256), 0, s, ev, rec, jac, B,
+                               lnl, grad);
+        else
+            hipLaunchKernelGGL((k_loglike_grad<ND, false, kWfNrtv2>), dim3(grid), dim3(256), 0, s, ev, rec, jac, B,
+                               lnl, grad);
+    } else {
+        if (mixed)
+            hipLaunchKernelGGL((k_loglike_grad<ND, true, kWfTaylorF2>), dim3(grid), dim3(256), 0, s, ev, rec, jac,
+                               B, lnl, grad);
+        else
+            hipLaunchKernelGGL((k_loglike_grad<ND, false, kWfTaylorF2>), dim3(grid), dim3(256), 0, s, ev, rec, jac,
+                               B, lnl, grad);
+    }
 }
 
 hipError_t launch_loglike_grad(const EventDev& ev, const double* rec, const double* jac, int64_t B, int mixed,

@@ -12,7 +12,7 @@ constexpr int kWfTaylorF2 = 0;  // RBL_TAYLORF2
 constexpr int kWfNrtv2 = 1;     // RBL_PHENOMD_NRTV2
 constexpr int kNodeTile = 64;  // node tables are padded to a multiple of the wavefront
 
-// Per-chain record produced by the setup kernels (FP64, 32 doubles, 256 B).
+// Per-chain record produced by the setup kernels (FP64, 64 doubles, 512 B).
 //   [0]        status: 1 valid, 0 outside the physical domain, NaN if theta has a NaN
 //   [1..10]    dc_b  = c_b(theta) - c_b(theta0), TaylorF2 basis coefficients [rev]
 //   [11..16]   likelihood setup: K_d = P_d G, (re, im) per detector;
@@ -33,13 +33,18 @@ constexpr int kRecDl = 22;
 constexpr int kRecUsed = 20;                 // entries 1..19 are used by the likelihood kernels
 constexpr int kRecNrt = 24;
 
-// Partial derivatives stored per chain for the gradient (FP64, 112 doubles):
-//   [0, 72)    d(dc_b, dc_const, ln amp)/d(Mc, q, chi1, chi2, Lambda1, Lambda2), [12][6]
-//   [72, 108)  d(Re P_d, Im P_d, dt_d)/d(iota, psi, ra, dec), [3 det][3][4]
+// Partial derivatives stored per chain for the gradient (FP64, 200 doubles):
+//   [0, 162)   intrinsic block, rows of 6 (d/d(Mc, q, chi1, chi2, Lambda1, Lambda2)):
+//              TaylorF2: rows 0-9 dc_b, row 10 dc_const, row 11 ln amp;
+//              IMRPhenomD_NRTidalv2: rows 0-25 the node parameters in adjoint order
+//              (see nrt_node_adjoint), row 26 ln amp
+//   [162, 198) d(Re P_d, Im P_d, dt_d)/d(iota, psi, ra, dec), [3 det][3][4]
 // The remaining dependencies (dL, tc, phic) are applied in closed form.
-constexpr int kJacStride = 112;
+constexpr int kJacStride = 200;
 constexpr int kJacInt = 0;
-constexpr int kJacExt = 72;
+constexpr int kJacExt = 162;
+constexpr int kJacAmpTf2 = 11;
+constexpr int kJacAmpNrt = kNrtAdj;
 
 // Reference (fiducial) constants computed once per event on the device.
 struct RefConsts {

@@ -214,4 +214,106 @@ __device__ inline void nrt_node(const NrtParams<double>& p, double f, double x, 
     }
 }
 
+// Adjoint of one edge: acc[k] += gphi dPhi/dp_k + ga da/dp_k for the node parameters
+// p_k in the order of NrtParams without f2 and amp (kNrtAdj of them; index k is field k
+// for k < kNrtAdjSkip and field k + 1 above).  gphi = d lnL / dPhi [per revolution],
+// ga = d lnL / da.  The region and taper branches are taken as in nrt_node; derivatives
+// of the branch conditions are zero almost everywhere.
+constexpr int kNrtAdj = 26;
+constexpr int kNrtAdjSkip = 21;  // f2
+constexpr int kAdjMs = 0, kAdjLnMs = 1, kAdjS = 2, kAdjLnS = 3, kAdjC = 4, kAdjCc = 12, kAdjB = 13, kAdjA = 17,
+              kAdjTp = 21, kAdjM9k = 22, kAdjFpk = 23, kAdjFdp = 24, kAdjFm = 25;
+
+__device__ inline void nrt_node_adjoint(const NrtParams<double>& p, double f, double x, double ix, double lx,
+                                        double gphi, double ga, double* acc) {
+    const double mf = p.ms * f;
+    if (mf < kNrtF1) {
+        const double ix2 = ix * ix, ix3 = ix2 * ix;
+        acc[kAdjC + 0] = fma(gphi, ix3 * ix2, acc[kAdjC + 0]);
+        acc[kAdjC + 1] = fma(gphi, ix3, acc[kAdjC + 1]);
+        acc[kAdjC + 2] = fma(gphi, ix2, acc[kAdjC + 2]);
+        acc[kAdjC + 3] = fma(gphi, ix, acc[kAdjC + 3]);
+        acc[kAdjC + 4] = fma(gphi, lx, acc[kAdjC + 4]);
+        acc[kAdjC + 5] = fma(gphi, x, acc[kAdjC + 5]);
+        acc[kAdjC + 6] = fma(gphi, x * lx, acc[kAdjC + 6]);
+        acc[kAdjC + 7] = fma(gphi, x * x, acc[kAdjC + 7]);
+        acc[kAdjCc] += gphi;
+    } else {
+        const double lnmf = p.lnms + 3.0 * lx;
+        const double im = 1.0 / mf;
+        if (mf < p.f2) {
+            const double im3 = im * im * im;
+            acc[kAdjB + 0] += gphi;
+            acc[kAdjB + 1] = fma(gphi, mf, acc[kAdjB + 1]);
+            acc[kAdjB + 2] = fma(gphi, lnmf, acc[kAdjB + 2]);
+            acc[kAdjB + 3] = fma(gphi, -(1.0 / 3.0) * im3, acc[kAdjB + 3]);
+            acc[kAdjMs] = fma(gphi, f * (p.b[1] + p.b[3] * (im3 * im)), acc[kAdjMs]);
+            acc[kAdjLnMs] = fma(gphi, p.b[2], acc[kAdjLnMs]);
+        } else {
+            const double e = exp(0.75 * lnmf);
+            acc[kAdjA + 0] += gphi;
+            acc[kAdjA + 1] = fma(gphi, mf, acc[kAdjA + 1]);
+            acc[kAdjA + 2] = fma(gphi, -im, acc[kAdjA + 2]);
+            acc[kAdjA + 3] = fma(gphi, (4.0 / 3.0) * e, acc[kAdjA + 3]);
+            acc[kAdjMs] = fma(gphi, f * (p.a[1] + p.a[2] * (im * im)), acc[kAdjMs]);
+            acc[kAdjLnMs] = fma(gphi, p.a[3] * e, acc[kAdjLnMs]);
+        }
+    }
+    // tidal phase tp sx^5 N(sx) / D(sx), sx = s x
+    const double sx = p.s * x;
+    const double xt = sx * sx;
+    const double xt2 = xt * xt;
+    const double sx5 = xt2 * sx;
+    const double num = 1.0 + kTn1 * xt + kTn32 * xt * sx + kTn2 * xt2 + kTn52 * xt2 * sx + kTn3 * xt2 * xt;
+    const double den = 1.0 + kTd1 * xt + kTd32 * xt * sx + kTd2 * xt2;
+    const double dnum = sx * (2.0 * kTn1 + 3.0 * kTn32 * sx + 4.0 * kTn2 * xt + 5.0 * kTn52 * xt * sx + 6.0 * kTn3 * xt2);
+    const double dden = sx * (2.0 * kTd1 + 3.0 * kTd32 * sx + 4.0 * kTd2 * xt);
+    const double rat = num / den;
+    acc[kAdjTp] = fma(gphi, sx5 * rat, acc[kAdjTp]);
+    const double dtid = p.tp * (5.0 * xt2 * rat + sx5 * (dnum - rat * dden) / den);  // d tidal / d sx
+    double gs = gphi * dtid * x;                                                      // -> d / ds
+    // amplitude a = (a_pp + a_T) w
+    double w = 1.0, dw = 0.0;  // taper and its derivative with respect to f_merger
+    const double fe = 1.2 * p.fm;
+    if (f >= fe) {
+        w = 0.0;
+    } else if (f > p.fm) {
+        const double wd = fe - p.fm;
+        const double u1 = 1.0 / (f - p.fm), u2 = 1.0 / (f - fe);
+        double z = wd * u1 + wd * u2;
+        const bool clip = z > 700.0 || z < -700.0;
+        z = fmin(fmax(z, -700.0), 700.0);
+        const double ez = exp(z);
+        w = 1.0 - 1.0 / (ez + 1.0);
+        if (!clip) {
+            const double dz = 0.2 * u1 + wd * u1 * u1 + 0.2 * u2 + 1.2 * wd * u2 * u2;
+            dw = w * (1.0 - w) * dz;
+        }
+    }
+    const double gA = ga * w;  // d lnL / d(a_pp + a_T)
+    double app = 1.0;
+    if (mf >= p.fpk) {
+        const double id = 1.0 / p.fdp;
+        app = exp(-(mf - p.fpk) * id);
+        const double g = gA * app * id;
+        acc[kAdjMs] = fma(-g, f, acc[kAdjMs]);
+        acc[kAdjFpk] += g;
+        acc[kAdjFdp] = fma(g, (mf - p.fpk) * id, acc[kAdjFdp]);
+    }
+    const double lxt = 2.0 * (p.lns + lx);
+    const double e289 = exp(2.89 * lxt);
+    const double xt4 = xt2 * xt2;
+    const double nn = 1.0 + (449.0 / 108.0) * xt + (22672.0 / 9.0) * e289;
+    const double dd = 1.0 + 13477.8 * xt4;
+    const double idd = 1.0 / dd;
+    const double base = xt4 * xt * nn * idd;  // a_T / m9k
+    acc[kAdjM9k] = fma(gA, base, acc[kAdjM9k]);
+    const double dat_dxt = p.m9k * (5.0 * xt4 * nn * idd + xt4 * xt * ((449.0 / 108.0) - nn * idd * (4.0 * 13477.8) * xt2 * xt) * idd);
+    gs = fma(gA * dat_dxt, 2.0 * sx * x, gs);
+    acc[kAdjS] += gs;
+    acc[kAdjLnS] = fma(gA, p.m9k * xt4 * xt * (22672.0 / 9.0) * 2.89 * e289 * idd * 2.0, acc[kAdjLnS]);
+    const double at = p.m9k * base;
+    acc[kAdjFm] = fma(ga * (app + at), dw, acc[kAdjFm]);
+}
+
 }  // namespace rbl

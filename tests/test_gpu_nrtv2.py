@@ -146,3 +146,67 @@ def test_tapered_reference_with_zero_amplitude_node_is_rejected():
     L.prepare(ev)
     with pytest.raises(RblError):
         gpu_event(ev)
+
+
+# ---- gradient (hand-written adjoint through the NRTidalv2 node parameters) ----------------
+
+from gpu_common import WIDTHS  # noqa: E402
+
+
+def _grad_rel(g, want):
+    gs, ws = g * WIDTHS, want * WIDTHS
+    return np.abs(gs - ws).max(axis=1) / np.abs(ws).max(axis=1)
+
+
+def test_gradient_parity_cfg3_near_reference(cfg3):
+    ev, _, gev = cfg3
+    th = near_draws(ev.theta_ref, 64, 47, scale=0.3)
+    lnl, g = gev.loglike_grad(_cuda(th))
+    lnl, g = lnl.cpu().numpy(), g.cpu().numpy()
+    wl, wg = L.loglike_rb_grad(ev, th)
+    scale = np.maximum(np.abs(wl), rb_condition_scale(ev, th))
+    assert np.all(np.abs(lnl - wl) <= 1e-8 * scale)
+    rel = _grad_rel(g, wg)
+    say("cfg3 near-theta0 grad max rel err", rel.max())
+    assert np.all(rel <= 1e-5)
+
+
+def test_gradient_parity_cfg4_nrtv2_sampled():
+    """8192 prior draws on the cfg3 data (the differentiation workload), oracle on a sample."""
+    ev, w = oracle_event("cfg4_nrtv2")
+    gev = gpu_event(ev)
+    th = w["theta"]
+    lnl, g = gev.loglike_grad(_cuda(th))
+    lnl, g = lnl.cpu().numpy(), g.cpu().numpy()
+    idx = np.random.default_rng(48).choice(len(th), 64, replace=False)
+    idx.sort()
+    wl, wg = L.loglike_rb_grad(ev, th[idx])
+    scale = np.maximum(np.abs(wl), rb_condition_scale(ev, th[idx]))
+    assert np.all(np.abs(lnl[idx] - wl) <= 1e-8 * scale)
+    rel = _grad_rel(g[idx], wg)
+    say("cfg4_nrtv2 grad max rel err", rel.max())
+    assert np.all(rel <= 1e-5)
+    lm, gm = gev.loglike_grad(_cuda(th), precision="mixed")
+    lm, gm = lm.cpu().numpy(), gm.cpu().numpy()
+    say("cfg4_nrtv2 mixed lnL max abs err", np.abs(lm[idx] - wl).max(), "grad rel", _grad_rel(gm[idx], wg).max())
+    assert np.all(np.abs(lm[idx] - wl) <= 1e-2)
+    assert np.all(_grad_rel(gm[idx], wg) <= 1e-3)
+
+
+def test_gradient_tapered_reference_and_zero_gradient_at_peak():
+    """Tapered reference, zero-noise data: the gradient vanishes at theta0 (the
+    binned lnL peaks there), and matches the oracle nearby."""
+    ev = _tapered_reference_event()
+    h = W.strain(ev.f, ev.theta_ref[None, :], ev.tensors, ev.vertices, ev.gmst, "phenomd_nrtv2", True)
+    ev.data = np.stack([x[0] for x in h])
+    L.prepare(ev)
+    gev = gpu_event(ev)
+    th = np.vstack([ev.theta_ref[None, :], near_draws(ev.theta_ref, 31, 49)])
+    lnl, g = gev.loglike_grad(_cuda(th))
+    lnl, g = lnl.cpu().numpy(), g.cpu().numpy()
+    wl, wg = L.loglike_rb_grad(ev, th)
+    scale = np.abs(wg[1:] * WIDTHS).max()
+    assert np.abs(g[0] * WIDTHS).max() <= 1e-8 * scale
+    rel = _grad_rel(g[1:], wg[1:])
+    say("tapered-reference grad max rel err", rel.max())
+    assert np.all(rel <= 1e-5)

@@ -152,6 +152,82 @@ int rbl_profile_read_summary(double *ms, int64_t *events);
 
 const char *rbl_last_error(void);
 
+/* ---------------------------------------------------------------------------------------
+ * Serving: continuous batching of likelihood requests over many resident events (the
+ * sampler of Sec. II D evaluates thousands of chains per step; a service answers such
+ * batches for many events at once).
+ *
+ * A server owns a worker thread, n_streams HIP streams of the device that was current at
+ * rbl_server_create, and a pool of request buffers (device: theta, lnL, grad and
+ * workspace; pinned host: theta and results) in power-of-two size classes of at least
+ * 256 chains.  Admission is by HBM footprint: the resident bytes of the registered events
+ * plus the bytes of the pool never exceed hbm_budget_bytes.  Requests are admitted in
+ * arrival order (FIFO) as soon as a stream is free and a buffer of their class is free
+ * or can be allocated within the budget (idle buffers of other classes are released to
+ * make room); otherwise they wait (back-pressure).  Admitted requests run concurrently,
+ * one per stream.  Each runs as one persistent hipGraph replay (copy in, per-chain setup,
+ * likelihood kernel, copy out), captured on first use for its (buffer, event, B,
+ * precision, gradient) and reused afterwards; RBL_SERVE_NO_GRAPHS makes plain launches
+ * instead.  Results are bitwise identical to rbl_loglike / rbl_loglike_grad on the same
+ * theta: no value is reduced across chains or requests.
+ *
+ * Times are host CLOCK_MONOTONIC nanoseconds (rbl_clock_ns). */
+typedef struct rbl_server rbl_server;
+
+#define RBL_SERVE_NO_GRAPHS 0x1u
+
+typedef struct {
+    int64_t t_arrival_ns;  /* as given to rbl_server_submit (or the submit time) */
+    int64_t t_admit_ns;    /* launched on a stream */
+    int64_t t_done_ns;     /* results copied to the caller's buffers */
+    int32_t status;        /* RBL_OK, or the error of the request */
+    int32_t stream;        /* index of the stream it ran on */
+} rbl_request_info;
+
+typedef struct {
+    int64_t budget_bytes, resident_bytes, buffer_bytes;
+    int64_t submitted, completed, queued, in_flight, max_in_flight;
+    int64_t graphs, graph_launches, plain_launches;
+    int64_t buffer_allocs, buffer_releases, admission_waits;
+} rbl_server_stats;
+
+/* Create a server.  hbm_budget_bytes > 0; n_streams in 1..16.  RBL_ENOMEM if resources
+ * cannot be created. */
+int rbl_server_create(int64_t hbm_budget_bytes, int32_t n_streams, uint32_t flags, rbl_server **out);
+
+/* Register a resident event (created by rbl_event_create, owned by the caller, alive
+ * until removed).  RBL_ENOMEM if its footprint does not fit in the budget next to the
+ * events already registered and the current buffer pool. */
+int rbl_server_add_event(rbl_server *srv, const rbl_event *ev, int32_t *event_id);
+
+/* Unregister an event; RBL_EINVAL if requests for it are queued or running. */
+int rbl_server_remove_event(rbl_server *srv, int32_t event_id);
+
+/* Queue one request: B chains of theta_host [B][13] (host float64) for a registered event.
+ * lnl_host [B] and, if with_grad, grad_host [B][13] receive the results.  The caller keeps
+ * all three buffers alive and untouched until rbl_server_wait returns for the ticket.
+ * t_arrival_ns = 0 takes the submit time.  RBL_ENOMEM if the request's buffer can never
+ * fit in the budget next to the resident events.  B = 0 completes at once. */
+int rbl_server_submit(rbl_server *srv, int32_t event_id, const double *theta_host, int64_t B,
+                      int32_t precision, int32_t with_grad, double *lnl_host, double *grad_host,
+                      int64_t t_arrival_ns, int64_t *ticket);
+
+/* Block until the request has completed, fill info (may be NULL), release the ticket and
+ * return the request's status. */
+int rbl_server_wait(rbl_server *srv, int64_t ticket, rbl_request_info *info);
+
+int rbl_server_get_stats(const rbl_server *srv, rbl_server_stats *out);
+
+/* Finish every queued and running request, then release the streams, buffers and graphs. */
+void rbl_server_destroy(rbl_server *srv);
+
+/* Host monotonic clock used for request times [ns]. */
+int64_t rbl_clock_ns(void);
+
+/* Resident device bytes of an event (summary data and edge tables, plus the grid with
+ * RBL_KEEP_GRID). */
+int64_t rbl_event_footprint_bytes(const rbl_event *ev);
+
 #ifdef __cplusplus
 }
 #endif

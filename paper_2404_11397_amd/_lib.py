@@ -19,7 +19,10 @@ ERROR_NAMES = {-1: "RBL_EINVAL", -2: "RBL_EEDGES", -3: "RBL_EPSD", -4: "RBL_ENOM
 EXPORTS = ("rbl_event_create", "rbl_event_free", "rbl_workspace_bytes", "rbl_loglike",
            "rbl_loglike_grad", "rbl_loglike_full", "rbl_strain", "rbl_event_get_summary",
            "rbl_event_info", "rbl_bin_edges", "rbl_profile_enable", "rbl_profile_read", "rbl_profile_read_summary",
-           "rbl_last_error")
+           "rbl_last_error", "rbl_server_create", "rbl_server_add_event", "rbl_server_remove_event",
+           "rbl_server_submit", "rbl_server_wait", "rbl_server_get_stats", "rbl_server_destroy", "rbl_clock_ns",
+           "rbl_event_footprint_bytes")
+RBL_SERVE_NO_GRAPHS = 0x1
 
 
 class RblError(RuntimeError):
@@ -35,6 +38,18 @@ class EventDesc(ctypes.Structure):
                 ("data", ctypes.c_void_p), ("psd", ctypes.c_void_p),
                 ("det_tensor", ctypes.c_void_p), ("det_vertex", ctypes.c_void_p),
                 ("theta_ref", ctypes.c_void_p), ("edges", ctypes.c_void_p)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("t_arrival_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64),
+                ("status", ctypes.c_int32), ("stream", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "budget_bytes", "resident_bytes", "buffer_bytes", "submitted", "completed", "queued", "in_flight",
+        "max_in_flight", "graphs", "graph_launches", "plain_launches", "buffer_allocs", "buffer_releases",
+        "admission_waits")]
 
 
 _lib = None
@@ -77,6 +92,24 @@ def lib():
     L.rbl_profile_read_summary.restype = ctypes.c_int
     L.rbl_last_error.argtypes = []
     L.rbl_last_error.restype = ctypes.c_char_p
+    L.rbl_server_create.argtypes = [i64, i32, ctypes.c_uint32, ctypes.POINTER(vp)]
+    L.rbl_server_create.restype = ctypes.c_int
+    L.rbl_server_add_event.argtypes = [vp, vp, ctypes.POINTER(i32)]
+    L.rbl_server_add_event.restype = ctypes.c_int
+    L.rbl_server_remove_event.argtypes = [vp, i32]
+    L.rbl_server_remove_event.restype = ctypes.c_int
+    L.rbl_server_submit.argtypes = [vp, i32, vp, i64, i32, i32, vp, vp, i64, ctypes.POINTER(i64)]
+    L.rbl_server_submit.restype = ctypes.c_int
+    L.rbl_server_wait.argtypes = [vp, i64, ctypes.POINTER(RequestInfo)]
+    L.rbl_server_wait.restype = ctypes.c_int
+    L.rbl_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    L.rbl_server_get_stats.restype = ctypes.c_int
+    L.rbl_server_destroy.argtypes = [vp]
+    L.rbl_server_destroy.restype = None
+    L.rbl_clock_ns.argtypes = []
+    L.rbl_clock_ns.restype = i64
+    L.rbl_event_footprint_bytes.argtypes = [vp]
+    L.rbl_event_footprint_bytes.restype = i64
     _lib = L
     return L
 

@@ -7,12 +7,11 @@
 #include <string>
 #include <vector>
 
-#include "../../include/rbl.h"
-#include "rbl_launch.h"
+#include "rbl_host.h"
 
 using namespace rbl;
 
-namespace {
+namespace rbl {
 
 thread_local std::string g_err;
 
@@ -26,10 +25,11 @@ int hip_fail(hipError_t e, const char* what) {
     return RBL_EDEVICE;
 }
 
-constexpr int64_t kChunk = 512;     // grid points per summary work item
-constexpr int64_t kAlign = 256;
+}  // namespace rbl
 
-int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+namespace {
+
+constexpr int64_t kChunk = 512;     // grid points per summary work item
 
 bool theta_in_domain(const double* t) {
     for (int i = 0; i < 13; ++i)
@@ -37,20 +37,6 @@ bool theta_in_domain(const double* t) {
     return t[0] > 0.0 && t[1] > 0.0 && t[6] > 0.0 && std::fabs(t[2]) < 1.0 && std::fabs(t[3]) < 1.0 &&
            t[4] >= 0.0 && t[5] >= 0.0;
 }
-
-// Device allocations of one event, released together.
-struct DevList {
-    std::vector<void*> ptrs;
-    hipError_t alloc(void** p, size_t bytes) {
-        hipError_t e = hipMalloc(p, bytes ? bytes : 1);
-        if (e == hipSuccess) ptrs.push_back(*p);
-        return e;
-    }
-    void release() {
-        for (void* p : ptrs) (void)hipFree(p);
-        ptrs.clear();
-    }
-};
 
 // Benchmark timing: events around the setup and main kernel of each call.
 struct ProfState {
@@ -125,21 +111,6 @@ extern "C" int rbl_profile_read(double* main_ms, double* setup_ms, int64_t* call
     if (calls) *calls = n;
     return RBL_OK;
 }
-
-struct rbl_event {
-    int32_t n_det = 0, n_bins = 0, n_nodes = 0, n_nodes_pad = 0, waveform = 0;
-    uint32_t flags = 0;
-    int64_t n_freq = 0;
-    double f_low = 0, delta_f = 0, gmst = 0;
-    Network net{};
-    RefConsts ref{};
-    EventDev dev{};
-    double* d_summary = nullptr;
-    double* d_data = nullptr;  // only with RBL_KEEP_GRID
-    double* d_psd = nullptr;
-    int64_t footprint = 0;
-    DevList mem;
-};
 
 extern "C" const char* rbl_last_error(void) { return g_err.c_str(); }
 
@@ -450,10 +421,10 @@ extern "C" void rbl_event_free(rbl_event* ev) {
 
 extern "C" int64_t rbl_workspace_bytes(const rbl_event* ev, int64_t B, int32_t with_grad) {
     if (!ev || B < 0) return 0;
-    int64_t bytes = align_up(B * kRecStride * (int64_t)sizeof(double));
-    if (with_grad) bytes += align_up(B * kJacStride * (int64_t)sizeof(double));
-    return bytes;
+    return workspace_bytes(B, with_grad != 0);
 }
+
+extern "C" int64_t rbl_event_footprint_bytes(const rbl_event* ev) { return ev ? ev->footprint : 0; }
 
 static int check_call(const char* who, const rbl_event* ev, const double* theta, int64_t B, int32_t precision,
                       const void* lnl, const void* ws) {

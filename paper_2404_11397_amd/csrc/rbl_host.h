@@ -1,0 +1,57 @@
+// Host-side state shared by the C-ABI translation units (events, errors, helpers).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rbl.h"
+#include "rbl_launch.h"
+
+namespace rbl {
+
+// Thread-local error text for rbl_last_error; both return the code they are given
+// (hip_fail: RBL_EDEVICE).
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+constexpr int64_t kAlign = 256;
+inline int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Device allocations of one owner, released together.
+struct DevList {
+    std::vector<void*> ptrs;
+    hipError_t alloc(void** p, size_t bytes) {
+        hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+        if (e == hipSuccess) ptrs.push_back(*p);
+        return e;
+    }
+    void release() {
+        for (void* p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+    }
+};
+
+// Workspace bytes of B chains (records, plus the Jacobians for the gradient).
+inline int64_t workspace_bytes(int64_t B, bool with_grad) {
+    int64_t bytes = align_up(B * kRecStride * (int64_t)sizeof(double));
+    if (with_grad) bytes += align_up(B * kJacStride * (int64_t)sizeof(double));
+    return bytes;
+}
+
+}  // namespace rbl
+
+// A resident event: immutable after rbl_event_create.
+struct rbl_event {
+    int32_t n_det = 0, n_bins = 0, n_nodes = 0, n_nodes_pad = 0, waveform = 0;
+    uint32_t flags = 0;
+    int64_t n_freq = 0;
+    double f_low = 0, delta_f = 0, gmst = 0;
+    rbl::Network net{};
+    rbl::RefConsts ref{};
+    rbl::EventDev dev{};
+    double* d_summary = nullptr;
+    double* d_data = nullptr;  // only with RBL_KEEP_GRID
+    double* d_psd = nullptr;
+    int64_t footprint = 0;
+    rbl::DevList mem;
+};

@@ -1,0 +1,498 @@
+// Request server: continuous batching of likelihood requests over resident events.
+//
+// One worker thread owns the streams, the request-buffer pool and the graph cache.
+// Callers queue requests (rbl_server_submit) and block on tickets (rbl_server_wait).
+// The worker loop: (1) reap finished requests (event query per stream), copying the
+// results from pinned staging to the caller's buffers; (2) admit queued requests in
+// FIFO order while a stream is free and a buffer fits the HBM budget; (3) sleep on a
+// condition variable when nothing is queued or running, otherwise yield and poll.
+// Every launch is either one graph replay or the same operations issued one by one.
+#include <time.h>
+
+#include <algorithm>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "rbl_host.h"
+
+using namespace rbl;
+
+namespace {
+
+int64_t now_ns() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (int64_t)ts.tv_sec * 1000000000LL + ts.tv_nsec;
+}
+
+constexpr int64_t kMinClass = 256;  // smallest buffer class [chains]
+constexpr int kMaxStreams = 16;
+
+int64_t class_of(int64_t B) {
+    int64_t c = kMinClass;
+    while (c < B) c <<= 1;
+    return c;
+}
+
+// Device layout of one request buffer of `cap` chains: theta | lnl | grad | workspace.
+struct BufLayout {
+    int64_t theta, lnl, grad, ws, total;
+    explicit BufLayout(int64_t cap)
+        : theta(align_up(cap * 13 * (int64_t)sizeof(double))),
+          lnl(align_up(cap * (int64_t)sizeof(double))),
+          grad(align_up(cap * 13 * (int64_t)sizeof(double))),
+          ws(workspace_bytes(cap, true)),
+          total(theta + lnl + grad + ws) {}
+};
+
+struct Buffer {
+    uint64_t id = 0;
+    int64_t cap = 0, bytes = 0;
+    char* dev = nullptr;
+    double* h_theta = nullptr;  // pinned [cap][13]
+    double* h_out = nullptr;    // pinned: lnl [cap], then grad [cap][13]
+    bool busy = false;
+    int64_t last_use = 0;
+};
+
+struct Request {
+    int64_t ticket = 0;
+    int32_t event = 0;
+    const rbl_event* ev = nullptr;
+    const double* theta = nullptr;
+    int64_t B = 0;
+    int32_t precision = RBL_FP64;
+    bool grad = false;
+    double* lnl = nullptr;
+    double* gout = nullptr;
+    rbl_request_info info{};
+    int state = 0;  // 0 queued, 1 running, 2 done
+    bool counted_wait = false;
+    Buffer* buf = nullptr;
+};
+
+struct Slot {
+    hipStream_t s = nullptr;
+    hipEvent_t done = nullptr;
+    Request* cur = nullptr;
+};
+
+using GraphKey = std::tuple<uint64_t, int32_t, int64_t, int32_t, int32_t>;  // buffer, event, B, precision, grad
+
+}  // namespace
+
+struct rbl_server {
+    int device = 0;
+    int64_t budget = 0;
+    uint32_t flags = 0;
+    mutable std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request*> queue;
+    std::unordered_map<int64_t, Request*> reqs;
+    int64_t next_ticket = 1;
+    std::map<int32_t, const rbl_event*> events;
+    std::map<int32_t, int64_t> users;  // queued + running requests per event
+    int32_t next_event = 0;
+    int64_t resident = 0;
+    int64_t buffer_bytes = 0;
+    std::vector<Slot> slots;
+    std::vector<std::unique_ptr<Buffer>> bufs;
+    uint64_t next_buf = 1;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    rbl_server_stats st{};
+    bool stop = false;
+    std::thread worker;
+};
+
+namespace {
+
+// ---- buffers -----------------------------------------------------------------------------
+
+void drop_graphs_if(rbl_server* S, uint64_t buf_id, int32_t event) {
+    for (auto it = S->graphs.begin(); it != S->graphs.end();) {
+        if (std::get<0>(it->first) == buf_id || std::get<1>(it->first) == event) {
+            (void)hipGraphExecDestroy(it->second);
+            it = S->graphs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+void free_buffer_memory(Buffer* b) {
+    if (b->dev) (void)hipFree(b->dev);
+    if (b->h_theta) (void)hipHostFree(b->h_theta);
+    if (b->h_out) (void)hipHostFree(b->h_out);
+    b->dev = nullptr;
+    b->h_theta = b->h_out = nullptr;
+}
+
+void release_buffer(rbl_server* S, Buffer* b) {
+    drop_graphs_if(S, b->id, -1);
+    free_buffer_memory(b);
+    S->buffer_bytes -= b->bytes;
+    S->st.buffer_releases++;
+    S->bufs.erase(std::remove_if(S->bufs.begin(), S->bufs.end(), [&](const std::unique_ptr<Buffer>& p) {
+                      return p.get() == b;
+                  }),
+                  S->bufs.end());
+}
+
+Buffer* allocate_buffer(rbl_server* S, int64_t cap) {
+    auto b = std::make_unique<Buffer>();
+    b->id = S->next_buf++;
+    b->cap = cap;
+    b->bytes = BufLayout(cap).total;
+    if (hipMalloc((void**)&b->dev, (size_t)b->bytes) != hipSuccess ||
+        hipHostMalloc((void**)&b->h_theta, (size_t)(cap * 13 * sizeof(double)), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->h_out, (size_t)(cap * 14 * sizeof(double)), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        free_buffer_memory(b.get());
+        return nullptr;
+    }
+    S->buffer_bytes += b->bytes;
+    S->st.buffer_allocs++;
+    S->bufs.push_back(std::move(b));
+    return S->bufs.back().get();
+}
+
+// A free buffer for B chains: its own class if free; else a new one of its class within
+// the budget; else a free larger one; else a new one after releasing idle buffers
+// (least recently used first).  nullptr: wait for running requests.
+Buffer* acquire(rbl_server* S, int64_t B) {
+    const int64_t cap = class_of(B);
+    for (auto& b : S->bufs)
+        if (!b->busy && b->cap == cap) return b.get();
+    const int64_t need = BufLayout(cap).total;
+    if (S->resident + S->buffer_bytes + need <= S->budget) {
+        if (Buffer* b = allocate_buffer(S, cap)) return b;
+    }
+    Buffer* larger = nullptr;
+    for (auto& b : S->bufs)
+        if (!b->busy && b->cap >= B && (!larger || b->cap < larger->cap)) larger = b.get();
+    if (larger) return larger;
+    while (S->resident + S->buffer_bytes + need > S->budget) {
+        Buffer* victim = nullptr;
+        for (auto& b : S->bufs)
+            if (!b->busy && (!victim || b->last_use < victim->last_use)) victim = b.get();
+        if (!victim) return nullptr;
+        release_buffer(S, victim);
+    }
+    return allocate_buffer(S, cap);
+}
+
+// ---- launches ----------------------------------------------------------------------------
+
+hipError_t enqueue(const Request* r, const Buffer* b, hipStream_t s) {
+    const int64_t B = r->B;
+    const BufLayout lay(b->cap);
+    double* d_theta = (double*)b->dev;
+    double* d_lnl = (double*)(b->dev + lay.theta);
+    double* d_grad = (double*)(b->dev + lay.theta + lay.lnl);
+    char* ws = b->dev + lay.theta + lay.lnl + lay.grad;
+    double* rec = (double*)ws;
+    double* jac = r->grad ? (double*)(ws + align_up(B * kRecStride * (int64_t)sizeof(double))) : nullptr;
+    const bool mixed = r->precision == RBL_MIXED;
+    hipError_t e = hipMemcpyAsync(d_theta, b->h_theta, (size_t)(B * 13 * sizeof(double)), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    e = launch_chain_setup(d_theta, B, r->ev->net, r->ev->ref, rec, jac, s);
+    if (e != hipSuccess) return e;
+    e = r->grad ? launch_loglike_grad(r->ev->dev, rec, jac, B, mixed, d_lnl, d_grad, s)
+                : launch_loglike(r->ev->dev, rec, B, mixed, d_lnl, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(b->h_out, d_lnl, (size_t)(B * sizeof(double)), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && r->grad)
+        e = hipMemcpyAsync(b->h_out + b->cap, d_grad, (size_t)(B * 13 * sizeof(double)), hipMemcpyDeviceToHost, s);
+    return e;
+}
+
+hipGraphExec_t capture(const Request* r, const Buffer* b, hipStream_t s) {
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    const hipError_t e = enqueue(r, b, s);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s, &g);
+    hipGraphExec_t ex = nullptr;
+    if (e == hipSuccess && e2 == hipSuccess && g) {
+        if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) ex = nullptr;
+    }
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return ex;
+}
+
+void complete(rbl_server* S, Request* r, int status) {
+    r->info.status = status;
+    r->info.t_done_ns = now_ns();
+    r->state = 2;
+    S->users[r->event]--;
+    S->st.completed++;
+}
+
+void launch(rbl_server* S, Request* r, Buffer* b, int si) {
+    Slot& sl = S->slots[si];
+    std::memcpy(b->h_theta, r->theta, (size_t)(r->B * 13 * sizeof(double)));
+    r->buf = b;
+    r->state = 1;
+    r->info.stream = si;
+    r->info.t_admit_ns = now_ns();
+    b->busy = true;
+    hipError_t e = hipSuccess;
+    hipGraphExec_t ex = nullptr;
+    if (!(S->flags & RBL_SERVE_NO_GRAPHS)) {
+        const GraphKey k{b->id, r->event, r->B, r->precision, r->grad ? 1 : 0};
+        auto it = S->graphs.find(k);
+        if (it != S->graphs.end()) {
+            ex = it->second;
+        } else if ((ex = capture(r, b, sl.s)) != nullptr) {
+            S->graphs.emplace(k, ex);
+            S->st.graphs++;
+        }
+    }
+    if (ex) {
+        e = hipGraphLaunch(ex, sl.s);
+        S->st.graph_launches++;
+    } else {
+        e = enqueue(r, b, sl.s);
+        S->st.plain_launches++;
+    }
+    if (e == hipSuccess) e = hipEventRecord(sl.done, sl.s);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(sl.s);
+        b->busy = false;
+        complete(S, r, hip_fail(e, "rbl_server: launch"));
+        S->cv_done.notify_all();
+        return;
+    }
+    sl.cur = r;
+    S->st.in_flight++;
+    S->st.max_in_flight = std::max(S->st.max_in_flight, S->st.in_flight);
+}
+
+bool reap(rbl_server* S) {
+    bool any = false;
+    for (auto& sl : S->slots) {
+        if (!sl.cur) continue;
+        const hipError_t q = hipEventQuery(sl.done);
+        if (q == hipErrorNotReady) continue;
+        Request* r = sl.cur;
+        Buffer* b = r->buf;
+        int status = RBL_OK;
+        if (q == hipSuccess) {
+            std::memcpy(r->lnl, b->h_out, (size_t)(r->B * sizeof(double)));
+            if (r->grad) std::memcpy(r->gout, b->h_out + b->cap, (size_t)(r->B * 13 * sizeof(double)));
+        } else {
+            status = hip_fail(q, "rbl_server: request");
+        }
+        b->busy = false;
+        b->last_use = now_ns();
+        sl.cur = nullptr;
+        S->st.in_flight--;
+        complete(S, r, status);
+        any = true;
+    }
+    if (any) S->cv_done.notify_all();
+    return any;
+}
+
+void admit(rbl_server* S) {
+    while (!S->queue.empty()) {
+        int si = -1;
+        for (int i = 0; i < (int)S->slots.size(); ++i)
+            if (!S->slots[i].cur) {
+                si = i;
+                break;
+            }
+        if (si < 0) return;
+        Request* r = S->queue.front();
+        Buffer* b = acquire(S, r->B);
+        if (!b) {
+            if (!r->counted_wait) {
+                r->counted_wait = true;
+                S->st.admission_waits++;
+            }
+            return;
+        }
+        S->queue.pop_front();
+        launch(S, r, b, si);
+    }
+}
+
+void worker_main(rbl_server* S) {
+    (void)hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        reap(S);
+        admit(S);
+        if (S->st.in_flight > 0) {
+            lk.unlock();
+            std::this_thread::yield();
+            lk.lock();
+            continue;
+        }
+        if (!S->queue.empty()) {
+            // nothing runs and the head still does not fit: it never will
+            Request* r = S->queue.front();
+            S->queue.pop_front();
+            complete(S, r, fail(RBL_ENOMEM, "rbl_server: request buffer does not fit in the HBM budget"));
+            S->cv_done.notify_all();
+            continue;
+        }
+        if (S->stop) break;
+        S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+    }
+}
+
+}  // namespace
+
+extern "C" int64_t rbl_clock_ns(void) { return now_ns(); }
+
+extern "C" int rbl_server_create(int64_t hbm_budget_bytes, int32_t n_streams, uint32_t flags, rbl_server** out) {
+    if (!out) return fail(RBL_EINVAL, "rbl_server_create: null output");
+    *out = nullptr;
+    if (hbm_budget_bytes <= 0) return fail(RBL_EINVAL, "rbl_server_create: budget must be positive");
+    if (n_streams < 1 || n_streams > kMaxStreams) return fail(RBL_EINVAL, "rbl_server_create: n_streams not in 1..16");
+    auto S = std::make_unique<rbl_server>();
+    S->budget = hbm_budget_bytes;
+    S->flags = flags;
+    hipError_t e = hipGetDevice(&S->device);
+    if (e != hipSuccess) return hip_fail(e, "rbl_server_create: device");
+    S->slots.resize((size_t)n_streams);
+    for (auto& sl : S->slots) {
+        if ((e = hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess) {
+            for (auto& t : S->slots) {
+                if (t.s) (void)hipStreamDestroy(t.s);
+                if (t.done) (void)hipEventDestroy(t.done);
+            }
+            return hip_fail(e, "rbl_server_create: streams");
+        }
+    }
+    S->st.budget_bytes = hbm_budget_bytes;
+    rbl_server* p = S.release();
+    p->worker = std::thread(worker_main, p);
+    *out = p;
+    return RBL_OK;
+}
+
+extern "C" int rbl_server_add_event(rbl_server* S, const rbl_event* ev, int32_t* event_id) {
+    if (!S || !ev || !event_id) return fail(RBL_EINVAL, "rbl_server_add_event: null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->resident + ev->footprint + S->buffer_bytes > S->budget)
+        return fail(RBL_ENOMEM, "rbl_server_add_event: event footprint exceeds the HBM budget");
+    const int32_t id = S->next_event++;
+    S->events[id] = ev;
+    S->users[id] = 0;
+    S->resident += ev->footprint;
+    *event_id = id;
+    return RBL_OK;
+}
+
+extern "C" int rbl_server_remove_event(rbl_server* S, int32_t event_id) {
+    if (!S) return fail(RBL_EINVAL, "rbl_server_remove_event: null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->events.find(event_id);
+    if (it == S->events.end()) return fail(RBL_EINVAL, "rbl_server_remove_event: unknown event");
+    if (S->users[event_id] > 0) return fail(RBL_EINVAL, "rbl_server_remove_event: requests pending");
+    S->resident -= it->second->footprint;
+    S->events.erase(it);
+    S->users.erase(event_id);
+    drop_graphs_if(S, 0, event_id);
+    return RBL_OK;
+}
+
+extern "C" int rbl_server_submit(rbl_server* S, int32_t event_id, const double* theta_host, int64_t B,
+                                 int32_t precision, int32_t with_grad, double* lnl_host, double* grad_host,
+                                 int64_t t_arrival_ns, int64_t* ticket) {
+    const int64_t t_sub = now_ns();
+    if (!S || !ticket) return fail(RBL_EINVAL, "rbl_server_submit: null argument");
+    if (B < 0 || B > ((int64_t)1 << 31)) return fail(RBL_EINVAL, "rbl_server_submit: B out of range");
+    if (precision != RBL_FP64 && precision != RBL_MIXED) return fail(RBL_EINVAL, "rbl_server_submit: unknown precision");
+    if (B > 0 && (!theta_host || !lnl_host || (with_grad && !grad_host)))
+        return fail(RBL_EINVAL, "rbl_server_submit: null theta or output");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->events.find(event_id);
+    if (it == S->events.end()) return fail(RBL_EINVAL, "rbl_server_submit: unknown event");
+    if (B > 0 && S->resident + BufLayout(class_of(B)).total > S->budget)
+        return fail(RBL_ENOMEM, "rbl_server_submit: request buffer can never fit in the HBM budget");
+    auto* r = new Request();
+    r->ticket = S->next_ticket++;
+    r->event = event_id;
+    r->ev = it->second;
+    r->theta = theta_host;
+    r->B = B;
+    r->precision = precision;
+    r->grad = with_grad != 0;
+    r->lnl = lnl_host;
+    r->gout = grad_host;
+    r->info.t_arrival_ns = t_arrival_ns > 0 ? t_arrival_ns : t_sub;
+    r->info.stream = -1;
+    S->reqs[r->ticket] = r;
+    S->users[event_id]++;
+    S->st.submitted++;
+    *ticket = r->ticket;
+    if (B == 0) {
+        r->info.t_admit_ns = t_sub;
+        complete(S, r, RBL_OK);
+        return RBL_OK;
+    }
+    S->queue.push_back(r);
+    S->cv_work.notify_one();
+    return RBL_OK;
+}
+
+extern "C" int rbl_server_wait(rbl_server* S, int64_t ticket, rbl_request_info* info) {
+    if (!S) return fail(RBL_EINVAL, "rbl_server_wait: null server");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(RBL_EINVAL, "rbl_server_wait: unknown ticket");
+    Request* r = it->second;
+    S->cv_done.wait(lk, [&] { return r->state == 2; });
+    if (info) *info = r->info;
+    const int status = r->info.status;
+    S->reqs.erase(it);
+    delete r;
+    if (status != RBL_OK) return fail(status, "rbl_server_wait: request failed");
+    return RBL_OK;
+}
+
+extern "C" int rbl_server_get_stats(const rbl_server* S, rbl_server_stats* out) {
+    if (!S || !out) return fail(RBL_EINVAL, "rbl_server_get_stats: null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    *out = S->st;
+    out->budget_bytes = S->budget;
+    out->resident_bytes = S->resident;
+    out->buffer_bytes = S->buffer_bytes;
+    out->queued = (int64_t)S->queue.size();
+    return RBL_OK;
+}
+
+extern "C" void rbl_server_destroy(rbl_server* S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv_work.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    for (auto& kv : S->graphs) (void)hipGraphExecDestroy(kv.second);
+    S->graphs.clear();
+    for (auto& b : S->bufs) free_buffer_memory(b.get());
+    S->bufs.clear();
+    for (auto& sl : S->slots) {
+        (void)hipStreamDestroy(sl.s);
+        (void)hipEventDestroy(sl.done);
+    }
+    for (auto& kv : S->reqs) delete kv.second;
+    delete S;
+}

@@ -95,3 +95,23 @@ def test_null_arguments():
     assert lib.rbl_loglike_grad(None, None, 1, 0, None, None, None, None) == -1
     assert lib.rbl_bin_edges(20.0, 1.0, 10, 20, None) == -1
     assert lib.rbl_workspace_bytes(None, 10, 0) == 0
+
+
+def test_server_argument_errors_without_gpu():
+    """Argument checks of the server API are synchronous and need no device."""
+    import ctypes
+    from paper_2404_11397_amd import _lib
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.rbl_server_create(0, 4, 0, ctypes.byref(h)) == -1
+    assert L.rbl_server_create(1 << 30, 0, 0, ctypes.byref(h)) == -1
+    assert L.rbl_server_create(1 << 30, 17, 0, ctypes.byref(h)) == -1
+    assert L.rbl_server_create(1 << 30, 4, 0, None) == -1
+    t = ctypes.c_int64()
+    assert L.rbl_server_submit(None, 0, None, 1, 0, 1, None, None, 0, ctypes.byref(t)) == -1
+    assert L.rbl_server_wait(None, 1, None) == -1
+    assert L.rbl_server_add_event(None, None, None) == -1
+    L.rbl_server_destroy(None)
+    a, b = L.rbl_clock_ns(), L.rbl_clock_ns()
+    assert 0 < a <= b
+    assert L.rbl_event_footprint_bytes(None) == 0

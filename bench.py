@@ -23,28 +23,40 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
+import synth  # noqa: E402
+
 # Peaks of one MI355X (vendor figures): FP64 vector 78.6 TFLOP/s, HBM 8 TB/s.
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
 def flops_per_eval(n_nodes, n_det, grad, waveform="taylorf2"):
-    """Counted algorithmic FP64 flops of one chain's relative-binned lnL (+ gradient).
+    """Algorithmic FP64 flops of one chain's relative-binned lnL (+ gradient), counted
+    from the operations the method needs (FMA = 2, add/mul = 1, a division 10, an exp
+    or log 20, each sin/cos pair of a phase in revolutions at its minimal polynomial
+    cost: exact reduction 2 + 17 FMA = 36).
 
-    Counting FMA = 2, add/mul = 1, and each sin/cos pair of a phase in revolutions at
-    its minimal polynomial cost (exact reduction 2 + 17 FMA = 36).  Per edge: TaylorF2
-    phase in the separable basis (8 mul + 10 FMA = 28); per edge and detector: phase
-    with delay (2), sin/cos (36), ratio K u (6), the binned terms and their sums (14).
-    The gradient adds per edge and detector the edge adjoint and its accumulations (26)
-    and per edge the basis accumulations (20).  Per chain: setup 600 (lnL) or 6000
-    (with the 13-tangent Jacobian).
+    Per edge and detector: phase with delay (2), sin/cos (36), ratio K u (6), the binned
+    terms and their sums (14); the gradient adds the edge adjoint and its sums (26).
+    Per edge, TaylorF2: phase in the separable basis (8 mul + 10 FMA = 28); gradient:
+    basis accumulations (20).  IMRPhenomD_NRTidalv2: point-particle phase, NRTidal Pade
+    phase and tidal amplitude with its power-law term (110) and the amplitude ratio
+    (2 per detector); gradient: the node-parameter adjoint (180).  Per chain: setup 600
+    (TaylorF2) / 1500 (NRTidalv2) for lnL, 6000 / 18000 with the Jacobian.
     """
-    per_node = 28 + n_det * (2 + 36 + 6 + 14)
-    setup = 600
-    if grad:
-        per_node += n_det * 26 + 20
-        setup = 6000
-    return n_nodes * per_node + setup
+    if waveform == "taylorf2":
+        per_node = 28 + n_det * (2 + 36 + 6 + 14)
+        setup = 600
+        if grad:
+            per_node += n_det * 26 + 20
+            setup = 6000
+    else:
+        per_node = 110 + n_det * (2 + 36 + 2 + 6 + 14)
+        setup = 1500
+        if grad:
+            per_node += n_det * 26 + 180
+            setup = 18000
+    return n_nodes * per_node, setup
 
 
 def parse():
@@ -55,6 +67,9 @@ def parse():
     p.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--no-nrtv2", action="store_true", help="skip the IMRPhenomD_NRTidalv2 forms")
+    p.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    p.add_argument("--serve-requests", type=int, default=2000)
     return p.parse_args()
 
 
@@ -64,7 +79,15 @@ def build_event(torch, workload):
     w = synth.workload(workload)
     dev = torch.device("cuda:0")
     edges = bin_edges(w["f_low"], w["delta_f"], w["n_freq"], w["n_bins"])
-    th0 = w["theta_inj"]
+    th0 = w["theta_inj"].copy()
+    psd_d = torch.as_tensor(w["psd"], device=dev)
+    if np.isnan(th0[6]):  # distance set by an SNR target: <h, h> scales as 1/dL^2
+        th0[6] = 1.0
+        h1 = strain(w["waveform"], w["tensors"], w["vertices"], w["gmst"], w["f_low"], w["delta_f"],
+                    w["n_freq"], th0, device=dev)
+        rho1 = float(torch.sqrt(4.0 * w["delta_f"] * (h1.abs() ** 2 / psd_d).sum()))
+        th0[6] = rho1 / w["snr"]
+        w["theta_inj"] = th0
     h = strain(w["waveform"], w["tensors"], w["vertices"], w["gmst"], w["f_low"], w["delta_f"],
                w["n_freq"], th0, device=dev)
     data = h + torch.as_tensor(w["noise"], device=dev)
@@ -125,6 +148,141 @@ def summary_pass(torch, w, edges, data, psd, repeats=3):
     return ms / n * 1e3
 
 
+def forms_on(torch, ev, theta, lnl, grad, ws, steps, with_grad=True):
+    """evals/s and HIP-event kernel times of lnL and lnL+grad, FP64 and mixed."""
+    B = theta.shape[0]
+    out = {}
+    combos = [("lnl", False), ("lnl_grad", True)] if with_grad else [("lnl", False)]
+    for tag, g in combos:
+        for prec in ("fp64", "mixed"):
+            if g:
+                fn = lambda p=prec: ev.loglike_grad(theta, p, out=(lnl, grad), workspace=ws)  # noqa: E731
+            else:
+                fn = lambda p=prec: ev.loglike(theta, p, out=lnl[:B], workspace=ws)  # noqa: E731
+            el, ku, su = time_calls(torch, fn, steps, 3)
+            out[f"{tag}_{prec}"] = {"evals_per_s": B * steps / el, "us_per_call": el / steps * 1e6,
+                                    "kernel_us": ku, "setup_us": su}
+    return out
+
+
+def nrtv2_forms(torch, steps):
+    """IMRPhenomD_NRTidalv2 on the 3-detector 256 s data: lnL+grad at 8192 chains and
+    lnL at 16384 chains, FP64 and mixed, with the estimated VALU fraction."""
+    ev, w, edges, data = build_event(torch, "nrtv2_3det_256s_grad8192")
+    nd, n_nodes = len(w["tensors"]), w["n_bins"] + 1
+    res = {"workload": "IMRPhenomD_NRTidalv2: 3 det, 256 s, 20-2048 Hz (519169 pts/det), 1000 bins, SNR 12 "
+                       "injection; lnL+grad at 8192 chains (GW190425 prior, Mc window +-0.0025), lnL at 16384"}
+    th = torch.as_tensor(w["theta"], device="cuda:0")
+    B = th.shape[0]
+    lnl = torch.empty(2 * B, dtype=torch.float64, device="cuda:0")
+    grad = torch.empty((B, 13), dtype=torch.float64, device="cuda:0")
+    ws = ev.workspace(2 * B, with_grad=True)
+    f = forms_on(torch, ev, th, lnl[:B], grad, ws, steps)
+    w3 = synth.workload("nrtv2_3det_256s")
+    th3 = torch.as_tensor(w3["theta"], device="cuda:0")
+    f.update({k + "_16384": v for k, v in forms_on(torch, ev, th3, lnl, grad, ws, steps, with_grad=False).items()})
+    for k, v in f.items():
+        g = "grad" in k
+        per, _ = flops_per_eval(n_nodes, nd, grad=g, waveform="phenomd_nrtv2")
+        nb = th3.shape[0] if k.endswith("16384") else B
+        v["est_tflops"] = per * nb / (v["kernel_us"] * 1e-6) / 1e12
+        v["est_frac_fp64_peak"] = v["est_tflops"] / PEAK_FP64_TFLOPS
+    psd = torch.as_tensor(w["psd"], device="cuda:0")
+    su = summary_pass(torch, w, edges, data, psd)
+    nbytes = w["n_freq"] * nd * 24
+    res["forms"] = f
+    res["summary_pass"] = {"us": su, "bytes": nbytes, "GB_per_s": nbytes / (su * 1e-6) / 1e9,
+                           "frac_of_hbm_peak": nbytes / (su * 1e-6) / 1e9 / PEAK_HBM_GBS}
+    return res
+
+
+def build_serving_events(torch):
+    from paper_2404_11397_amd import Event, bin_edges, strain
+    events, pools, specs = [], [], []
+    dev = torch.device("cuda:0")
+    for eid in range(synth.N_SERVE_EVENTS):
+        sp = synth.serving_event(eid)
+        x = synth.serving_inputs(sp)
+        edges = bin_edges(x["f_low"], x["delta_f"], x["n_freq"], sp["n_bins"])
+        h = strain(sp["waveform"], x["tensors"], x["vertices"], sp["gmst"], x["f_low"], x["delta_f"], x["n_freq"],
+                   sp["theta_inj"], device=dev)
+        data = h + torch.as_tensor(x["noise"], device=dev)
+        psd = torch.as_tensor(x["psd"], device=dev)
+        events.append(Event(data, psd, x["tensors"], x["vertices"], sp["gmst"], x["f_low"], x["delta_f"],
+                            sp["theta_inj"], edges, waveform=sp["waveform"], device=dev))
+        pools.append([np.ascontiguousarray(p) for p in x["pool"]])
+        specs.append(sp)
+        del data, psd, h
+    return events, pools, specs
+
+
+def run_stream(srv, ids, pools, n, rate, precision):
+    """Submit n requests at Poisson arrival times; latency = done - arrival (host clock)."""
+    import queue
+    import threading
+    from paper_2404_11397_amd import clock_ns
+    offs, evs, pidx = synth.serving_stream(n, rate)
+    q = queue.Queue()
+    lat = np.empty(n)
+    done = np.empty(n, dtype=np.int64)
+    chains = np.array([pools[e][k].shape[0] for e, k in zip(evs, pidx)])
+
+    def waiter():
+        for i in range(n):
+            _, _, info = srv.wait(q.get())
+            lat[i] = (info["t_done_ns"] - info["t_arrival_ns"]) * 1e-6
+            done[i] = info["t_done_ns"]
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = clock_ns() + 5_000_000
+    for i in range(n):
+        ta = t0 + int(offs[i] * 1e9)
+        while True:
+            d = ta - clock_ns()
+            if d <= 0:
+                break
+            if d > 400_000:
+                time.sleep((d - 300_000) * 1e-9)
+        q.put(srv.submit(ids[evs[i]], pools[evs[i]][pidx[i]], precision=precision, grad=True, t_arrival_ns=ta))
+    th.join()
+    span = (done.max() - t0) * 1e-9
+    return {"rate_hz": rate, "requests": n, "precision": precision,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "evals_per_s": float(chains.sum() / span),
+            "offered_evals_per_s": float(chains.sum() / (offs[-1] + 1e-9))}
+
+
+def serving(torch, n_requests):
+    """The multi-event request stream: 64 resident events, Poisson arrivals, lnL+grad
+    per request.  Served by the library's request server (mixed precision, 4 streams,
+    graph replays) and, for comparison, one FIFO with FP64 plain launches."""
+    from paper_2404_11397_amd import Server
+    t_build = time.perf_counter()
+    events, pools, specs = build_serving_events(torch)
+    t_build = time.perf_counter() - t_build
+    budget = 32 << 30
+    res = {"workload": f"{synth.N_SERVE_EVENTS} resident events (1-3 det, 32-256 s, 100-1000 bins, TaylorF2 / "
+                       f"IMRPhenomD_NRTidalv2, 256-4096 chains each); Poisson {synth.SERVE_RATE_HZ:.0f} req/s of "
+                       "lnL+grad requests",
+           "events_build_s": t_build, "hbm_budget_bytes": budget}
+    for tag, streams, graphs, prec in (("server", 4, True, "mixed"), ("baseline_fifo_fp64_plain", 1, False, "fp64")):
+        with Server(budget, n_streams=streams, graphs=graphs) as srv:
+            ids = [srv.add_event(e) for e in events]
+            warm = [srv.submit(ids[e], pools[e][k], precision=prec) for e in range(len(events))
+                    for k in range(len(pools[e]))]
+            for t in warm:
+                srv.wait(t)
+            r = run_stream(srv, ids, pools, n_requests, synth.SERVE_RATE_HZ, prec)
+            if tag == "server":
+                r["saturation"] = [run_stream(srv, ids, pools, n_requests, rate, prec) for rate in (2000.0, 20000.0)]
+            r["stats"] = srv.stats()
+            r["streams"], r["graphs"] = streams, graphs
+            res[tag] = r
+    res["resident_bytes"] = res["server"]["stats"]["resident_bytes"]
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -134,7 +292,7 @@ def main():
         sys.exit(2)
     import torch
 
-    workload = "cfg4_tf2"
+    workload = "tf2_3det_128s_grad8192"
     ev, w, edges, data = build_event(torch, workload)
     theta_np = w["theta"]
     B = theta_np.shape[0]
@@ -157,17 +315,7 @@ def main():
         lat.append((time.perf_counter() - t1) * 1e3)
     lat = np.array(lat)
 
-    # the other forms on the same batch (context beside the headline)
-    forms = {}
-    k = max(20, args.steps // 4)
-    for name, prec, g in (("lnl_fp64", "fp64", False), ("lnl_mixed", "mixed", False),
-                          ("lnl_grad_fp64", "fp64", True), ("lnl_grad_mixed", "mixed", True)):
-        if g:
-            fn = lambda p=prec: ev.loglike_grad(theta, p, out=(lnl, grad), workspace=ws)  # noqa: E731
-        else:
-            fn = lambda p=prec: ev.loglike(theta, p, out=lnl, workspace=ws)  # noqa: E731
-        el, ku, su = time_calls(torch, fn, k, 3)
-        forms[name] = {"evals_per_s": B * k / el, "us_per_call": el / k * 1e6, "kernel_us": ku, "setup_us": su}
+    forms = forms_on(torch, ev, theta, lnl, grad, ws, max(20, args.steps // 4))
 
     nd = len(w["tensors"])
     psd = torch.as_tensor(w["psd"], device="cuda:0")
@@ -175,8 +323,7 @@ def main():
     summ_bytes = w["n_freq"] * nd * 24  # data (complex128) + PSD (float64) per grid point and detector
 
     n_nodes = w["n_bins"] + 1
-    fl = flops_per_eval(n_nodes, nd, grad=True)
-    fl_kernel = fl - 6000
+    fl_kernel, _ = flops_per_eval(n_nodes, nd, grad=True)
     achieved = fl_kernel * B / (kern_us * 1e-6) / 1e12
     out = {
         "metric": "relative-binned lnL+grad evals/sec (13-param BNS, 3 det); p50/p99 latency",
@@ -190,7 +337,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f64-phase/f32",
-        "data": "synthetic (library TaylorF2 injection + seeded Gaussian noise, analytic PSD)",
+        "data": "synthetic (library waveform injections + seeded Gaussian noise, analytic PSD)",
         "config": {"workload": "TaylorF2 lnL+grad: 3 det, 128 s, 20-2048 Hz (259585 pts/det), "
                                "500 bins, 8192 chains, GW170817 prior",
                    "global_batch": B, "n_bins": w["n_bins"], "n_det": nd, "n_freq": w["n_freq"],
@@ -205,6 +352,16 @@ def main():
         "summary_pass": {"us": summ_us, "bytes": summ_bytes, "GB_per_s": summ_bytes / (summ_us * 1e-6) / 1e9,
                          "frac_of_hbm_peak": summ_bytes / (summ_us * 1e-6) / 1e9 / PEAK_HBM_GBS},
     }
+    if not args.no_nrtv2:
+        out["nrtv2"] = nrtv2_forms(torch, max(20, args.steps // 4))
+    if not args.no_serve:
+        sv = serving(torch, args.serve_requests)
+        out["serving"] = sv
+        out["latency_ms"] = {"p50": sv["server"]["p50_ms"], "p99": sv["server"]["p99_ms"],
+                             "what": "request latency (arrival to results in host memory) under the "
+                                     "multi-event Poisson stream, request server",
+                             "batch_call_p50": float(np.percentile(lat, 50)),
+                             "batch_call_p99": float(np.percentile(lat, 99))}
     if not args.no_cpu_baseline:
         data_host = data.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(w, edges, data_host, theta_np, args.cpu_seconds)

@@ -4,8 +4,7 @@ as used by the oracle.
 The paper names the model but prints none of it, and the calibration tables it rests
 on (the IMRPhenomD phenomenological fits, the NRTidalv2 fits) are not available here.
 This module therefore implements the model's *structure* with every coefficient fixed
-by a stated rule (each rule is listed in the design doc; parity with the published model
-is unpinned):
+by a stated rule (parity with the published model is unpinned):
 
 Point-particle phase, piecewise in Mf = M f (M total mass in seconds):
   inspiral      Mf < f1 = 0.018     TaylorF2 (3.5PN point particle + aligned spins,

@@ -16,4 +16,12 @@ from .inputs import (  # noqa: F401
     draw_theta,
     PRIORS,
 )
-from .configs import CONFIGS, workload  # noqa: F401
+from .configs import (  # noqa: F401
+    CONFIGS,
+    workload,
+    N_SERVE_EVENTS,
+    SERVE_RATE_HZ,
+    serving_event,
+    serving_inputs,
+    serving_stream,
+)

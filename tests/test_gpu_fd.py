@@ -19,7 +19,7 @@ def _cuda(a):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-@pytest.mark.parametrize("name", ["cfg2", "cfg3"])
+@pytest.mark.parametrize("name", ["tf2_3det_128s", "nrtv2_3det_256s"])
 def test_gradient_matches_central_differences(name):
     ev, _ = oracle_event(name, batch=8)
     gev = gpu_event(ev)

@@ -40,29 +40,29 @@ def test_strain_nrtv2_matches_oracle(taper):
 
 
 @pytest.fixture(scope="module")
-def cfg3():
-    say("[cfg3] building oracle event (519169 points x 3 detectors)")
-    ev, w = oracle_event("cfg3")
-    say("[cfg3] building GPU event")
+def nrtv2_3det_256s():
+    say("[nrtv2_3det_256s] building oracle event (519169 points x 3 detectors)")
+    ev, w = oracle_event("nrtv2_3det_256s")
+    say("[nrtv2_3det_256s] building GPU event")
     gev = gpu_event(ev)
     return ev, w, gev
 
 
-def test_summary_matches_oracle_cfg3(cfg3):
-    ev, _, gev = cfg3
+def test_summary_matches_oracle_nrtv2_3det_256s(nrtv2_3det_256s):
+    ev, _, gev = nrtv2_3det_256s
     s = gev.summary()
     ref = ev.summary
     fields = [ref["A0"].real, ref["A0"].imag, ref["A1"].real, ref["A1"].imag, ref["B0"], ref["B1"]]
     for j, want in enumerate(fields):
         err = np.abs(s[:, :, j] - want).max() / np.abs(want).max()
-        say("cfg3 summary field", j, "rel err", err)
+        say("nrtv2_3det_256s summary field", j, "rel err", err)
         assert err < 1e-10
 
 
-def test_loglike_parity_cfg3_sampled(cfg3):
+def test_loglike_parity_nrtv2_3det_256s_sampled(nrtv2_3det_256s):
     """Full batch (16384 prior draws) in the launch shape the benchmark uses; the
     oracle checks a seeded sample, FP64 and mixed."""
-    ev, w, gev = cfg3
+    ev, w, gev = nrtv2_3det_256s
     th = w["theta"]
     t = _cuda(th)
     lnl = gev.loglike(t).cpu().numpy()
@@ -72,16 +72,16 @@ def test_loglike_parity_cfg3_sampled(cfg3):
     want = L.loglike_rb(ev, th[idx])
     scale = np.maximum(np.abs(want), rb_condition_scale(ev, th[idx]))
     err = np.abs(lnl[idx] - want) / scale
-    say("cfg3 FP64 lnL max scaled err", err.max())
+    say("nrtv2_3det_256s FP64 lnL max scaled err", err.max())
     assert np.all(err <= 1e-8)
     em = np.abs(lm[idx] - want)
-    say("cfg3 mixed lnL max abs err", em.max())
+    say("nrtv2_3det_256s mixed lnL max abs err", em.max())
     assert np.all(em <= 1e-2)
 
 
-def test_loglike_parity_cfg3_near_reference(cfg3):
+def test_loglike_parity_nrtv2_3det_256s_near_reference(nrtv2_3det_256s):
     """Chains near the posterior (where lnL is large), FP64 and mixed."""
-    ev, _, gev = cfg3
+    ev, _, gev = nrtv2_3det_256s
     th = near_draws(ev.theta_ref, 256, 44, scale=0.3)
     t = _cuda(th)
     lnl = gev.loglike(t).cpu().numpy()
@@ -89,13 +89,13 @@ def test_loglike_parity_cfg3_near_reference(cfg3):
     want = L.loglike_rb(ev, th)
     scale = np.maximum(np.abs(want), rb_condition_scale(ev, th))
     err = np.abs(lnl - want) / scale
-    say("cfg3 near-theta0 FP64 scaled err", err.max(), "mixed abs err", np.abs(lm - want).max())
+    say("nrtv2_3det_256s near-theta0 FP64 scaled err", err.max(), "mixed abs err", np.abs(lm - want).max())
     assert np.all(err <= 1e-8)
     assert np.all(np.abs(lm - want) <= 1e-2)
 
 
-def test_label_swap_nrtv2_on_gpu(cfg3):
-    ev, w, gev = cfg3
+def test_label_swap_nrtv2_on_gpu(nrtv2_3det_256s):
+    ev, w, gev = nrtv2_3det_256s
     th = near_draws(ev.theta_ref, 32, 45)
     sw = th.copy()
     sw[:, 1] = 1 / th[:, 1]
@@ -158,8 +158,8 @@ def _grad_rel(g, want):
     return np.abs(gs - ws).max(axis=1) / np.abs(ws).max(axis=1)
 
 
-def test_gradient_parity_cfg3_near_reference(cfg3):
-    ev, _, gev = cfg3
+def test_gradient_parity_nrtv2_3det_256s_near_reference(nrtv2_3det_256s):
+    ev, _, gev = nrtv2_3det_256s
     th = near_draws(ev.theta_ref, 64, 47, scale=0.3)
     lnl, g = gev.loglike_grad(_cuda(th))
     lnl, g = lnl.cpu().numpy(), g.cpu().numpy()
@@ -167,13 +167,13 @@ def test_gradient_parity_cfg3_near_reference(cfg3):
     scale = np.maximum(np.abs(wl), rb_condition_scale(ev, th))
     assert np.all(np.abs(lnl - wl) <= 1e-8 * scale)
     rel = _grad_rel(g, wg)
-    say("cfg3 near-theta0 grad max rel err", rel.max())
+    say("nrtv2_3det_256s near-theta0 grad max rel err", rel.max())
     assert np.all(rel <= 1e-5)
 
 
-def test_gradient_parity_cfg4_nrtv2_sampled():
-    """8192 prior draws on the cfg3 data (the differentiation workload), oracle on a sample."""
-    ev, w = oracle_event("cfg4_nrtv2")
+def test_gradient_parity_nrtv2_3det_256s_grad8192_sampled():
+    """8192 prior draws on the nrtv2_3det_256s data (the differentiation workload), oracle on a sample."""
+    ev, w = oracle_event("nrtv2_3det_256s_grad8192")
     gev = gpu_event(ev)
     th = w["theta"]
     lnl, g = gev.loglike_grad(_cuda(th))
@@ -184,11 +184,11 @@ def test_gradient_parity_cfg4_nrtv2_sampled():
     scale = np.maximum(np.abs(wl), rb_condition_scale(ev, th[idx]))
     assert np.all(np.abs(lnl[idx] - wl) <= 1e-8 * scale)
     rel = _grad_rel(g[idx], wg)
-    say("cfg4_nrtv2 grad max rel err", rel.max())
+    say("nrtv2_3det_256s_grad8192 grad max rel err", rel.max())
     assert np.all(rel <= 1e-5)
     lm, gm = gev.loglike_grad(_cuda(th), precision="mixed")
     lm, gm = lm.cpu().numpy(), gm.cpu().numpy()
-    say("cfg4_nrtv2 mixed lnL max abs err", np.abs(lm[idx] - wl).max(), "grad rel", _grad_rel(gm[idx], wg).max())
+    say("nrtv2_3det_256s_grad8192 mixed lnL max abs err", np.abs(lm[idx] - wl).max(), "grad rel", _grad_rel(gm[idx], wg).max())
     assert np.all(np.abs(lm[idx] - wl) <= 1e-2)
     assert np.all(_grad_rel(gm[idx], wg) <= 1e-3)
 

@@ -22,17 +22,17 @@ def _cuda(a):
 
 
 @pytest.fixture(scope="module")
-def cfg1():
-    say("[cfg1] building oracle event")
-    ev, w = oracle_event("cfg1")
-    say("[cfg1] building GPU event")
+def tf2_1det_32s():
+    say("[tf2_1det_32s] building oracle event")
+    ev, w = oracle_event("tf2_1det_32s")
+    say("[tf2_1det_32s] building GPU event")
     gev = gpu_event(ev, keep_grid=True)
     return ev, w, gev
 
 
-def test_strain_matches_oracle(cfg1):
+def test_strain_matches_oracle(tf2_1det_32s):
     from paper_2404_11397_amd import strain
-    ev, w, _ = cfg1
+    ev, w, _ = tf2_1det_32s
     th = w["theta"][3]
     h_gpu = strain("taylorf2", ev.tensors, ev.vertices, ev.gmst, ev.f[0], ev.delta_f, len(ev.f), th).cpu().numpy()
     h_ref = np.stack([x[0] for x in W.strain(ev.f, th, ev.tensors, ev.vertices, ev.gmst, "taylorf2")])
@@ -41,8 +41,8 @@ def test_strain_matches_oracle(cfg1):
     assert err < 1e-10
 
 
-def test_summary_matches_oracle(cfg1):
-    ev, _, gev = cfg1
+def test_summary_matches_oracle(tf2_1det_32s):
+    ev, _, gev = tf2_1det_32s
     s = gev.summary()
     ref = ev.summary
     fields = [ref["A0"].real, ref["A0"].imag, ref["A1"].real, ref["A1"].imag, ref["B0"], ref["B1"], ref["B2"]]
@@ -54,31 +54,31 @@ def test_summary_matches_oracle(cfg1):
         assert err < 1e-10, j
 
 
-def test_loglike_rb_parity_cfg1(cfg1):
-    ev, w, gev = cfg1
+def test_loglike_rb_parity_tf2_1det_32s(tf2_1det_32s):
+    ev, w, gev = tf2_1det_32s
     th = w["theta"]
     got = gev.loglike(_cuda(th)).cpu().numpy()
     want = L.loglike_rb(ev, th)
     scale = np.maximum(np.abs(want), rb_condition_scale(ev, th))
     err = np.abs(got - want) / scale
-    say("cfg1 RB lnL max scaled err", err.max())
+    say("tf2_1det_32s RB lnL max scaled err", err.max())
     assert np.all(err <= 1e-8)
 
 
-def test_loglike_full_parity_cfg1(cfg1):
-    ev, w, gev = cfg1
+def test_loglike_full_parity_tf2_1det_32s(tf2_1det_32s):
+    ev, w, gev = tf2_1det_32s
     th = w["theta"][:64]
     got = gev.loglike_full(_cuda(th)).cpu().numpy()
     want = L.loglike_full(ev, th)
     hh = L.optimal_snr2(ev, th)
     err = np.abs(got - want) / np.maximum(np.abs(want), hh)
-    say("cfg1 full lnL max scaled err", err.max())
+    say("tf2_1det_32s full lnL max scaled err", err.max())
     assert np.all(err <= 1e-8)
 
 
-def test_reference_exactness_on_gpu(cfg1):
+def test_reference_exactness_on_gpu(tf2_1det_32s):
     """At theta0 the binned lnL equals the full lnL (r == 1)."""
-    ev, w, gev = cfg1
+    ev, w, gev = tf2_1det_32s
     th0 = ev.theta_ref[None, :]
     rb = gev.loglike(_cuda(th0)).cpu().numpy()[0]
     full = gev.loglike_full(_cuda(th0)).cpu().numpy()[0]
@@ -86,8 +86,8 @@ def test_reference_exactness_on_gpu(cfg1):
     assert rb == pytest.approx(L.loglike_full(ev, th0)[0], rel=1e-10)
 
 
-def test_gradient_parity_cfg1(cfg1):
-    ev, w, gev = cfg1
+def test_gradient_parity_tf2_1det_32s(tf2_1det_32s):
+    ev, w, gev = tf2_1det_32s
     th = w["theta"][:96]
     lnl, g = gev.loglike_grad(_cuda(th))
     lnl, g = lnl.cpu().numpy(), g.cpu().numpy()
@@ -96,12 +96,12 @@ def test_gradient_parity_cfg1(cfg1):
     assert np.all(np.abs(lnl - want_l) <= 1e-8 * scale)
     gs, ws = g * WIDTHS, want_g * WIDTHS
     rel = np.abs(gs - ws).max(axis=1) / np.abs(ws).max(axis=1)
-    say("cfg1 grad max rel err", rel.max())
+    say("tf2_1det_32s grad max rel err", rel.max())
     assert np.all(rel <= 1e-5)
 
 
-def test_bitwise_determinism(cfg1):
-    ev, w, gev = cfg1
+def test_bitwise_determinism(tf2_1det_32s):
+    ev, w, gev = tf2_1det_32s
     t = _cuda(w["theta"])
     a = gev.loglike(t).cpu().numpy()
     b = gev.loglike(t).cpu().numpy()
@@ -111,8 +111,8 @@ def test_bitwise_determinism(cfg1):
     assert torch.equal(la, lb) and torch.equal(ga, gb)
 
 
-def test_domain_errors_and_ragged_batch(cfg1):
-    ev, w, gev = cfg1
+def test_domain_errors_and_ragged_batch(tf2_1det_32s):
+    ev, w, gev = tf2_1det_32s
     th = w["theta"][:7].copy()
     th[1, 0] = np.nan       # NaN -> NaN
     th[2, 6] = -5.0         # dL <= 0 -> -inf
@@ -132,8 +132,8 @@ def test_domain_errors_and_ragged_batch(cfg1):
     assert gev.loglike(_cuda(np.zeros((0, 13)))).numel() == 0
 
 
-def test_label_swap_on_gpu(cfg1):
-    ev, w, gev = cfg1
+def test_label_swap_on_gpu(tf2_1det_32s):
+    ev, w, gev = tf2_1det_32s
     th = w["theta"][:16].copy()
     sw = th.copy()
     sw[:, 1] = 1 / th[:, 1]
@@ -147,7 +147,7 @@ def test_label_swap_on_gpu(cfg1):
 
 def test_one_bin_per_grid_point_with_b2():
     """Tiny event, edges at every grid point, B2 kept: binned == full (GPU and oracle)."""
-    ev, w = oracle_event("cfg2", batch=16, duration=1.0, n_bins=None)
+    ev, w = oracle_event("tf2_3det_128s", batch=16, duration=1.0, n_bins=None)
     ev.keep_b2 = True
     # 20-300 Hz, 1 s: 281 points
     keep = ev.f <= 300.0
@@ -164,29 +164,29 @@ def test_one_bin_per_grid_point_with_b2():
 
 
 @pytest.fixture(scope="module")
-def cfg2():
-    say("[cfg2] building oracle event (259585 points x 3 detectors)")
-    ev, w = oracle_event("cfg2")
-    say("[cfg2] building GPU event")
+def tf2_3det_128s():
+    say("[tf2_3det_128s] building oracle event (259585 points x 3 detectors)")
+    ev, w = oracle_event("tf2_3det_128s")
+    say("[tf2_3det_128s] building GPU event")
     gev = gpu_event(ev)
     return ev, w, gev
 
 
-def test_summary_matches_oracle_cfg2(cfg2):
-    ev, _, gev = cfg2
+def test_summary_matches_oracle_tf2_3det_128s(tf2_3det_128s):
+    ev, _, gev = tf2_3det_128s
     s = gev.summary()
     ref = ev.summary
     fields = [ref["A0"].real, ref["A0"].imag, ref["A1"].real, ref["A1"].imag, ref["B0"], ref["B1"]]
     for j, want in enumerate(fields):
         err = np.abs(s[:, :, j] - want).max() / np.abs(want).max()
-        say("cfg2 summary field", j, "rel err", err)
+        say("tf2_3det_128s summary field", j, "rel err", err)
         assert err < 1e-10
 
 
-def test_loglike_and_grad_parity_cfg2_sampled(cfg2):
+def test_loglike_and_grad_parity_tf2_3det_128s_sampled(tf2_3det_128s):
     """Full batch (4096) in the launch shape the benchmark uses; the oracle checks
     a seeded sample of 128 chains."""
-    ev, w, gev = cfg2
+    ev, w, gev = tf2_3det_128s
     th = w["theta"]
     t = _cuda(th)
     lnl = gev.loglike(t).cpu().numpy()
@@ -202,24 +202,24 @@ def test_loglike_and_grad_parity_cfg2_sampled(cfg2):
     wl, wg = L.loglike_rb_grad(ev, th[idx[:32]])
     gs, ws = g[idx[:32]] * WIDTHS, wg * WIDTHS
     rel = np.abs(gs - ws).max(axis=1) / np.abs(ws).max(axis=1)
-    say("cfg2 grad max rel err", rel.max())
+    say("tf2_3det_128s grad max rel err", rel.max())
     assert np.all(rel <= 1e-5)
 
 
 # ---- mixed precision (FP64 phase, FP32 sin/cos and per-edge products, FP64 sums) -------------
 
-def test_mixed_loglike_cfg1(cfg1):
-    ev, w, gev = cfg1
+def test_mixed_loglike_tf2_1det_32s(tf2_1det_32s):
+    ev, w, gev = tf2_1det_32s
     th = w["theta"]
     got = gev.loglike(_cuda(th), precision="mixed").cpu().numpy()
     want = L.loglike_rb(ev, th)
     err = np.abs(got - want)
-    say("cfg1 mixed lnL max abs err", err.max())
+    say("tf2_1det_32s mixed lnL max abs err", err.max())
     assert np.all(err <= 1e-2)
 
 
-def test_mixed_loglike_and_grad_cfg2(cfg2):
-    ev, w, gev = cfg2
+def test_mixed_loglike_and_grad_tf2_3det_128s(tf2_3det_128s):
+    ev, w, gev = tf2_3det_128s
     th = w["theta"]
     t = _cuda(th)
     lm = gev.loglike(t, precision="mixed").cpu().numpy()
@@ -230,10 +230,10 @@ def test_mixed_loglike_and_grad_cfg2(cfg2):
     want = L.loglike_rb(ev, th[idx])
     err = np.abs(lm[idx] - want)
     errg = np.abs(lgm[idx] - want)
-    say("cfg2 mixed lnL max abs err", err.max(), "grad-kernel lnL", errg.max())
+    say("tf2_3det_128s mixed lnL max abs err", err.max(), "grad-kernel lnL", errg.max())
     assert np.all(err <= 1e-2) and np.all(errg <= 1e-2)
     wl, wg = L.loglike_rb_grad(ev, th[idx[:48]])
     gs, ws = gm[idx[:48]] * WIDTHS, wg * WIDTHS
     rel = np.abs(gs - ws).max(axis=1) / np.abs(ws).max(axis=1)
-    say("cfg2 mixed grad max rel err (reported, not the FP64 bar)", rel.max())
+    say("tf2_3det_128s mixed grad max rel err (reported, not the FP64 bar)", rel.max())
     assert np.all(rel <= 1e-3)

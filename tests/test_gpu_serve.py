@@ -15,7 +15,7 @@ if not torch.cuda.is_available():
 
 @pytest.fixture(scope="module")
 def events():
-    specs = [("cfg1", 300, 16.0, 100), ("cfg2", 700, 16.0, 200), ("cfg3", 1100, 16.0, 300), ("cfg2", 256, 8.0, 120)]
+    specs = [("tf2_1det_32s", 300, 16.0, 100), ("tf2_3det_128s", 700, 16.0, 200), ("nrtv2_3det_256s", 1100, 16.0, 300), ("tf2_3det_128s", 256, 8.0, 120)]
     out = []
     for name, batch, dur, nb in specs:
         ev, w = oracle_event(name, batch=batch, duration=dur, n_bins=nb)

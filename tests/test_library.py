@@ -32,10 +32,10 @@ def test_exports_every_declared_symbol():
     assert declared == set(L.EXPORTS)
 
 
-@pytest.mark.parametrize("cfg,nb", [("cfg1", 100), ("cfg2", 500), ("cfg3", 1000)])
-def test_bin_edges_match_oracle(cfg, nb):
+@pytest.mark.parametrize("name,nb", [("tf2_1det_32s", 100), ("tf2_3det_128s", 500), ("nrtv2_3det_256s", 1000)])
+def test_bin_edges_match_oracle(name, nb):
     from paper_2404_11397_amd import bin_edges
-    c = synth.CONFIGS[cfg]
+    c = synth.CONFIGS[name]
     f_low, df, n, _ = synth.frequency_grid(c["f_low"], c["f_high"], c["duration"])
     np.testing.assert_array_equal(bin_edges(f_low, df, n, nb), binning.pn_bin_edges(f_low, df, n, nb))
 

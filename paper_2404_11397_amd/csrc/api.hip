@@ -29,7 +29,7 @@ int hip_fail(hipError_t e, const char* what) {
 
 namespace {
 
-constexpr int64_t kChunk = 512;     // grid points per summary work item
+constexpr int64_t kChunk = 128;     // grid points per summary work item
 
 bool theta_in_domain(const double* t) {
     for (int i = 0; i < 13; ++i)

@@ -331,14 +331,14 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
         }
         {   // the previous edge is now complete: W += conj(sum_d w_d)
             const double wr = wre + pre, wi = wim - pim;
-            nrt_node_adjoint(cv.np, fp, xp, ixp, lxp, (2.0 * kPi) * wi, ap > 0.0 ? wr / ap : 0.0, G.sa);
+            nrt_node_adjoint(cv.np, fp, xp, ixp, lxp, (2.0 * kPi) * wi, ap != 0.0 ? wr / ap : 0.0, G.sa);
         }
         wre = qre;
         wim = qim;
         ap = a;
         fp = f; xp = x; ixp = ix; lxp = lx;
     }
-    nrt_node_adjoint(cv.np, fp, xp, ixp, lxp, (2.0 * kPi) * wim, ap > 0.0 ? wre / ap : 0.0, G.sa);
+    nrt_node_adjoint(cv.np, fp, xp, ixp, lxp, (2.0 * kPi) * wim, ap != 0.0 ? wre / ap : 0.0, G.sa);
 }
 
 template <int ND, bool MIXED, int WF>

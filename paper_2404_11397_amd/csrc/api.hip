@@ -296,7 +296,9 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
         return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (summary)"));
     double* node_block = nullptr;
     // FP64 tables, scales, FP32 tables (2 nd np floats), reference phase / amplitude (2 np), FP32 amplitude
-    const int64_t node_doubles = np * (4 + 5 * nd) + 2 * kMaxDet + np * 2 * nd + 2 * np + (np + 1) / 2;
+    // tables: 4 edge columns and 5 per-detector columns (FP64), the scales, 5 per-detector
+    // FP32 columns, phi0 and 1/a0 (FP64), 1/a0 (FP32), x^5.78 (FP64); np is a multiple of 64
+    const int64_t node_doubles = np * (4 + 5 * nd) + 2 * kMaxDet + np * 5 * nd / 2 + 2 * np + np / 2 + np;
     if (ev->mem.alloc((void**)&node_block, sizeof(double) * node_doubles) != hipSuccess)
         return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (node tables)"));
 
@@ -361,9 +363,11 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     na.g_im32 = na.g_re32 + nd * np;
     na.mu32 = na.g_im32 + nd * np;
     na.nuL32 = na.mu32 + nd * np;
-    na.phi0 = na.scales + 2 * kMaxDet + np * 2 * nd;  // after the FP32 tables (4 nd np floats)
+    na.nuR32 = na.nuL32 + nd * np;
+    na.phi0 = na.scales + 2 * kMaxDet + np * 5 * nd / 2;  // after the FP32 tables (5 nd np floats)
     na.ia0 = na.phi0 + np;
     na.ia0_32 = (float*)(na.ia0 + np);
+    na.node_x578 = na.ia0 + np + np / 2;
     na.ref = ev->ref;
     na.ref_taper = (desc->flags & RBL_REF_TAPER) ? 1 : 0;
     int32_t* d_bad = nullptr;
@@ -402,11 +406,13 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     dv.g_im32 = na.g_im32;
     dv.mu32 = na.mu32;
     dv.nuL32 = na.nuL32;
+    dv.nuR32 = na.nuR32;
     dv.scales = na.scales;
     dv.waveform = desc->waveform;
     dv.phi0 = na.phi0;
     dv.ia0 = na.ia0;
     dv.ia0_32 = na.ia0_32;
+    dv.node_x578 = na.node_x578;
     ev->footprint = (int64_t)sizeof(double) * (nd * nb * 7 + node_doubles) +
                     ((desc->flags & RBL_KEEP_GRID) ? (int64_t)sizeof(double) * 3 * nd * n : 0);
     *out = ev;

@@ -287,7 +287,7 @@ __global__ __launch_bounds__(256) void k_summary_items(SummaryArgs a) {
         double amp = ref.amp0 * (ix * ix * ix) * sqrt(ix);  // f^(-7/6)
         if (ref.waveform == kWfNrtv2) {
             double a0;
-            nrt_node(ref.nrt, f, x, ix, lx, a.ref_taper != 0, phi, a0);
+            nrt_node(ref.nrt, f, x, ix, lx, exp(5.78 * lx), a.ref_taper != 0, phi, a0);
             amp *= a0;
         } else {
             double bas[kTf2Basis];
@@ -352,7 +352,8 @@ __global__ void k_summary_reduce(const double* __restrict__ partials, const int6
 __global__ void k_node_tables(NodeArgs a) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;  // edge index
     if (j >= a.n_nodes_pad) return;
-    const int pos = (j % a.L) * kNodeTile + j / a.L;       // lane-contiguous position
+    // lane-contiguous position (TaylorF2) or natural order (IMRPhenomD_NRTidalv2)
+    const int pos = a.ref.waveform == kWfNrtv2 ? j : (j % a.L) * kNodeTile + j / a.L;
     const bool real_node = j < a.n_nodes;
     const int nb = a.n_nodes - 1;
     double f = 0.0, x = 1.0, ix = 1.0, lx = 0.0;
@@ -368,7 +369,9 @@ __global__ void k_node_tables(NodeArgs a) {
     a.node_lx[pos] = lx;
     if (a.ref.waveform == kWfNrtv2) {
         double phi0 = 0.0, a0 = 1.0;
-        if (real_node) nrt_node(a.ref.nrt, f, x, ix, lx, a.ref_taper != 0, phi0, a0);
+        const double x578 = exp(5.78 * lx);
+        a.node_x578[pos] = x578;
+        if (real_node) nrt_node(a.ref.nrt, f, x, ix, lx, x578, a.ref_taper != 0, phi0, a0);
         const bool ok = a0 > 0.0 && isfinite(a0) && isfinite(phi0);
         if (!ok) *a.bad_ref = 1;
         a.phi0[pos] = phi0;
@@ -407,6 +410,7 @@ __global__ void k_node_tables(NodeArgs a) {
         a.g_im32[o] = (float)gim;
         a.mu32[o] = (float)mu;
         a.nuL32[o] = (float)nul;
+        a.nuR32[o] = (float)nur;
     }
 }
 
@@ -467,7 +471,7 @@ __global__ __launch_bounds__(256) void k_loglike_full(FullArgs a) {
         double am = (ix * ix * ix) * sqrt(ix);
         if (nrt) {
             double af;
-            nrt_node(np, f, x, ix, lx, true, ph, af);
+            nrt_node(np, f, x, ix, lx, exp(5.78 * lx), true, ph, af);
             am *= af;
         } else {
             double bas[kTf2Basis];
@@ -506,7 +510,7 @@ __global__ __launch_bounds__(256) void k_strain(const RefConsts* __restrict__ cs
     double am = r.amp0 * (ix * ix * ix) * sqrt(ix);
     if (r.waveform == kWfNrtv2) {
         double af;
-        nrt_node(r.nrt, f, x, ix, lx, taper != 0, ph, af);
+        nrt_node(r.nrt, f, x, ix, lx, exp(5.78 * lx), taper != 0, ph, af);
         am *= af;
     } else {
         double bas[kTf2Basis];

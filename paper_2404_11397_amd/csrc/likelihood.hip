@@ -32,6 +32,9 @@ struct EdgeTab {
 };
 __device__ inline EdgeTab<double> edge_tab(const EventDev& ev, double) { return {ev.g_re, ev.g_im, ev.mu, ev.nuL}; }
 __device__ inline EdgeTab<float> edge_tab(const EventDev& ev, float) { return {ev.g_re32, ev.g_im32, ev.mu32, ev.nuL32}; }
+// nuR_j = nuL_{j+1}: the cross coefficient of the bin right of edge j
+__device__ inline const double* nur_tab(const EventDev& ev, double) { return ev.nuR; }
+__device__ inline const float* nur_tab(const EventDev& ev, float) { return ev.nuR32; }
 
 // Per-chain values shared by the walks.
 template <int ND>
@@ -64,7 +67,7 @@ __device__ inline void edge_phase(const EventDev& ev, const ChainVals<ND>& cv, i
     const double x = ev.node_x[pos], ix = ev.node_ix[pos], lx = ev.node_lx[pos];
     if (WF == kWfNrtv2) {
         double ph, a;
-        nrt_node(cv.np, f, x, ix, lx, true, ph, a);
+        nrt_node(cv.np, f, x, ix, lx, ev.node_x578[pos], true, ph, a);
         dph = ph - ev.phi0[pos];
         ar = a * ev.ia0[pos];
     } else {
@@ -129,6 +132,61 @@ __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, i
     return acc;
 }
 
+// IMRPhenomD_NRTidalv2 events keep their edge tables in natural order (edge j at
+// position j): step k covers edges 64k .. 64k+63, so the lanes of a wavefront sit in
+// the same region of the piecewise model (phase regions, taper) and branch together.
+// The left neighbour of an edge is the previous lane, or for lane 0 the last lane of
+// the previous step (a wave-uniform carry).
+template <int ND, class R>
+__device__ inline void nrt_ratio(const EventDev& ev, const ChainVals<ND>& cv, int pos, const R* kre, const R* kim,
+                                 R* rre, R* rim, double& a) {
+    const double f = ev.node_f[pos];
+    double ph;
+    nrt_node(cv.np, f, ev.node_x[pos], ev.node_ix[pos], ev.node_lx[pos], ev.node_x578[pos], true, ph, a);
+    const double dph = ph - ev.phi0[pos];
+    const R ar = (R)(a * ev.ia0[pos]);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        R cu, su;
+        unit_phasor(fma(f, cv.dtau[d], dph), cu, su);
+        cu *= ar;
+        su *= ar;
+        rre[d] = kre[d] * cu - kim[d] * su;
+        rim[d] = kre[d] * su + kim[d] * cu;
+    }
+}
+
+template <int ND, class R>
+__device__ inline double fwd_walk_natural(const EventDev& ev, const ChainVals<ND>& cv, int lane) {
+    const EdgeTab<R> T = edge_tab(ev, R(0));
+    const int npad = ev.n_nodes_pad;
+    R kre[ND], kim[ND], cre[ND], cim[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        kre[d] = (R)cv.kre[d];
+        kim[d] = (R)cv.kim[d];
+        cre[d] = cim[d] = R(0);
+    }
+    double acc = 0.0;
+    for (int k = 0; k < ev.L; ++k) {
+        const int pos = k * 64 + lane;
+        R rre[ND], rim[ND];
+        double a;
+        nrt_ratio<ND, R>(ev, cv, pos, kre, kim, rre, rim, a);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const R lre = shift_up(rre[d], cre[d]), lim = shift_up(rim[d], cim[d]);
+            const int o = d * npad + pos;
+            const R t = (T.gre[o] * rre[d] + T.gim[o] * rim[d]) - R(0.5) * T.mu[o] * (rre[d] * rre[d] + rim[d] * rim[d])
+                      - R(0.5) * T.nul[o] * (lre * rre[d] + lim * rim[d]);
+            acc += (double)t;
+            cre[d] = lane_read(rre[d], 63);
+            cim[d] = lane_read(rim[d], 63);
+        }
+    }
+    return acc;
+}
+
 template <int ND, bool MIXED, int WF>
 __global__ __launch_bounds__(256) void k_loglike_fwd(EventDev ev, const double* __restrict__ recs, int64_t B,
                                                      double* __restrict__ lnl) {
@@ -156,10 +214,17 @@ __global__ __launch_bounds__(256) void k_loglike_fwd(EventDev ev, const double* 
         for (int i = 0; i < kNrtParams; ++i) dst[i] = rec[kRecNrt + i];
     }
     double acc;
-    if (MIXED && use_mixed<ND>(ev, cv))
-        acc = fwd_walk<ND, float, WF>(ev, cv, lane);
-    else
-        acc = fwd_walk<ND, double, WF>(ev, cv, lane);
+    if constexpr (WF == kWfNrtv2) {
+        if (MIXED && use_mixed<ND>(ev, cv))
+            acc = fwd_walk_natural<ND, float>(ev, cv, lane);
+        else
+            acc = fwd_walk_natural<ND, double>(ev, cv, lane);
+    } else {
+        if (MIXED && use_mixed<ND>(ev, cv))
+            acc = fwd_walk<ND, float, WF>(ev, cv, lane);
+        else
+            acc = fwd_walk<ND, double, WF>(ev, cv, lane);
+    }
     acc = wave_sum(acc);
     if (lane == 0) lnl[chain] = acc;
 }
@@ -261,88 +326,71 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, in
 // IMRPhenomD_NRTidalv2: r_dj = K_d (a_j / a0_j) exp(-2 pi i (Phi_j - Phi0_j + f_j dtau_d)).
 // With W_j = sum_d z_dj, the node parameters p receive
 //   d lnL / dp = sum_j [ 2 pi Im(W_j) dPhi_j / dp + Re(W_j) / a_j  da_j / dp ],
-// accumulated by nrt_node_adjoint once W_j is complete (one step later, as above).  The
-// right cross term of a lane's last edge is added by the next lane at its halo edge;
-// the accumulation is linear in W_j, so each part can be added where it is known.
+// accumulated by nrt_node_adjoint.  Natural edge order (see fwd_walk_natural): the
+// ratio of the next step is evaluated first, so that both neighbours of every edge of
+// the current step are known (previous / next lane, or the carry from the previous
+// step / lane 0 of the next step) and W_j is complete when its adjoint runs.  The right
+// cross coefficient c_{j+1} = -nuR_j / 2 is read from the edge's own table.
 template <int ND, class R>
 __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv, int lane, GradAcc<ND, kNrtAdj>& G) {
     const EdgeTab<R> T = edge_tab(ev, R(0));
+    const R* nur = nur_tab(ev, R(0));
     const int npad = ev.n_nodes_pad;
     const int L = ev.L;
-    R kre[ND], kim[ND], rpr[ND], rpi[ND];
+    R kre[ND], kim[ND], rcr[ND], rci[ND], rnr[ND], rni[ND], cre[ND], cim[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         kre[d] = (R)cv.kre[d];
         kim[d] = (R)cv.kim[d];
+        cre[d] = cim[d] = R(0);
     }
-    const int hpos = lane > 0 ? (L - 1) * 64 + (lane - 1) : npad - 1;
-    double fp = ev.node_f[hpos], xp = ev.node_x[hpos], ixp = ev.node_ix[hpos], lxp = ev.node_lx[hpos];
-    double ap;
-    {
-        double ph, a;
-        nrt_node(cv.np, fp, xp, ixp, lxp, true, ph, a);
-        const double dph = ph - ev.phi0[hpos];
-        const R ar = (R)(a * ev.ia0[hpos]);
-        ap = a;
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            R ur, ui;
-            unit_phasor(fma(fp, cv.dtau[d], dph), ur, ui);
-            ur *= ar;
-            ui *= ar;
-            rpr[d] = kre[d] * ur - kim[d] * ui;
-            rpi[d] = kre[d] * ui + kim[d] * ur;
-        }
-    }
-    double wre = 0.0, wim = 0.0;  // W of the previous edge without its right cross term (halo: not ours)
+    double acur, anext = 0.0;
+    nrt_ratio<ND, R>(ev, cv, lane, kre, kim, rcr, rci, acur);
     for (int k = 0; k < L; ++k) {
+        if (k + 1 < L) {
+            nrt_ratio<ND, R>(ev, cv, (k + 1) * 64 + lane, kre, kim, rnr, rni, anext);
+        } else {
+#pragma unroll
+            for (int d = 0; d < ND; ++d) rnr[d] = rni[d] = R(0);
+        }
         const int pos = k * 64 + lane;
-        const double f = ev.node_f[pos], x = ev.node_x[pos], ix = ev.node_ix[pos], lx = ev.node_lx[pos];
-        double ph, a;
-        nrt_node(cv.np, f, x, ix, lx, true, ph, a);
-        const double dph = ph - ev.phi0[pos];
-        const R ar = (R)(a * ev.ia0[pos]);
-        double qre = 0.0, qim = 0.0, pre = 0.0, pim = 0.0;
-        const double df = f - fp;
+        const double f = ev.node_f[pos];
+        double wre = 0.0, wim = 0.0;
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
-            R ur, ui;
-            unit_phasor(fma(f, cv.dtau[d], dph), ur, ui);
-            ur *= ar;
-            ui *= ar;
-            const R rre = kre[d] * ur - kim[d] * ui;
-            const R rim = kre[d] * ui + kim[d] * ur;
+            const R rre = rcr[d], rim = rci[d];
+            const R lre = shift_up(rre, cre[d]), lim = shift_up(rim, cim[d]);
+            const R nre = shift_down(rre, lane_read(rnr[d], 0)), nim = shift_down(rim, lane_read(rni[d], 0));
             const int o = d * npad + pos;
             const R gre = T.gre[o], gim = T.gim[o], mu = T.mu[o];
-            const R c = R(-0.5) * T.nul[o];
-            const R glr = gre - mu * rre, gli = gim - mu * rim;
-            const R reloc = glr * rre + gli * rim, imz = glr * rim - gli * rre;
-            const R rew = c * (rpr[d] * rre + rpi[d] * rim), imw = c * (rpr[d] * rim - rpi[d] * rre);
-            G.acc += (double)(reloc + R(0.5) * mu * (rre * rre + rim * rim) + rew);
-            G.zr[d] += (double)(reloc + R(2) * rew);
-            G.zi[d] += (double)imz;
-            qre += (double)(reloc + rew);
-            qim += (double)(imz + imw);
-            pre += (double)rew;
-            pim += (double)imw;
-            G.ta[d] = fma((double)imz, f, fma((double)imw, df, G.ta[d]));
-            rpr[d] = rre;
-            rpi[d] = rim;
+            const R cl = R(-0.5) * T.nul[o], cr = R(-0.5) * nur[o];
+            G.acc += (double)((gre * rre + gim * rim) - R(0.5) * mu * (rre * rre + rim * rim) + cl * (lre * rre + lim * rim));
+            const R gbr = gre - mu * rre + cl * lre + cr * nre;
+            const R gbi = gim - mu * rim + cl * lim + cr * nim;
+            const double zr = (double)(gbr * rre + gbi * rim), zi = (double)(gbr * rim - gbi * rre);
+            G.zr[d] += zr;
+            G.zi[d] += zi;
+            G.ta[d] = fma(zi, f, G.ta[d]);
+            wre += zr;
+            wim += zi;
+            cre[d] = lane_read(rre, 63);
+            cim[d] = lane_read(rim, 63);
         }
-        {   // the previous edge is now complete: W += conj(sum_d w_d)
-            const double wr = wre + pre, wi = wim - pim;
-            nrt_node_adjoint(cv.np, fp, xp, ixp, lxp, (2.0 * kPi) * wi, ap != 0.0 ? wr / ap : 0.0, G.sa);
+        nrt_node_adjoint(cv.np, f, ev.node_x[pos], ev.node_ix[pos], ev.node_lx[pos], ev.node_x578[pos],
+                         (2.0 * kPi) * wim, acur != 0.0 ? wre / acur : 0.0, G.sa);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            rcr[d] = rnr[d];
+            rci[d] = rni[d];
         }
-        wre = qre;
-        wim = qim;
-        ap = a;
-        fp = f; xp = x; ixp = ix; lxp = lx;
+        acur = anext;
     }
-    nrt_node_adjoint(cv.np, fp, xp, ixp, lxp, (2.0 * kPi) * wim, ap != 0.0 ? wre / ap : 0.0, G.sa);
 }
 
+// Occupancy target: 3 waves per SIMD for TaylorF2; 2 for NRTidalv2, whose 26 adjoint
+// accumulators and per-edge model would otherwise spill.
 template <int ND, bool MIXED, int WF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_loglike_grad(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNrtv2 ? 2 : 3))) void k_loglike_grad(
     EventDev ev, const double* __restrict__ recs, const double* __restrict__ jac, int64_t B,
     double* __restrict__ lnl, double* __restrict__ grad) {
     const int lane = threadIdx.x & 63;

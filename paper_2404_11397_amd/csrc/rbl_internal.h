@@ -21,7 +21,7 @@ constexpr int kNodeTile = 64;  // node tables are padded to a multiple of the wa
 //   [17..19]   dtau_d = (tc + dt_d) - (tc0 + dt_d0)  [s]
 //   [20..21]   G (re, im)                 (gradient setup only)
 //   [22]       dL                         (gradient setup only)
-//   [24..51]   NrtParams<double> of the chain (IMRPhenomD_NRTidalv2 events; dc and the
+//   [24..52]   NrtParams<double> of the chain (IMRPhenomD_NRTidalv2 events; dc and the
 //              constant phase are then unused: the edge phase is taken absolutely)
 constexpr int kRecStride = 64;
 constexpr int kRecStatus = 0;
@@ -96,10 +96,12 @@ struct EventDev {
     const float* g_im32;
     const float* mu32;
     const float* nuL32;
+    const float* nuR32;
     // IMRPhenomD_NRTidalv2 events: reference phase [rev] and inverse amplitude factor per edge
     const double* phi0;
     const double* ia0;
     const float* ia0_32;
+    const double* node_x578;  // x^5.78 per edge (IMRPhenomD_NRTidalv2 tidal amplitude)
     // per detector: Gs_d = sum_j |gamma_dj|, Hs_d = sum_j (|mu_dj| + |nuL_dj|)  [2 * kMaxDet]
     // (a chain's binned-sum magnitude is at most sum_d |K_d| Gs_d + |K_d|^2 Hs_d)
     const double* scales;

@@ -29,13 +29,14 @@ struct NodeArgs {
     RefConsts ref;
     double *phi0, *ia0;
     float* ia0_32;
+    double* node_x578;
     int32_t* bad_ref;  // set to 1 if the reference amplitude is not positive and finite at an edge
     const int64_t* edges;
     double f_low, delta_f;
     const double* summary;  // [n_det][n_bins][7]
     double *node_f, *node_x, *node_ix, *node_lx;
     double *g_re, *g_im, *mu, *nuL, *nuR;
-    float *g_re32, *g_im32, *mu32, *nuL32;
+    float *g_re32, *g_im32, *mu32, *nuL32, *nuR32;
     double* scales;
 };
 

@@ -50,8 +50,9 @@ struct NrtParams {
     T fpk, fdp;           // amplitude peak and damping frequency (Mf)
     T fm;                 // taper start [Hz]
     T amp;                // 0PN amplitude scale (see tf2_amp)
+    T s578;               // exp(5.78 ln s) = s^5.78: with the edge table x^5.78 it gives xt^2.89
 };
-constexpr int kNrtParams = 28;  // doubles in NrtParams<double>
+constexpr int kNrtParams = 29;  // doubles in NrtParams<double>
 static_assert(sizeof(NrtParams<double>) == kNrtParams * sizeof(double), "NrtParams layout");
 
 namespace nrt_detail {
@@ -169,12 +170,13 @@ __device__ inline void nrt_params(const T& mc, const T& q, const T& chi1, const 
                   (1.0 + 7.542e-2 * kappa + 2.236e-4 * kappa * kappa);
     o.fm = mfm / o.ms;
     o.amp = tf2_amp<T>(mc);
+    o.s578 = dexp(5.78 * o.lns);
 }
 
 // Phase [rev] and amplitude factor a = (a_pp + a_T) w at one frequency, given
-// x = f^(1/3), 1/x and ln x.
-__device__ inline void nrt_node(const NrtParams<double>& p, double f, double x, double ix, double lx, bool taper,
-                                double& phi, double& a) {
+// x = f^(1/3), 1/x, ln x and x^5.78 (so that (s x)^5.78 = s578 x^5.78 needs no exp).
+__device__ inline void nrt_node(const NrtParams<double>& p, double f, double x, double ix, double lx, double x578,
+                                bool taper, double& phi, double& a) {
     const double mf = p.ms * f;
     double ph;
     if (mf < kNrtF1) {
@@ -197,8 +199,7 @@ __device__ inline void nrt_node(const NrtParams<double>& p, double f, double x, 
     const double den = 1.0 + kTd1 * xt + kTd32 * xt * sx + kTd2 * xt2;
     phi = ph + p.tp * xt2 * sx * num / den;
     const double app = mf < p.fpk ? 1.0 : exp(-(mf - p.fpk) / p.fdp);
-    const double lxt = 2.0 * (p.lns + lx);
-    const double at = p.m9k * (xt2 * xt2 * xt) * (1.0 + (449.0 / 108.0) * xt + (22672.0 / 9.0) * exp(2.89 * lxt)) /
+    const double at = p.m9k * (xt2 * xt2 * xt) * (1.0 + (449.0 / 108.0) * xt + (22672.0 / 9.0) * (p.s578 * x578)) /
                       (1.0 + 13477.8 * xt2 * xt2);
     a = app + at;
     if (taper) {
@@ -225,7 +226,7 @@ constexpr int kAdjMs = 0, kAdjLnMs = 1, kAdjS = 2, kAdjLnS = 3, kAdjC = 4, kAdjC
               kAdjTp = 21, kAdjM9k = 22, kAdjFpk = 23, kAdjFdp = 24, kAdjFm = 25;
 
 __device__ inline void nrt_node_adjoint(const NrtParams<double>& p, double f, double x, double ix, double lx,
-                                        double gphi, double ga, double* acc) {
+                                        double x578, double gphi, double ga, double* acc) {
     const double mf = p.ms * f;
     if (mf < kNrtF1) {
         const double ix2 = ix * ix, ix3 = ix2 * ix;
@@ -300,8 +301,7 @@ __device__ inline void nrt_node_adjoint(const NrtParams<double>& p, double f, do
         acc[kAdjFpk] += g;
         acc[kAdjFdp] = fma(g, (mf - p.fpk) * id, acc[kAdjFdp]);
     }
-    const double lxt = 2.0 * (p.lns + lx);
-    const double e289 = exp(2.89 * lxt);
+    const double e289 = p.s578 * x578;  // xt^2.89
     const double xt4 = xt2 * xt2;
     const double nn = 1.0 + (449.0 / 108.0) * xt + (22672.0 / 9.0) * e289;
     const double dd = 1.0 + 13477.8 * xt4;

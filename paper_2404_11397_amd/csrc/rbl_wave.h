@@ -33,21 +33,36 @@ __device__ inline double wave_sum(double v) {
     const int hi = __builtin_amdgcn_readlane(__double2hiint(s), 63);
     return __hiloint2double(hi, lo);
 }
+// Whole-wave shifts by one lane (DPP wave_shr:1 / wave_shl:1).  The lane without a
+// source (lane 0, resp. lane 63) receives `fill`.  All lanes must be active.
+template <int CTRL>
+__device__ inline double wave_shift(double v, double fill) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(fill), __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(fill), __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ inline float wave_shift(float v, float fill) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
 // lane i receives lane i-1's value; lane 0 receives `fill`
-__device__ inline double shift_up(double v, double fill, int lane) {
-    const double u = __shfl_up(v, 1, 64);
-    return lane == 0 ? fill : u;
-}
+template <class R>
+__device__ inline R shift_up(R v, R fill) { return wave_shift<0x138>(v, fill); }
 // lane i receives lane i+1's value; lane 63 receives `fill`
-__device__ inline double shift_down(double v, double fill, int lane) {
-    const double u = __shfl_down(v, 1, 64);
-    return lane == 63 ? fill : u;
+template <class R>
+__device__ inline R shift_down(R v, R fill) { return wave_shift<0x130>(v, fill); }
+__device__ inline double shift_up(double v, double fill, int) { return shift_up<double>(v, fill); }
+__device__ inline float shift_up(float v, float fill, int) { return shift_up<float>(v, fill); }
+
+// The value of one lane, wave-uniform.
+__device__ inline double lane_read(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
 }
-__device__ inline float shift_up(float v, float fill, int lane) {
-    const float u = __shfl_up(v, 1, 64);
-    return lane == 0 ? fill : u;
+__device__ inline float lane_read(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
-__device__ inline double lane_value(double v, int src) { return __shfl(v, src, 64); }
 
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 

@@ -36,6 +36,13 @@ __device__ inline EdgeTab<float> edge_tab(const EventDev& ev, float) { return {e
 __device__ inline const double* nur_tab(const EventDev& ev, double) { return ev.nuR; }
 __device__ inline const float* nur_tab(const EventDev& ev, float) { return ev.nuR32; }
 
+// Table load with a 32-bit byte offset: lets the compiler address every table of a step
+// from its scalar base plus one shared vector offset (global_load ... saddr).
+template <class T>
+__device__ inline T ld(const T* base, unsigned idx) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(T));
+}
+
 // Per-chain values shared by the walks.
 template <int ND>
 struct ChainVals {
@@ -62,14 +69,14 @@ __device__ inline bool use_mixed(const EventDev& ev, const ChainVals<ND>& cv) {
 //   TaylorF2:  sum_b dc_b B_b(x), ratio 1 (the Mc^(5/6) factor is in K);
 //   IMRPhenomD_NRTidalv2:  Phi(f; theta) - Phi0_j, ratio a(f; theta) / a0_j.
 template <int ND, int WF>
-__device__ inline void edge_phase(const EventDev& ev, const ChainVals<ND>& cv, int pos, double f, double& dph,
+__device__ inline void edge_phase(const EventDev& ev, const ChainVals<ND>& cv, unsigned pos, double f, double& dph,
                                   double& ar) {
-    const double x = ev.node_x[pos], ix = ev.node_ix[pos], lx = ev.node_lx[pos];
+    const double x = ld(ev.node_x, pos), ix = ld(ev.node_ix, pos), lx = ld(ev.node_lx, pos);
     if (WF == kWfNrtv2) {
         double ph, a;
-        nrt_node(cv.np, f, x, ix, lx, ev.node_x578[pos], true, ph, a);
-        dph = ph - ev.phi0[pos];
-        ar = a * ev.ia0[pos];
+        nrt_node(cv.np, f, x, ix, lx, ld(ev.node_x578, pos), true, ph, a);
+        dph = ph - ld(ev.phi0, pos);
+        ar = a * ld(ev.ia0, pos);
     } else {
         double bas[kTf2Basis];
         tf2_basis(x, ix, lx, bas);
@@ -98,8 +105,8 @@ __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, i
     }
     double acc = 0.0;
     for (int k = 0; k < ev.L; ++k) {
-        const int pos = k * 64 + lane;
-        const double f = ev.node_f[pos];
+        const unsigned pos = (unsigned)(k * 64 + lane);
+        const double f = ld(ev.node_f, pos);
         double ph, ard;
         edge_phase<ND, WF>(ev, cv, pos, f, ph, ard);
         const R ar = (R)ard;
@@ -111,10 +118,10 @@ __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, i
             su *= ar;
             const R rre = kre[d] * cu - kim[d] * su;
             const R rim = kre[d] * su + kim[d] * cu;
-            const int o = d * npad + pos;
-            R t = (T.gre[o] * rre + T.gim[o] * rim) - R(0.5) * T.mu[o] * (rre * rre + rim * rim);
+            const unsigned o = (unsigned)(d * npad) + pos;
+            R t = (ld(T.gre, o) * rre + ld(T.gim, o) * rim) - R(0.5) * ld(T.mu, o) * (rre * rre + rim * rim);
             if (k > 0) {
-                t -= R(0.5) * T.nul[o] * (pre[d] * rre + pim[d] * rim);
+                t -= R(0.5) * ld(T.nul, o) * (pre[d] * rre + pim[d] * rim);
             } else {
                 fre[d] = rre;
                 fim[d] = rim;
@@ -127,7 +134,7 @@ __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, i
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         const R lre = shift_up(pre[d], R(0), lane), lim = shift_up(pim[d], R(0), lane);
-        acc -= (double)(R(0.5) * T.nul[d * npad + lane] * (lre * fre[d] + lim * fim[d]));
+        acc -= (double)(R(0.5) * ld(T.nul, (unsigned)(d * npad + lane)) * (lre * fre[d] + lim * fim[d]));
     }
     return acc;
 }
@@ -138,13 +145,13 @@ __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, i
 // The left neighbour of an edge is the previous lane, or for lane 0 the last lane of
 // the previous step (a wave-uniform carry).
 template <int ND, class R>
-__device__ inline void nrt_ratio(const EventDev& ev, const ChainVals<ND>& cv, int pos, const R* kre, const R* kim,
+__device__ inline void nrt_ratio(const EventDev& ev, const ChainVals<ND>& cv, unsigned pos, const R* kre, const R* kim,
                                  R* rre, R* rim, double& a) {
-    const double f = ev.node_f[pos];
+    const double f = ld(ev.node_f, pos);
     double ph;
-    nrt_node(cv.np, f, ev.node_x[pos], ev.node_ix[pos], ev.node_lx[pos], ev.node_x578[pos], true, ph, a);
-    const double dph = ph - ev.phi0[pos];
-    const R ar = (R)(a * ev.ia0[pos]);
+    nrt_node(cv.np, f, ld(ev.node_x, pos), ld(ev.node_ix, pos), ld(ev.node_lx, pos), ld(ev.node_x578, pos), true, ph, a);
+    const double dph = ph - ld(ev.phi0, pos);
+    const R ar = (R)(a * ld(ev.ia0, pos));
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         R cu, su;
@@ -169,16 +176,16 @@ __device__ inline double fwd_walk_natural(const EventDev& ev, const ChainVals<ND
     }
     double acc = 0.0;
     for (int k = 0; k < ev.L; ++k) {
-        const int pos = k * 64 + lane;
+        const unsigned pos = (unsigned)(k * 64 + lane);
         R rre[ND], rim[ND];
         double a;
         nrt_ratio<ND, R>(ev, cv, pos, kre, kim, rre, rim, a);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const R lre = shift_up(rre[d], cre[d]), lim = shift_up(rim[d], cim[d]);
-            const int o = d * npad + pos;
-            const R t = (T.gre[o] * rre[d] + T.gim[o] * rim[d]) - R(0.5) * T.mu[o] * (rre[d] * rre[d] + rim[d] * rim[d])
-                      - R(0.5) * T.nul[o] * (lre * rre[d] + lim * rim[d]);
+            const unsigned o = (unsigned)(d * npad) + pos;
+            const R t = (ld(T.gre, o) * rre[d] + ld(T.gim, o) * rim[d]) - R(0.5) * ld(T.mu, o) * (rre[d] * rre[d] + rim[d] * rim[d])
+                      - R(0.5) * ld(T.nul, o) * (lre * rre[d] + lim * rim[d]);
             acc += (double)t;
             cre[d] = lane_read(rre[d], 63);
             cim[d] = lane_read(rim[d], 63);
@@ -259,8 +266,8 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, in
         kim[d] = (R)cv.kim[d];
     }
     // halo edge: the last edge of lane - 1 (lane 0 has none; its first edge has nuL = 0)
-    const int hpos = lane > 0 ? (L - 1) * 64 + (lane - 1) : npad - 1;
-    double fp = ev.node_f[hpos], xp = ev.node_x[hpos], ixp = ev.node_ix[hpos], lxp = ev.node_lx[hpos];
+    const unsigned hpos = (unsigned)(lane > 0 ? (L - 1) * 64 + (lane - 1) : npad - 1);
+    double fp = ld(ev.node_f, hpos), xp = ld(ev.node_x, hpos), ixp = ld(ev.node_ix, hpos), lxp = ld(ev.node_lx, hpos);
     {
         double bas[kTf2Basis];
         tf2_basis(xp, ixp, lxp, bas);
@@ -277,8 +284,8 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, in
     }
     double qprev = 0.0;  // Im z of the previous edge without its right cross term (halo: not ours)
     for (int k = 0; k < L; ++k) {
-        const int pos = k * 64 + lane;
-        const double f = ev.node_f[pos], x = ev.node_x[pos], ix = ev.node_ix[pos], lx = ev.node_lx[pos];
+        const unsigned pos = (unsigned)(k * 64 + lane);
+        const double f = ld(ev.node_f, pos), x = ld(ev.node_x, pos), ix = ld(ev.node_ix, pos), lx = ld(ev.node_lx, pos);
         double bas[kTf2Basis];
         tf2_basis(x, ix, lx, bas);
         double ph = 0.0;
@@ -292,9 +299,9 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, in
             unit_phasor(fma(f, cv.dtau[d], ph), ur, ui);
             const R rre = kre[d] * ur - kim[d] * ui;
             const R rim = kre[d] * ui + kim[d] * ur;
-            const int o = d * npad + pos;
-            const R gre = T.gre[o], gim = T.gim[o], mu = T.mu[o];
-            const R c = R(-0.5) * T.nul[o];
+            const unsigned o = (unsigned)(d * npad) + pos;
+            const R gre = ld(T.gre, o), gim = ld(T.gim, o), mu = ld(T.mu, o);
+            const R c = R(-0.5) * ld(T.nul, o);
             const R glr = gre - mu * rre, gli = gim - mu * rim;  // local part of Gbar
             const R reloc = glr * rre + gli * rim, imz = glr * rim - gli * rre;
             const R rew = c * (rpr[d] * rre + rpi[d] * rim), imw = c * (rpr[d] * rim - rpi[d] * rre);
@@ -353,17 +360,17 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
 #pragma unroll
             for (int d = 0; d < ND; ++d) rnr[d] = rni[d] = R(0);
         }
-        const int pos = k * 64 + lane;
-        const double f = ev.node_f[pos];
+        const unsigned pos = (unsigned)(k * 64 + lane);
+        const double f = ld(ev.node_f, pos);
         double wre = 0.0, wim = 0.0;
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const R rre = rcr[d], rim = rci[d];
             const R lre = shift_up(rre, cre[d]), lim = shift_up(rim, cim[d]);
             const R nre = shift_down(rre, lane_read(rnr[d], 0)), nim = shift_down(rim, lane_read(rni[d], 0));
-            const int o = d * npad + pos;
-            const R gre = T.gre[o], gim = T.gim[o], mu = T.mu[o];
-            const R cl = R(-0.5) * T.nul[o], cr = R(-0.5) * nur[o];
+            const unsigned o = (unsigned)(d * npad) + pos;
+            const R gre = ld(T.gre, o), gim = ld(T.gim, o), mu = ld(T.mu, o);
+            const R cl = R(-0.5) * ld(T.nul, o), cr = R(-0.5) * ld(nur, o);
             G.acc += (double)((gre * rre + gim * rim) - R(0.5) * mu * (rre * rre + rim * rim) + cl * (lre * rre + lim * rim));
             const R gbr = gre - mu * rre + cl * lre + cr * nre;
             const R gbi = gim - mu * rim + cl * lim + cr * nim;
@@ -376,7 +383,7 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
             cre[d] = lane_read(rre, 63);
             cim[d] = lane_read(rim, 63);
         }
-        nrt_node_adjoint(cv.np, f, ev.node_x[pos], ev.node_ix[pos], ev.node_lx[pos], ev.node_x578[pos],
+        nrt_node_adjoint(cv.np, f, ld(ev.node_x, pos), ld(ev.node_ix, pos), ld(ev.node_lx, pos), ld(ev.node_x578, pos),
                          (2.0 * kPi) * wim, acur != 0.0 ? wre / acur : 0.0, G.sa);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
@@ -462,17 +469,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNr
             if (cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d] > 1e-280) continue;
             double sr = 0.0, si = 0.0;
             for (int k = 0; k < ev.L; ++k) {
-                const int pos = k * 64 + lane;
-                const double f = ev.node_f[pos];
+                const unsigned pos = (unsigned)(k * 64 + lane);
+                const double f = ld(ev.node_f, pos);
                 double ph, ar;
                 edge_phase<ND, WF>(ev, cv, pos, f, ph, ar);
                 double ur, ui;
                 expm2pi_rev(fma(f, cv.dtau[d], ph), ur, ui);
                 ur *= ar;
                 ui *= ar;
-                const int o = d * npad + pos;
-                sr += ev.g_re[o] * ur + ev.g_im[o] * ui;
-                si += ev.g_re[o] * ui - ev.g_im[o] * ur;
+                const unsigned o = (unsigned)(d * npad) + pos;
+                sr += ld(ev.g_re, o) * ur + ld(ev.g_im, o) * ui;
+                si += ld(ev.g_re, o) * ui - ld(ev.g_im, o) * ur;
             }
             ZR[d] = wave_sum(sr);
             ZI[d] = wave_sum(si);

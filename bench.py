@@ -70,6 +70,8 @@ def parse():
     p.add_argument("--no-nrtv2", action="store_true", help="skip the IMRPhenomD_NRTidalv2 forms")
     p.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     p.add_argument("--serve-requests", type=int, default=2000)
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="also run a plain device copy of known size (HBM counter calibration)")
     return p.parse_args()
 
 
@@ -146,6 +148,51 @@ def summary_pass(torch, w, edges, data, psd, repeats=3):
     ms, n = profile_read_summary()
     profile_enable(False)
     return ms / n * 1e3
+
+
+COPY_BYTES = 256 << 20   # the calibration copy reads and writes this many bytes per launch
+
+
+def calibrate_copy(torch, repeats=10):
+    """A plain device-to-device copy of COPY_BYTES (one copy kernel per launch): the
+    FETCH_SIZE / WRITE_SIZE counters of this launch give the scale factor from counter
+    units to HBM bytes."""
+    x = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(repeats):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    return {"bytes_read_per_launch": COPY_BYTES, "bytes_written_per_launch": COPY_BYTES, "launches": repeats}
+
+
+KERNEL_SOURCES = ("likelihood.hip", "kernels.hip", "rbl_launch.h", "rbl_internal.h", "rbl_wave.h", "rbl_math.h",
+                  "rbl_physics.h", "rbl_nrtv2.h")
+
+
+def kernel_source_hash():
+    """sha256 over the kernel sources: counters taken on other sources do not apply."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2404_11397_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel_tag):
+    """HBM bytes per launch of a kernel from the committed counter summary
+    profiles/<kernel_tag>_traffic.md (a line 'traffic: {json}'), if it was taken on
+    the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic: "):
+                rec = json.loads(line[len("traffic: "):])
+                return rec if rec.get("source_hash") == kernel_source_hash() else None
+    return None
 
 
 def forms_on(torch, ev, theta, lnl, grad, ws, steps, with_grad=True):
@@ -364,13 +411,18 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_loglike_grad<3>", "achieved": achieved,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": None, "flops_per_eval": fl_kernel,
-                     "avg_kernel_us": kern_us, "avg_setup_us": setup_us},
+                     "avg_kernel_us": kern_us, "avg_setup_us": setup_us,
+                     "kernel_source_hash": kernel_source_hash()},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "what": "one synchronised rbl_loglike_grad call over the 8192-chain batch"},
         "forms": forms,
         "summary_pass": {"us": summ_us, "bytes": summ_bytes, "GB_per_s": summ_bytes / (summ_us * 1e-6) / 1e9,
                          "frac_of_hbm_peak": summ_bytes / (summ_us * 1e-6) / 1e9 / PEAK_HBM_GBS},
     }
+    tr = stored_traffic("k_loglike_grad_tf2_3det_128s_8192_fp64")
+    if tr is not None:
+        out["roofline"]["traffic"] = tr["hbm_bytes_per_launch"]
+        out["roofline"]["traffic_detail"] = tr
     if not args.no_nrtv2:
         out["nrtv2"] = nrtv2_forms(torch, max(20, args.steps // 4))
     if not args.no_serve:
@@ -381,6 +433,8 @@ def main():
                                      "multi-event Poisson stream, request server",
                              "batch_call_p50": float(np.percentile(lat, 50)),
                              "batch_call_p99": float(np.percentile(lat, 99))}
+    if args.calibrate_copy:
+        out["copy_calibration"] = calibrate_copy(torch)
     if not args.no_cpu_baseline:
         data_host = data.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(w, edges, data_host, theta_np, args.cpu_seconds)

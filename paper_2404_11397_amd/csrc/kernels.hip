@@ -19,7 +19,7 @@ namespace rbl {
 // ---------------------------------------------------------------------------
 // Reference constants
 // ---------------------------------------------------------------------------
-__global__ void k_ref_setup(Theta13 th, Network net, int32_t waveform, RefConsts* out) {
+__global__ void k_ref_setup(Theta13 th, Network net, int32_t waveform, NrtConsts nc, RefConsts* out) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     RefConsts r{};
     const double* t = th.v;
@@ -35,7 +35,7 @@ __global__ void k_ref_setup(Theta13 th, Network net, int32_t waveform, RefConsts
     r.amp0 = c.amp;
     if (waveform == kWfNrtv2) {
         // the edge phase is taken absolutely: no constant phase in h0fac
-        nrt_params<double>(t[0], t[1], t[2], t[3], t[4], t[5], r.nrt);
+        nrt_params<double>(t[0], t[1], t[2], t[3], t[4], t[5], nc, r.nrt);
         r.c0_const = 0.0;
         c.c_const = 0.0;
     }
@@ -58,6 +58,7 @@ __global__ void k_ref_setup(Theta13 th, Network net, int32_t waveform, RefConsts
         r.h0fac_re[d] = are * ce - aim * se;
         r.h0fac_im[d] = are * se + aim * ce;
     }
+    r.nc = nc;
     *out = r;
 }
 
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(64) void k_chain_setup(const double* __restrict__ t
     for (int i = 1; i < kRecUsed; ++i) out[i] = r[i];
     if (ref.waveform == kWfNrtv2) {
         NrtParams<double> np;
-        nrt_params<double>(t[0], t[1], t[2], t[3], t[4], t[5], np);
+        nrt_params<double>(t[0], t[1], t[2], t[3], t[4], t[5], ref.nc, np);
         const double* src = reinterpret_cast<const double*>(&np);
         for (int i = 0; i < kNrtParams; ++i) out[kRecNrt + i] = src[i];
     }
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(256) void k_chain_setup_grad(const double* __restri
         }
         if (ref.waveform == kWfNrtv2) {
             NrtParams<D1> np;
-            nrt_params<D1>(ti[0], ti[1], ti[2], ti[3], ti[4], ti[5], np);
+            nrt_params<D1>(ti[0], ti[1], ti[2], ti[3], ti[4], ti[5], ref.nc, np);
             const D1* pv = reinterpret_cast<const D1*>(&np);
             for (int k = 0; k < kNrtAdj; ++k) J[kJacInt + k * 6 + tg] = pv[k < kNrtAdjSkip ? k : k + 1].d[0];
             const D1 amp = tf2_amp<D1>(ti[0]);
@@ -533,7 +534,7 @@ hipError_t launch_ref_setup(const double* theta, const Network& net, int32_t wav
                             hipStream_t s) {
     Theta13 th;
     for (int i = 0; i < 13; ++i) th.v[i] = theta[i];
-    hipLaunchKernelGGL(k_ref_setup, dim3(1), dim3(64), 0, s, th, net, waveform, out_dev);
+    hipLaunchKernelGGL(k_ref_setup, dim3(1), dim3(64), 0, s, th, net, waveform, nrt_consts(), out_dev);
     return hipGetLastError();
 }
 

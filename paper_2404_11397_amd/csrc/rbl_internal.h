@@ -58,6 +58,7 @@ struct RefConsts {
     int32_t status;                                 // 1 if theta0 is valid
     int32_t waveform;                               // RBL_TAYLORF2 or RBL_PHENOMD_NRTV2
     NrtParams<double> nrt;                          // theta0 coefficients (IMRPhenomD_NRTidalv2; c0_const = 0)
+    NrtConsts nc;                                   // parameter-independent matching constants
 };
 
 // Detector network description passed by value to kernels.

@@ -65,11 +65,46 @@ constexpr double G(double p, int n) {
     for (int k = 1; k <= n; ++k) s += binom(n, k) * F(p, n - k) * ((k - 1) % 2 ? -1.0 : 1.0) * fact(k - 1);
     return s;
 }
+// The inspiral phase terms used in the matching: PN orders k = 0, 2..7 (p_k = (k - 5) / 3).
+constexpr int kMatchK[7] = {0, 2, 3, 4, 5, 6, 7};
+struct FGTable {
+    double F[7][4], G[7][4];
+};
+constexpr FGTable make_fg() {
+    FGTable t{};
+    for (int i = 0; i < 7; ++i)
+        for (int n = 0; n < 4; ++n) {
+            const double p = (kMatchK[i] - 5) / 3.0;
+            t.F[i][n] = F(p, n);
+            t.G[i][n] = G(p, n);
+        }
+    return t;
+}
+constexpr FGTable kFG = make_fg();
 }  // namespace nrt_detail
+
+// Parameter-independent powers used by the phase matching at Mf = 0.018, computed once on
+// the host: pi^(p_k), X^(p_k - n) with X = 0.018, ln X and ln(pi) / 3.
+struct NrtConsts {
+    double pip[7];
+    double xp[7][4];
+    double lX, lpi3;
+};
+__host__ inline NrtConsts nrt_consts() {
+    NrtConsts c{};
+    for (int i = 0; i < 7; ++i) {
+        const double p = (nrt_detail::kMatchK[i] - 5) / 3.0;
+        c.pip[i] = std::pow(kPi, p);
+        for (int n = 0; n < 4; ++n) c.xp[i][n] = std::pow(kNrtF1, p - n);
+    }
+    c.lX = std::log(kNrtF1);
+    c.lpi3 = std::log(kPi) / 3.0;
+    return c;
+}
 
 template <class T>
 __device__ inline void nrt_params(const T& mc, const T& q, const T& chi1, const T& chi2, const T& lam1,
-                                  const T& lam2, NrtParams<T>& o) {
+                                  const T& lam2, const NrtConsts& nc, NrtParams<T>& o) {
     using namespace nrt_detail;
     Tf2Pn<T> pn;
     const T zero(0.0);
@@ -96,18 +131,16 @@ __device__ inline void nrt_params(const T& mc, const T& q, const T& chi1, const 
     }
     // eta times the inspiral phase [rad] and its Mf-derivatives at F1, from the power form
     // Psi = -pi/4 + sum_k (A_k + B_k ln Mf) Mf^p_k, p_k = (k-5)/3
-    const double X = kNrtF1, lX = log(kNrtF1);
+    const double X = kNrtF1, lX = nc.lX;
     T y[4];
     {
         const T P3 = 3.0 / 128.0;  // eta * 3 / (128 eta)
-        const double lpi3 = log(kPi) / 3.0;
+        const double lpi3 = nc.lpi3;
         for (int n = 0; n < 4; ++n) y[n] = T(n == 0 ? -0.25 * kPi : 0.0) * eta;
-        const int ks[7] = {0, 2, 3, 4, 5, 6, 7};
 #pragma unroll
         for (int i = 0; i < 7; ++i) {
-            const int k = ks[i];
-            const double p = (k - 5) / 3.0;
-            const double pip = pow(kPi, p);
+            const int k = kMatchK[i];
+            const double pip = nc.pip[i];
             T A = P3 * pn.p[k] * pip;
             T Bc = T(0.0);
             if (k == 5) {
@@ -119,8 +152,9 @@ __device__ inline void nrt_params(const T& mc, const T& q, const T& chi1, const 
             }
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
-                const double xp = pow(X, p - n);
-                y[n] = y[n] + (A * F(p, n) + Bc * (F(p, n) * lX + G(p, n))) * xp;
+                const double xp = nc.xp[i][n];
+                const double Fn = kFG.F[i][n], Gn = kFG.G[i][n];
+                y[n] = y[n] + (A * Fn + Bc * (Fn * lX + Gn)) * xp;
             }
         }
     }

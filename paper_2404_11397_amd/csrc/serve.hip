@@ -42,7 +42,9 @@ int64_t class_of(int64_t B) {
     return c;
 }
 
-// Device layout of one request buffer of `cap` chains: theta | lnl | grad | workspace.
+// Device layout of one request buffer of `cap` chains: theta | lnl | grad | workspace
+// (cap is a multiple of 256, so lnl occupies exactly cap doubles and grad follows it, as in
+// the pinned result buffer).
 struct BufLayout {
     int64_t theta, lnl, grad, ws, total;
     explicit BufLayout(int64_t cap)
@@ -208,10 +210,9 @@ hipError_t enqueue(const Request* r, const Buffer* b, hipStream_t s) {
     e = r->grad ? launch_loglike_grad(r->ev->dev, rec, jac, B, mixed, d_lnl, d_grad, s)
                 : launch_loglike(r->ev->dev, rec, B, mixed, d_lnl, s);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(b->h_out, d_lnl, (size_t)(B * sizeof(double)), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess && r->grad)
-        e = hipMemcpyAsync(b->h_out + b->cap, d_grad, (size_t)(B * 13 * sizeof(double)), hipMemcpyDeviceToHost, s);
-    return e;
+    // lnl [cap] and grad [cap][13] are contiguous on both sides: one copy back
+    const size_t out_bytes = r->grad ? (size_t)((b->cap + B * 13) * sizeof(double)) : (size_t)(B * sizeof(double));
+    return hipMemcpyAsync(b->h_out, d_lnl, out_bytes, hipMemcpyDeviceToHost, s);
 }
 
 hipGraphExec_t capture(const Request* r, const Buffer* b, hipStream_t s) {

@@ -154,8 +154,9 @@ COPY_BYTES = 256 << 20   # the calibration copy reads and writes this many bytes
 
 
 def calibrate_copy(torch, repeats=10):
-    """A plain device-to-device copy of COPY_BYTES (one copy kernel per launch): the
-    FETCH_SIZE / WRITE_SIZE counters of this launch give the scale factor from counter
+    """Plain copies of COPY_BYTES between two device buffers, one kernel per launch: the
+    runtime's copy (hipMemcpyAsync device to device) and an elementwise kernel (y = x + 0).
+    The FETCH_SIZE / WRITE_SIZE counters of these launches give the scale from counter
     units to HBM bytes."""
     x = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
     y = torch.empty_like(x)
@@ -163,7 +164,11 @@ def calibrate_copy(torch, repeats=10):
     for _ in range(repeats):
         y.copy_(x)
     torch.cuda.synchronize()
-    return {"bytes_read_per_launch": COPY_BYTES, "bytes_written_per_launch": COPY_BYTES, "launches": repeats}
+    for _ in range(repeats):
+        torch.add(x, 0.0, out=y)
+    torch.cuda.synchronize()
+    return {"bytes_read_per_launch": COPY_BYTES, "bytes_written_per_launch": COPY_BYTES, "launches": repeats,
+            "kernels": ["runtime device copy", "elementwise y = x + 0"]}
 
 
 KERNEL_SOURCES = ("likelihood.hip", "kernels.hip", "rbl_launch.h", "rbl_internal.h", "rbl_wave.h", "rbl_math.h",

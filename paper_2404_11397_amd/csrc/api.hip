@@ -38,11 +38,12 @@ bool theta_in_domain(const double* t) {
            t[4] >= 0.0 && t[5] >= 0.0;
 }
 
-// Benchmark timing: events around the setup and main kernel of each call.
+// Benchmark timing: the runtime records start / stop events at the setup kernel's and the
+// main kernel's own start and end (hipExtLaunchKernel), so the times are kernel durations.
 struct ProfState {
     bool on = false;
     std::vector<hipEvent_t> free_events;
-    std::vector<std::array<hipEvent_t, 3>> pending;  // start, after setup, after main
+    std::vector<std::array<hipEvent_t, 4>> pending;  // setup start, setup stop, main start, main stop
     double summary_ms = 0.0;                          // summary-pass kernels of rbl_event_create
     int64_t summary_n = 0;
     hipEvent_t get() {
@@ -59,20 +60,17 @@ struct ProfState {
 ProfState g_prof;
 
 struct CallTimer {
-    std::array<hipEvent_t, 3> ev{{nullptr, nullptr, nullptr}};
-    hipStream_t s;
-    explicit CallTimer(hipStream_t st) : s(st) {
+    std::array<hipEvent_t, 4> ev{{nullptr, nullptr, nullptr, nullptr}};
+    bool active = false;
+    CallTimer() {
         if (!g_prof.on) return;
         for (auto& e : ev) e = g_prof.get();
-        if (ev[0]) (void)hipEventRecord(ev[0], s);
+        active = ev[0] && ev[1] && ev[2] && ev[3];
     }
-    void mark_setup() {
-        if (g_prof.on && ev[1]) (void)hipEventRecord(ev[1], s);
-    }
+    KTime setup() const { return active ? KTime{ev[0], ev[1]} : KTime{}; }
+    KTime main() const { return active ? KTime{ev[2], ev[3]} : KTime{}; }
     void done() {
-        if (!g_prof.on || !ev[0] || !ev[1] || !ev[2]) return;
-        (void)hipEventRecord(ev[2], s);
-        g_prof.pending.push_back(ev);
+        if (active) g_prof.pending.push_back(ev);
     }
 };
 
@@ -95,11 +93,11 @@ extern "C" int rbl_profile_read(double* main_ms, double* setup_ms, int64_t* call
     double m = 0.0, st = 0.0;
     int64_t n = 0;
     for (auto& t : g_prof.pending) {
-        hipError_t e = hipEventSynchronize(t[2]);
+        hipError_t e = hipEventSynchronize(t[3]);
         if (e != hipSuccess) return hip_fail(e, "rbl_profile_read");
         float a = 0.f, b = 0.f;
         (void)hipEventElapsedTime(&a, t[0], t[1]);
-        (void)hipEventElapsedTime(&b, t[1], t[2]);
+        (void)hipEventElapsedTime(&b, t[2], t[3]);
         st += a;
         m += b;
         ++n;
@@ -322,12 +320,11 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     if (g_prof.on) {
         t0 = g_prof.get();
         t1 = g_prof.get();
-        if (t0) (void)hipEventRecord(t0, s);
     }
-    if ((e = launch_summary(sa, d_bin_first, ev->d_summary, s)) != hipSuccess)
+    const KTime skt = (t0 && t1) ? KTime{t0, t1} : KTime{};
+    if ((e = launch_summary(sa, d_bin_first, ev->d_summary, s, skt)) != hipSuccess)
         return cleanup(hip_fail(e, "rbl_event_create: summary pass"));
     if (t0 && t1) {
-        (void)hipEventRecord(t1, s);
         if (hipEventSynchronize(t1) == hipSuccess) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, t0, t1) == hipSuccess) {
@@ -451,11 +448,10 @@ extern "C" int rbl_loglike(const rbl_event* ev, const double* theta_dev, int64_t
     if (rc || B == 0) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     double* rec = (double*)workspace;
-    CallTimer tm(s);
-    hipError_t e = launch_chain_setup(theta_dev, B, ev->net, ev->ref, rec, nullptr, s);
+    CallTimer tm;
+    hipError_t e = launch_chain_setup(theta_dev, B, ev->net, ev->ref, rec, nullptr, s, tm.setup());
     if (e != hipSuccess) return hip_fail(e, "rbl_loglike: setup launch");
-    tm.mark_setup();
-    e = launch_loglike(ev->dev, rec, B, precision == RBL_MIXED, lnl_dev, s);
+    e = launch_loglike(ev->dev, rec, B, precision == RBL_MIXED, lnl_dev, s, tm.main());
     if (e != hipSuccess) return hip_fail(e, "rbl_loglike: launch");
     tm.done();
     return RBL_OK;
@@ -469,11 +465,10 @@ extern "C" int rbl_loglike_grad(const rbl_event* ev, const double* theta_dev, in
     hipStream_t s = (hipStream_t)hip_stream;
     double* rec = (double*)workspace;
     double* jac = (double*)((char*)workspace + align_up(B * kRecStride * (int64_t)sizeof(double)));
-    CallTimer tm(s);
-    hipError_t e = launch_chain_setup(theta_dev, B, ev->net, ev->ref, rec, jac, s);
+    CallTimer tm;
+    hipError_t e = launch_chain_setup(theta_dev, B, ev->net, ev->ref, rec, jac, s, tm.setup());
     if (e != hipSuccess) return hip_fail(e, "rbl_loglike_grad: setup launch");
-    tm.mark_setup();
-    e = launch_loglike_grad(ev->dev, rec, jac, B, precision == RBL_MIXED, lnl_dev, grad_dev, s);
+    e = launch_loglike_grad(ev->dev, rec, jac, B, precision == RBL_MIXED, lnl_dev, grad_dev, s, tm.main());
     if (e != hipSuccess) return hip_fail(e, "rbl_loglike_grad: launch");
     tm.done();
     return RBL_OK;
@@ -487,10 +482,9 @@ extern "C" int rbl_loglike_full(const rbl_event* ev, const double* theta_dev, in
         return fail(RBL_EUNSUPPORTED, "rbl_loglike_full: event built without RBL_KEEP_GRID");
     hipStream_t s = (hipStream_t)hip_stream;
     double* rec = (double*)workspace;
-    CallTimer tm(s);
-    hipError_t e = launch_chain_setup(theta_dev, B, ev->net, ev->ref, rec, nullptr, s);
+    CallTimer tm;
+    hipError_t e = launch_chain_setup(theta_dev, B, ev->net, ev->ref, rec, nullptr, s, tm.setup());
     if (e != hipSuccess) return hip_fail(e, "rbl_loglike_full: setup launch");
-    tm.mark_setup();
     FullArgs a{};
     a.recs = rec;
     a.ref = ev->ref;
@@ -501,7 +495,7 @@ extern "C" int rbl_loglike_full(const rbl_event* ev, const double* theta_dev, in
     a.data = ev->d_data;
     a.psd = ev->d_psd;
     a.lnl = lnl_dev;
-    e = launch_loglike_full(a, B, s);
+    e = launch_loglike_full(a, B, s, tm.main());
     if (e != hipSuccess) return hip_fail(e, "rbl_loglike_full: launch");
     tm.done();
     return RBL_OK;

@@ -539,27 +539,28 @@ hipError_t launch_ref_setup(const double* theta, const Network& net, int32_t wav
 }
 
 hipError_t launch_chain_setup(const double* theta, int64_t B, const Network& net, const RefConsts& ref,
-                              double* rec, double* jac, hipStream_t s) {
+                              double* rec, double* jac, hipStream_t s, KTime kt) {
     if (jac) {
         const int64_t n_int = (B * kIntLanes + 255) / 256;
         const int64_t n_ext = (B * kExtLanes + 255) / 256;
-        hipLaunchKernelGGL(k_chain_setup_grad, dim3((unsigned)(n_int + n_ext)), dim3(256), 0, s, theta, B, net, ref,
+        launch_k(k_chain_setup_grad, dim3((unsigned)(n_int + n_ext)), dim3(256), s, kt, theta, B, net, ref,
                            rec, jac, n_int);
     } else {
-        hipLaunchKernelGGL(k_chain_setup, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, s, theta, B, net, ref, rec);
+        launch_k(k_chain_setup, dim3((unsigned)((B + 63) / 64)), dim3(64), s, kt, theta, B, net, ref, rec);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_summary(const SummaryArgs& a, const int64_t* bin_first_item, double* summary, hipStream_t s) {
+hipError_t launch_summary(const SummaryArgs& a, const int64_t* bin_first_item, double* summary, hipStream_t s,
+                          KTime kt) {
     const unsigned g1 = (unsigned)((a.n_items + 3) / 4);
     switch (a.n_det) {
-        case 1: hipLaunchKernelGGL(k_summary_items<1>, dim3(g1), dim3(256), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(k_summary_items<2>, dim3(g1), dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL(k_summary_items<3>, dim3(g1), dim3(256), 0, s, a); break;
+        case 1: launch_k(k_summary_items<1>, dim3(g1), dim3(256), s, KTime{kt.start, nullptr}, a); break;
+        case 2: launch_k(k_summary_items<2>, dim3(g1), dim3(256), s, KTime{kt.start, nullptr}, a); break;
+        default: launch_k(k_summary_items<3>, dim3(g1), dim3(256), s, KTime{kt.start, nullptr}, a); break;
     }
     const int64_t tot = (int64_t)a.n_det * a.n_bins * 7;
-    hipLaunchKernelGGL(k_summary_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a.partials,
+    launch_k(k_summary_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), s, KTime{nullptr, kt.stop}, a.partials,
                        bin_first_item, a.n_bins, a.n_det, summary);
     return hipGetLastError();
 }
@@ -570,8 +571,8 @@ hipError_t launch_node_tables(const NodeArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_loglike_full(const FullArgs& a, int64_t B, hipStream_t s) {
-    hipLaunchKernelGGL(k_loglike_full, dim3((unsigned)B), dim3(256), 0, s, a);
+hipError_t launch_loglike_full(const FullArgs& a, int64_t B, hipStream_t s, KTime kt) {
+    launch_k(k_loglike_full, dim3((unsigned)B), dim3(256), s, kt, a);
     return hipGetLastError();
 }
 

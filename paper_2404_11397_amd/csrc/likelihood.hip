@@ -537,57 +537,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNr
 // Launch wrappers: 4 chains (wavefronts) per 256-thread workgroup.
 // ---------------------------------------------------------------------------
 template <int ND>
-static void fwd_nd(const EventDev& ev, const double* rec, int64_t B, int mixed, double* lnl, hipStream_t s) {
+static void fwd_nd(const EventDev& ev, const double* rec, int64_t B, int mixed, double* lnl, hipStream_t s,
+                   KTime kt) {
     const unsigned grid = (unsigned)((B + 3) / 4);
     if (ev.waveform == kWfNrtv2) {
         if (mixed)
-            hipLaunchKernelGGL((k_loglike_fwd<ND, true, kWfNrtv2>), dim3(grid), dim3(256), 0, s, ev, rec, B, lnl);
+            launch_k(k_loglike_fwd<ND, true, kWfNrtv2>, dim3(grid), dim3(256), s, kt, ev, rec, B, lnl);
         else
-            hipLaunchKernelGGL((k_loglike_fwd<ND, false, kWfNrtv2>), dim3(grid), dim3(256), 0, s, ev, rec, B, lnl);
+            launch_k(k_loglike_fwd<ND, false, kWfNrtv2>, dim3(grid), dim3(256), s, kt, ev, rec, B, lnl);
     } else {
         if (mixed)
-            hipLaunchKernelGGL((k_loglike_fwd<ND, true, kWfTaylorF2>), dim3(grid), dim3(256), 0, s, ev, rec, B, lnl);
+            launch_k(k_loglike_fwd<ND, true, kWfTaylorF2>, dim3(grid), dim3(256), s, kt, ev, rec, B, lnl);
         else
-            hipLaunchKernelGGL((k_loglike_fwd<ND, false, kWfTaylorF2>), dim3(grid), dim3(256), 0, s, ev, rec, B, lnl);
+            launch_k(k_loglike_fwd<ND, false, kWfTaylorF2>, dim3(grid), dim3(256), s, kt, ev, rec, B, lnl);
     }
 }
 
-hipError_t launch_loglike(const EventDev& ev, const double* rec, int64_t B, int mixed, double* lnl, hipStream_t s) {
+hipError_t launch_loglike(const EventDev& ev, const double* rec, int64_t B, int mixed, double* lnl, hipStream_t s,
+                          KTime kt) {
     switch (ev.n_det) {
-        case 1: fwd_nd<1>(ev, rec, B, mixed, lnl, s); break;
-        case 2: fwd_nd<2>(ev, rec, B, mixed, lnl, s); break;
-        default: fwd_nd<3>(ev, rec, B, mixed, lnl, s); break;
+        case 1: fwd_nd<1>(ev, rec, B, mixed, lnl, s, kt); break;
+        case 2: fwd_nd<2>(ev, rec, B, mixed, lnl, s, kt); break;
+        default: fwd_nd<3>(ev, rec, B, mixed, lnl, s, kt); break;
     }
     return hipGetLastError();
 }
 
 template <int ND>
 static void grad_nd(const EventDev& ev, const double* rec, const double* jac, int64_t B, int mixed, double* lnl,
-                    double* grad, hipStream_t s) {
+                    double* grad, hipStream_t s, KTime kt) {
     const unsigned grid = (unsigned)((B + 3) / 4);
     if (ev.waveform == kWfNrtv2) {
         if (mixed)
-            hipLaunchKernelGGL((k_loglike_grad<ND, true, kWfNrtv2>), dim3(grid), dim3(256), 0, s, ev, rec, jac, B,
+            launch_k(k_loglike_grad<ND, true, kWfNrtv2>, dim3(grid), dim3(256), s, kt, ev, rec, jac, B,
                                lnl, grad);
         else
-            hipLaunchKernelGGL((k_loglike_grad<ND, false, kWfNrtv2>), dim3(grid), dim3(256), 0, s, ev, rec, jac, B,
+            launch_k(k_loglike_grad<ND, false, kWfNrtv2>, dim3(grid), dim3(256), s, kt, ev, rec, jac, B,
                                lnl, grad);
     } else {
         if (mixed)
-            hipLaunchKernelGGL((k_loglike_grad<ND, true, kWfTaylorF2>), dim3(grid), dim3(256), 0, s, ev, rec, jac,
+            launch_k(k_loglike_grad<ND, true, kWfTaylorF2>, dim3(grid), dim3(256), s, kt, ev, rec, jac,
                                B, lnl, grad);
         else
-            hipLaunchKernelGGL((k_loglike_grad<ND, false, kWfTaylorF2>), dim3(grid), dim3(256), 0, s, ev, rec, jac,
+            launch_k(k_loglike_grad<ND, false, kWfTaylorF2>, dim3(grid), dim3(256), s, kt, ev, rec, jac,
                                B, lnl, grad);
     }
 }
 
 hipError_t launch_loglike_grad(const EventDev& ev, const double* rec, const double* jac, int64_t B, int mixed,
-                               double* lnl, double* grad, hipStream_t s) {
+                               double* lnl, double* grad, hipStream_t s, KTime kt) {
     switch (ev.n_det) {
-        case 1: grad_nd<1>(ev, rec, jac, B, mixed, lnl, grad, s); break;
-        case 2: grad_nd<2>(ev, rec, jac, B, mixed, lnl, grad, s); break;
-        default: grad_nd<3>(ev, rec, jac, B, mixed, lnl, grad, s); break;
+        case 1: grad_nd<1>(ev, rec, jac, B, mixed, lnl, grad, s, kt); break;
+        case 2: grad_nd<2>(ev, rec, jac, B, mixed, lnl, grad, s, kt); break;
+        default: grad_nd<3>(ev, rec, jac, B, mixed, lnl, grad, s, kt); break;
     }
     return hipGetLastError();
 }

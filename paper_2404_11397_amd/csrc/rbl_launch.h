@@ -1,5 +1,6 @@
 // Kernel argument blocks and launch wrappers (internal to the library).
 #pragma once
+#include <hip/hip_ext.h>
 #include "rbl_internal.h"
 
 namespace rbl {
@@ -51,16 +52,32 @@ struct FullArgs {
     double* lnl;
 };
 
+// Optional start / stop events recorded by the runtime at the kernel's own start and end
+// (benchmark timing); both null = a plain launch.
+struct KTime {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+template <typename F, typename... Args>
+inline void launch_k(F kernel, dim3 grid, dim3 block, hipStream_t s, KTime kt, Args... args) {
+    if (kt.start || kt.stop)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, kt.start, kt.stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
+
 hipError_t launch_ref_setup(const double* theta_host, const Network& net, int32_t waveform, RefConsts* out_dev,
                             hipStream_t s);
 hipError_t launch_chain_setup(const double* theta, int64_t B, const Network& net, const RefConsts& ref,
-                              double* rec, double* jac, hipStream_t s);   // jac requires a TaylorF2 event
-hipError_t launch_summary(const SummaryArgs& a, const int64_t* bin_first_item, double* summary, hipStream_t s);
+                              double* rec, double* jac, hipStream_t s, KTime kt = {});
+// kt.start is recorded at the start of the per-item kernel, kt.stop at the end of the reduction.
+hipError_t launch_summary(const SummaryArgs& a, const int64_t* bin_first_item, double* summary, hipStream_t s,
+                          KTime kt = {});
 hipError_t launch_node_tables(const NodeArgs& a, hipStream_t s);
-hipError_t launch_loglike(const EventDev& ev, const double* rec, int64_t B, int mixed, double* lnl, hipStream_t s);
+hipError_t launch_loglike(const EventDev& ev, const double* rec, int64_t B, int mixed, double* lnl, hipStream_t s,
+                          KTime kt = {});
 hipError_t launch_loglike_grad(const EventDev& ev, const double* rec, const double* jac, int64_t B, int mixed,
-                               double* lnl, double* grad, hipStream_t s);
-hipError_t launch_loglike_full(const FullArgs& a, int64_t B, hipStream_t s);
+                               double* lnl, double* grad, hipStream_t s, KTime kt = {});
+hipError_t launch_loglike_full(const FullArgs& a, int64_t B, hipStream_t s, KTime kt = {});
 hipError_t launch_strain(const RefConsts* cst_dev, int32_t waveform, int32_t taper, int32_t n_det, double f_low,
                          double delta_f, int64_t n_freq, double* out, hipStream_t s);
 

@@ -316,25 +316,23 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     sa.partials = d_partials;
     sa.ref = ev->ref;
     sa.ref_taper = (desc->flags & RBL_REF_TAPER) ? 1 : 0;
-    hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (g_prof.on) {
-        t0 = g_prof.get();
-        t1 = g_prof.get();
-    }
-    const KTime skt = (t0 && t1) ? KTime{t0, t1} : KTime{};
-    if ((e = launch_summary(sa, d_bin_first, ev->d_summary, s, skt)) != hipSuccess)
+    // benchmark timing: the two kernels' own durations, summed
+    std::array<hipEvent_t, 4> te{{nullptr, nullptr, nullptr, nullptr}};
+    if (g_prof.on)
+        for (auto& t : te) t = g_prof.get();
+    const bool timed = te[0] && te[1] && te[2] && te[3];
+    if ((e = launch_summary(sa, d_bin_first, ev->d_summary, s, timed ? KTime{te[0], te[1]} : KTime{},
+                            timed ? KTime{te[2], te[3]} : KTime{})) != hipSuccess)
         return cleanup(hip_fail(e, "rbl_event_create: summary pass"));
-    if (t0 && t1) {
-        if (hipEventSynchronize(t1) == hipSuccess) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, t0, t1) == hipSuccess) {
-                g_prof.summary_ms += ms;
-                g_prof.summary_n += 1;
-            }
+    if (timed && hipEventSynchronize(te[3]) == hipSuccess) {
+        float m1 = 0.f, m2 = 0.f;
+        if (hipEventElapsedTime(&m1, te[0], te[1]) == hipSuccess && hipEventElapsedTime(&m2, te[2], te[3]) == hipSuccess) {
+            g_prof.summary_ms += m1 + m2;
+            g_prof.summary_n += 1;
         }
     }
-    if (t0) g_prof.free_events.push_back(t0);
-    if (t1) g_prof.free_events.push_back(t1);
+    for (auto t : te)
+        if (t) g_prof.free_events.push_back(t);
 
     NodeArgs na{};
     na.n_nodes = ev->n_nodes;

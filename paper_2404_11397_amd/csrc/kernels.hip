@@ -552,15 +552,15 @@ hipError_t launch_chain_setup(const double* theta, int64_t B, const Network& net
 }
 
 hipError_t launch_summary(const SummaryArgs& a, const int64_t* bin_first_item, double* summary, hipStream_t s,
-                          KTime kt) {
+                          KTime kt_items, KTime kt_reduce) {
     const unsigned g1 = (unsigned)((a.n_items + 3) / 4);
     switch (a.n_det) {
-        case 1: launch_k(k_summary_items<1>, dim3(g1), dim3(256), s, KTime{kt.start, nullptr}, a); break;
-        case 2: launch_k(k_summary_items<2>, dim3(g1), dim3(256), s, KTime{kt.start, nullptr}, a); break;
-        default: launch_k(k_summary_items<3>, dim3(g1), dim3(256), s, KTime{kt.start, nullptr}, a); break;
+        case 1: launch_k(k_summary_items<1>, dim3(g1), dim3(256), s, kt_items, a); break;
+        case 2: launch_k(k_summary_items<2>, dim3(g1), dim3(256), s, kt_items, a); break;
+        default: launch_k(k_summary_items<3>, dim3(g1), dim3(256), s, kt_items, a); break;
     }
     const int64_t tot = (int64_t)a.n_det * a.n_bins * 7;
-    launch_k(k_summary_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), s, KTime{nullptr, kt.stop}, a.partials,
+    launch_k(k_summary_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), s, kt_reduce, a.partials,
                        bin_first_item, a.n_bins, a.n_det, summary);
     return hipGetLastError();
 }

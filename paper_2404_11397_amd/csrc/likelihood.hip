@@ -394,10 +394,10 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
     }
 }
 
-// Occupancy target: 3 waves per SIMD for TaylorF2; 2 for NRTidalv2, whose 26 adjoint
+// Occupancy target: 4 waves per SIMD for TaylorF2; 2 for NRTidalv2, whose 26 adjoint
 // accumulators and per-edge model would otherwise spill.
 template <int ND, bool MIXED, int WF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNrtv2 ? 2 : 3))) void k_loglike_grad(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNrtv2 ? 2 : 4))) void k_loglike_grad(
     EventDev ev, const double* __restrict__ recs, const double* __restrict__ jac, int64_t B,
     double* __restrict__ lnl, double* __restrict__ grad) {
     const int lane = threadIdx.x & 63;

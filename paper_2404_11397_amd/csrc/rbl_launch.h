@@ -69,9 +69,9 @@ hipError_t launch_ref_setup(const double* theta_host, const Network& net, int32_
                             hipStream_t s);
 hipError_t launch_chain_setup(const double* theta, int64_t B, const Network& net, const RefConsts& ref,
                               double* rec, double* jac, hipStream_t s, KTime kt = {});
-// kt.start is recorded at the start of the per-item kernel, kt.stop at the end of the reduction.
+// kt_items / kt_reduce: timing of the per-item kernel and of the reduction.
 hipError_t launch_summary(const SummaryArgs& a, const int64_t* bin_first_item, double* summary, hipStream_t s,
-                          KTime kt = {});
+                          KTime kt_items = {}, KTime kt_reduce = {});
 hipError_t launch_node_tables(const NodeArgs& a, hipStream_t s);
 hipError_t launch_loglike(const EventDev& ev, const double* rec, int64_t B, int mixed, double* lnl, hipStream_t s,
                           KTime kt = {});

@@ -200,7 +200,7 @@ int rbl_server_create(int64_t hbm_budget_bytes, int32_t n_streams, uint32_t flag
  * events already registered and the current buffer pool. */
 int rbl_server_add_event(rbl_server *srv, const rbl_event *ev, int32_t *event_id);
 
-/* Unregister an event; RBL_EINVAL if requests for it are queued or running. */
+/* Unregister an event; RBL_EINVAL while requests for it have not been waited for. */
 int rbl_server_remove_event(rbl_server *srv, int32_t event_id);
 
 /* Queue one request: B chains of theta_host [B][13] (host float64) for a registered event.

@@ -101,7 +101,7 @@ struct rbl_server {
     std::unordered_map<int64_t, Request*> reqs;
     int64_t next_ticket = 1;
     std::map<int32_t, const rbl_event*> events;
-    std::map<int32_t, int64_t> users;  // queued + running requests per event
+    std::map<int32_t, int64_t> users;  // requests per event not yet waited for
     int32_t next_event = 0;
     int64_t resident = 0;
     int64_t buffer_bytes = 0;
@@ -236,7 +236,6 @@ void complete(rbl_server* S, Request* r, int status) {
     r->info.status = status;
     r->info.t_done_ns = now_ns();
     r->state = 2;
-    S->users[r->event]--;
     S->st.completed++;
 }
 
@@ -461,6 +460,7 @@ extern "C" int rbl_server_wait(rbl_server* S, int64_t ticket, rbl_request_info* 
     S->cv_done.wait(lk, [&] { return r->state == 2; });
     if (info) *info = r->info;
     const int status = r->info.status;
+    S->users[r->event]--;
     S->reqs.erase(it);
     delete r;
     if (status != RBL_OK) return fail(status, "rbl_server_wait: request failed");

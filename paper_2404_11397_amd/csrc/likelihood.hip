@@ -167,12 +167,12 @@ template <int ND, class R>
 __device__ inline double fwd_walk_natural(const EventDev& ev, const ChainVals<ND>& cv, int lane) {
     const EdgeTab<R> T = edge_tab(ev, R(0));
     const int npad = ev.n_nodes_pad;
-    R kre[ND], kim[ND], cre[ND], cim[ND];
+    R kre[ND], kim[ND], pre[ND], pim[ND];  // pre/pim: the previous step's ratios
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         kre[d] = (R)cv.kre[d];
         kim[d] = (R)cv.kim[d];
-        cre[d] = cim[d] = R(0);
+        pre[d] = pim[d] = R(0);
     }
     double acc = 0.0;
     for (int k = 0; k < ev.L; ++k) {
@@ -182,13 +182,13 @@ __device__ inline double fwd_walk_natural(const EventDev& ev, const ChainVals<ND
         nrt_ratio<ND, R>(ev, cv, pos, kre, kim, rre, rim, a);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
-            const R lre = shift_up(rre[d], cre[d]), lim = shift_up(rim[d], cim[d]);
+            const R lre = left_neighbour(rre[d], pre[d]), lim = left_neighbour(rim[d], pim[d]);
             const unsigned o = (unsigned)(d * npad) + pos;
             const R t = (ld(T.gre, o) * rre[d] + ld(T.gim, o) * rim[d]) - R(0.5) * ld(T.mu, o) * (rre[d] * rre[d] + rim[d] * rim[d])
                       - R(0.5) * ld(T.nul, o) * (lre * rre[d] + lim * rim[d]);
             acc += (double)t;
-            cre[d] = lane_read(rre[d], 63);
-            cim[d] = lane_read(rim[d], 63);
+            pre[d] = rre[d];
+            pim[d] = rim[d];
         }
     }
     return acc;
@@ -344,12 +344,12 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
     const R* nur = nur_tab(ev, R(0));
     const int npad = ev.n_nodes_pad;
     const int L = ev.L;
-    R kre[ND], kim[ND], rcr[ND], rci[ND], rnr[ND], rni[ND], cre[ND], cim[ND];
+    R kre[ND], kim[ND], rcr[ND], rci[ND], rnr[ND], rni[ND], rpr[ND], rpi[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         kre[d] = (R)cv.kre[d];
         kim[d] = (R)cv.kim[d];
-        cre[d] = cim[d] = R(0);
+        rpr[d] = rpi[d] = R(0);
     }
     double acur, anext = 0.0;
     nrt_ratio<ND, R>(ev, cv, lane, kre, kim, rcr, rci, acur);
@@ -366,8 +366,8 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const R rre = rcr[d], rim = rci[d];
-            const R lre = shift_up(rre, cre[d]), lim = shift_up(rim, cim[d]);
-            const R nre = shift_down(rre, lane_read(rnr[d], 0)), nim = shift_down(rim, lane_read(rni[d], 0));
+            const R lre = left_neighbour(rre, rpr[d]), lim = left_neighbour(rim, rpi[d]);
+            const R nre = right_neighbour(rre, rnr[d]), nim = right_neighbour(rim, rni[d]);
             const unsigned o = (unsigned)(d * npad) + pos;
             const R gre = ld(T.gre, o), gim = ld(T.gim, o), mu = ld(T.mu, o);
             const R cl = R(-0.5) * ld(T.nul, o), cr = R(-0.5) * ld(nur, o);
@@ -380,13 +380,13 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
             G.ta[d] = fma(zi, f, G.ta[d]);
             wre += zr;
             wim += zi;
-            cre[d] = lane_read(rre, 63);
-            cim[d] = lane_read(rim, 63);
         }
         nrt_node_adjoint(cv.np, f, ld(ev.node_x, pos), ld(ev.node_ix, pos), ld(ev.node_lx, pos), ld(ev.node_x578, pos),
                          (2.0 * kPi) * wim, acur != 0.0 ? wre / acur : 0.0, G.sa);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
+            rpr[d] = rcr[d];
+            rpi[d] = rci[d];
             rcr[d] = rnr[d];
             rci[d] = rni[d];
         }

@@ -51,6 +51,13 @@ __device__ inline R shift_up(R v, R fill) { return wave_shift<0x138>(v, fill); }
 // lane i receives lane i+1's value; lane 63 receives `fill`
 template <class R>
 __device__ inline R shift_down(R v, R fill) { return wave_shift<0x130>(v, fill); }
+// Neighbours across steps of 64 edges, without leaving vector registers: lane i receives
+// cur[i-1], lane 0 the previous step's lane 63 (rotate prev right by one, then shift);
+// resp. lane i receives cur[i+1], lane 63 the next step's lane 0.
+template <class R>
+__device__ inline R left_neighbour(R cur, R prev) { return shift_up(cur, wave_shift<0x13C>(prev, prev)); }
+template <class R>
+__device__ inline R right_neighbour(R cur, R next) { return shift_down(cur, wave_shift<0x134>(next, next)); }
 __device__ inline double shift_up(double v, double fill, int) { return shift_up<double>(v, fill); }
 __device__ inline float shift_up(float v, float fill, int) { return shift_up<float>(v, fill); }
 

@@ -146,10 +146,11 @@ __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, i
 // the previous step (a wave-uniform carry).
 template <int ND, class R>
 __device__ inline void nrt_ratio(const EventDev& ev, const ChainVals<ND>& cv, unsigned pos, const R* kre, const R* kim,
-                                 R* rre, R* rim, double& a) {
+                                 R* rre, R* rim, double& a, NrtShared* sh = nullptr) {
     const double f = ld(ev.node_f, pos);
     double ph;
-    nrt_node(cv.np, f, ld(ev.node_x, pos), ld(ev.node_ix, pos), ld(ev.node_lx, pos), ld(ev.node_x578, pos), true, ph, a);
+    nrt_node(cv.np, f, ld(ev.node_x, pos), ld(ev.node_ix, pos), ld(ev.node_lx, pos), ld(ev.node_x578, pos), true, ph, a,
+             sh);
     const double dph = ph - ld(ev.phi0, pos);
     const R ar = (R)(a * ld(ev.ia0, pos));
 #pragma unroll
@@ -352,10 +353,11 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
         rpr[d] = rpi[d] = R(0);
     }
     double acur, anext = 0.0;
-    nrt_ratio<ND, R>(ev, cv, lane, kre, kim, rcr, rci, acur);
+    NrtShared scur, snext{0.0, 0.0, 0.0};
+    nrt_ratio<ND, R>(ev, cv, lane, kre, kim, rcr, rci, acur, &scur);
     for (int k = 0; k < L; ++k) {
         if (k + 1 < L) {
-            nrt_ratio<ND, R>(ev, cv, (k + 1) * 64 + lane, kre, kim, rnr, rni, anext);
+            nrt_ratio<ND, R>(ev, cv, (k + 1) * 64 + lane, kre, kim, rnr, rni, anext, &snext);
         } else {
 #pragma unroll
             for (int d = 0; d < ND; ++d) rnr[d] = rni[d] = R(0);
@@ -382,7 +384,7 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
             wim += zi;
         }
         nrt_node_adjoint(cv.np, f, ld(ev.node_x, pos), ld(ev.node_ix, pos), ld(ev.node_lx, pos), ld(ev.node_x578, pos),
-                         (2.0 * kPi) * wim, acur != 0.0 ? wre / acur : 0.0, G.sa);
+                         scur, (2.0 * kPi) * wim, acur != 0.0 ? wre / acur : 0.0, G.sa);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             rpr[d] = rcr[d];
@@ -391,6 +393,7 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
             rci[d] = rni[d];
         }
         acur = anext;
+        scur = snext;
     }
 }
 

@@ -207,10 +207,16 @@ __device__ inline void nrt_params(const T& mc, const T& q, const T& chi1, const 
     o.s578 = dexp(5.78 * o.lns);
 }
 
+// Quotients of one edge that the adjoint reuses: num/den and 1/den of the tidal phase,
+// 1/(1 + 13477.8 xt^4) of the tidal amplitude.
+struct NrtShared {
+    double rat, iden, idd;
+};
+
 // Phase [rev] and amplitude factor a = (a_pp + a_T) w at one frequency, given
 // x = f^(1/3), 1/x, ln x and x^5.78 (so that (s x)^5.78 = s578 x^5.78 needs no exp).
 __device__ inline void nrt_node(const NrtParams<double>& p, double f, double x, double ix, double lx, double x578,
-                                bool taper, double& phi, double& a) {
+                                bool taper, double& phi, double& a, NrtShared* sh = nullptr) {
     const double mf = p.ms * f;
     double ph;
     if (mf < kNrtF1) {
@@ -231,11 +237,14 @@ __device__ inline void nrt_node(const NrtParams<double>& p, double f, double x, 
     const double xt2 = xt * xt;
     const double num = 1.0 + kTn1 * xt + kTn32 * xt * sx + kTn2 * xt2 + kTn52 * xt2 * sx + kTn3 * xt2 * xt;
     const double den = 1.0 + kTd1 * xt + kTd32 * xt * sx + kTd2 * xt2;
-    phi = ph + p.tp * xt2 * sx * num / den;
+    const double iden = 1.0 / den;
+    const double rat = num * iden;
+    phi = ph + p.tp * xt2 * sx * rat;
     const double app = mf < p.fpk ? 1.0 : exp(-(mf - p.fpk) / p.fdp);
-    const double at = p.m9k * (xt2 * xt2 * xt) * (1.0 + (449.0 / 108.0) * xt + (22672.0 / 9.0) * (p.s578 * x578)) /
-                      (1.0 + 13477.8 * xt2 * xt2);
+    const double idd = 1.0 / (1.0 + 13477.8 * xt2 * xt2);
+    const double at = p.m9k * (xt2 * xt2 * xt) * (1.0 + (449.0 / 108.0) * xt + (22672.0 / 9.0) * (p.s578 * x578)) * idd;
     a = app + at;
+    if (sh) *sh = NrtShared{rat, iden, idd};
     if (taper) {
         const double fe = 1.2 * p.fm;
         if (f >= fe) {
@@ -260,7 +269,7 @@ constexpr int kAdjMs = 0, kAdjLnMs = 1, kAdjS = 2, kAdjLnS = 3, kAdjC = 4, kAdjC
               kAdjTp = 21, kAdjM9k = 22, kAdjFpk = 23, kAdjFdp = 24, kAdjFm = 25;
 
 __device__ inline void nrt_node_adjoint(const NrtParams<double>& p, double f, double x, double ix, double lx,
-                                        double x578, double gphi, double ga, double* acc) {
+                                        double x578, const NrtShared& sh, double gphi, double ga, double* acc) {
     const double mf = p.ms * f;
     if (mf < kNrtF1) {
         const double ix2 = ix * ix, ix3 = ix2 * ix;
@@ -299,13 +308,11 @@ __device__ inline void nrt_node_adjoint(const NrtParams<double>& p, double f, do
     const double xt = sx * sx;
     const double xt2 = xt * xt;
     const double sx5 = xt2 * sx;
-    const double num = 1.0 + kTn1 * xt + kTn32 * xt * sx + kTn2 * xt2 + kTn52 * xt2 * sx + kTn3 * xt2 * xt;
-    const double den = 1.0 + kTd1 * xt + kTd32 * xt * sx + kTd2 * xt2;
     const double dnum = sx * (2.0 * kTn1 + 3.0 * kTn32 * sx + 4.0 * kTn2 * xt + 5.0 * kTn52 * xt * sx + 6.0 * kTn3 * xt2);
     const double dden = sx * (2.0 * kTd1 + 3.0 * kTd32 * sx + 4.0 * kTd2 * xt);
-    const double rat = num / den;
+    const double rat = sh.rat;
     acc[kAdjTp] = fma(gphi, sx5 * rat, acc[kAdjTp]);
-    const double dtid = p.tp * (5.0 * xt2 * rat + sx5 * (dnum - rat * dden) / den);  // d tidal / d sx
+    const double dtid = p.tp * (5.0 * xt2 * rat + sx5 * (dnum - rat * dden) * sh.iden);  // d tidal / d sx
     double gs = gphi * dtid * x;                                                      // -> d / ds
     // amplitude a = (a_pp + a_T) w
     double w = 1.0, dw = 0.0;  // taper and its derivative with respect to f_merger
@@ -338,8 +345,7 @@ __device__ inline void nrt_node_adjoint(const NrtParams<double>& p, double f, do
     const double e289 = p.s578 * x578;  // xt^2.89
     const double xt4 = xt2 * xt2;
     const double nn = 1.0 + (449.0 / 108.0) * xt + (22672.0 / 9.0) * e289;
-    const double dd = 1.0 + 13477.8 * xt4;
-    const double idd = 1.0 / dd;
+    const double idd = sh.idd;
     const double base = xt4 * xt * nn * idd;  // a_T / m9k
     acc[kAdjM9k] = fma(gA, base, acc[kAdjM9k]);
     const double dat_dxt = p.m9k * (5.0 * xt4 * nn * idd + xt4 * xt * ((449.0 / 108.0) - nn * idd * (4.0 * 13477.8) * xt2 * xt) * idd);

@@ -253,37 +253,28 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
             return cleanup(fail(RBL_EREF, "rbl_event_create: reference strain vanishes in detector " + std::to_string(d)));
     }
 
-    // Work items of the summary pass: runs of <= kChunk points inside one bin.
-    std::vector<int32_t> item_bin;
-    std::vector<int64_t> item_start;
-    std::vector<int32_t> item_count;
+    // Work items of the summary pass: runs of <= kChunk points inside one bin; the bin centre
+    // f_m = (f_{e_b} + f_{e_{b+1}}) / 2 of the linear model is attached to each item.
+    std::vector<SumItem> items;
     std::vector<int64_t> bin_first((size_t)nb + 1);
     for (int32_t b = 0; b < nb; ++b) {
-        bin_first[(size_t)b] = (int64_t)item_bin.size();
+        bin_first[(size_t)b] = (int64_t)items.size();
         const int64_t lo = desc->edges[b];
         const int64_t hi = (b == nb - 1) ? n : desc->edges[b + 1];
-        for (int64_t k = lo; k < hi; k += kChunk) {
-            item_bin.push_back(b);
-            item_start.push_back(k);
-            item_count.push_back((int32_t)std::min(kChunk, hi - k));
-        }
+        const double fm = ev->f_low + 0.5 * (double)(desc->edges[b] + desc->edges[b + 1]) * ev->delta_f;
+        for (int64_t k = lo; k < hi; k += kChunk) items.push_back(SumItem{k, (int32_t)std::min(kChunk, hi - k), b, fm});
     }
-    bin_first[(size_t)nb] = (int64_t)item_bin.size();
-    const int64_t n_items = (int64_t)item_bin.size();
-    int32_t* d_item_bin = nullptr;
-    int64_t *d_item_start = nullptr, *d_bin_first = nullptr, *d_edges = nullptr;
-    int32_t* d_item_count = nullptr;
+    bin_first[(size_t)nb] = (int64_t)items.size();
+    const int64_t n_items = (int64_t)items.size();
+    SumItem* d_items = nullptr;
+    int64_t *d_bin_first = nullptr, *d_edges = nullptr;
     double* d_partials = nullptr;
-    if (tmp.alloc((void**)&d_item_bin, sizeof(int32_t) * n_items) != hipSuccess ||
-        tmp.alloc((void**)&d_item_start, sizeof(int64_t) * n_items) != hipSuccess ||
-        tmp.alloc((void**)&d_item_count, sizeof(int32_t) * n_items) != hipSuccess ||
+    if (tmp.alloc((void**)&d_items, sizeof(SumItem) * n_items) != hipSuccess ||
         tmp.alloc((void**)&d_bin_first, sizeof(int64_t) * (nb + 1)) != hipSuccess ||
         tmp.alloc((void**)&d_edges, sizeof(int64_t) * (nb + 1)) != hipSuccess ||
         tmp.alloc((void**)&d_partials, sizeof(double) * n_items * nd * 7) != hipSuccess)
         return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (work items)"));
-    if ((e = hipMemcpyAsync(d_item_bin, item_bin.data(), sizeof(int32_t) * n_items, hipMemcpyHostToDevice, s)) ||
-        (e = hipMemcpyAsync(d_item_start, item_start.data(), sizeof(int64_t) * n_items, hipMemcpyHostToDevice, s)) ||
-        (e = hipMemcpyAsync(d_item_count, item_count.data(), sizeof(int32_t) * n_items, hipMemcpyHostToDevice, s)) ||
+    if ((e = hipMemcpyAsync(d_items, items.data(), sizeof(SumItem) * n_items, hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(d_bin_first, bin_first.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(d_edges, desc->edges, sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, s)))
         return cleanup(hip_fail(e, "rbl_event_create: copy work items"));
@@ -302,10 +293,7 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
 
     SummaryArgs sa{};
     sa.n_items = n_items;
-    sa.item_bin = d_item_bin;
-    sa.item_start = d_item_start;
-    sa.item_count = d_item_count;
-    sa.edges = d_edges;
+    sa.items = d_items;
     sa.f_low = ev->f_low;
     sa.delta_f = ev->delta_f;
     sa.n_freq = n;

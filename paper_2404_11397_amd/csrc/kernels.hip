@@ -258,74 +258,100 @@ __global__ __launch_bounds__(256) void k_chain_setup_grad(const double* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Summary data: one wavefront per item (a run of <= chunk grid points inside
-// one bin); the reference waveform is generated inline, once per point, and
-// projected onto every detector.  Partials: [item][det][7].
+// Summary data: one wavefront per item (a run of <= 128 grid points inside one bin, two
+// points per lane); the reference waveform is generated inline, once per point, and
+// projected onto every detector.  The loads of both points are issued before the
+// arithmetic.  Each lane's 7 ND partial sums are reduced across the wavefront through
+// LDS (lane t < 7 ND sums row t over the 64 lanes in lane order).  Partials: [item][det][7].
 // ---------------------------------------------------------------------------
 template <int ND>
+__device__ inline void summary_point(const SummaryArgs& a, int64_t k, double fm, const double* dre, const double* dim,
+                                     const double* ps, double (&acc)[ND][7]) {
+    const RefConsts& ref = a.ref;
+    const double w = 4.0 * a.delta_f;
+    const double f = a.f_low + (double)k * a.delta_f;
+    const double x = cbrt(f);
+    const double ix = 1.0 / x;
+    const double lx = log(x);
+    double phi = 0.0;
+    double amp = ref.amp0 * (ix * ix * ix) * sqrt(ix);  // f^(-7/6)
+    if (ref.waveform == kWfNrtv2) {
+        double a0;
+        nrt_node(ref.nrt, f, x, ix, lx, exp(5.78 * lx), a.ref_taper != 0, phi, a0);
+        amp *= a0;
+    } else {
+        double bas[kTf2Basis];
+        tf2_basis(x, ix, lx, bas);
+#pragma unroll
+        for (int j = 0; j < kTf2Basis; ++j) phi = fma(ref.c0[j], bas[j], phi);
+    }
+    const double df = f - fm;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        double cu, su;
+        expm2pi_rev(fma(f, ref.tau0[d], phi), cu, su);
+        const double hre = amp * (ref.h0fac_re[d] * cu - ref.h0fac_im[d] * su);
+        const double him = amp * (ref.h0fac_re[d] * su + ref.h0fac_im[d] * cu);
+        const double wk = w / ps[d];
+        // d conj(h0) w and |h0|^2 w
+        const double are = (dre[d] * hre + dim[d] * him) * wk;
+        const double aim = (dim[d] * hre - dre[d] * him) * wk;
+        const double hh = (hre * hre + him * him) * wk;
+        acc[d][0] += are;
+        acc[d][1] += aim;
+        acc[d][2] += are * df;
+        acc[d][3] += aim * df;
+        acc[d][4] += hh;
+        acc[d][5] += hh * df;
+        acc[d][6] += hh * df * df;
+    }
+}
+
+template <int ND>
 __global__ __launch_bounds__(256) void k_summary_items(SummaryArgs a) {
+    __shared__ double red[4][7 * ND][65];  // padded rows: no bank conflicts between lanes
     const int lane = threadIdx.x & 63;
-    const int64_t item = (int64_t)blockIdx.x * 4 + wave_id();
+    const int wid = wave_id();
+    const int64_t item = (int64_t)blockIdx.x * 4 + wid;
     if (item >= a.n_items) return;
-    const int32_t bin = a.item_bin[item];
-    const int64_t k0 = a.item_start[item];
-    const int32_t cnt = a.item_count[item];
-    const double fm = a.f_low + 0.5 * (double)(a.edges[bin] + a.edges[bin + 1]) * a.delta_f;
+    const SumItem it = a.items[item];
+    const int64_t k0 = it.start;
+    const int32_t cnt = it.count;
+    const double fm = it.fm;
     double acc[ND][7];
 #pragma unroll
     for (int d = 0; d < ND; ++d)
 #pragma unroll
         for (int j = 0; j < 7; ++j) acc[d][j] = 0.0;
-    const RefConsts& ref = a.ref;
-    const double w = 4.0 * a.delta_f;
-    for (int i = lane; i < cnt; i += 64) {
-        const int64_t k = k0 + i;
-        const double f = a.f_low + (double)k * a.delta_f;
-        const double x = cbrt(f);
-        const double ix = 1.0 / x;
-        const double lx = log(x);
-        double phi = 0.0;
-        double amp = ref.amp0 * (ix * ix * ix) * sqrt(ix);  // f^(-7/6)
-        if (ref.waveform == kWfNrtv2) {
-            double a0;
-            nrt_node(ref.nrt, f, x, ix, lx, exp(5.78 * lx), a.ref_taper != 0, phi, a0);
-            amp *= a0;
-        } else {
-            double bas[kTf2Basis];
-            tf2_basis(x, ix, lx, bas);
-#pragma unroll
-            for (int j = 0; j < kTf2Basis; ++j) phi = fma(ref.c0[j], bas[j], phi);
-        }
-        const double df = f - fm;
+    for (int i0 = 0; i0 < cnt; i0 += 128) {
+        const bool v0 = i0 + lane < cnt, v1 = i0 + 64 + lane < cnt;
+        const int64_t ka = k0 + i0 + lane, kb = ka + 64;
+        double ra[ND], ia[ND], pa[ND], rb[ND], ib[ND], pb[ND];
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
-            double cu, su;
-            expm2pi_rev(fma(f, ref.tau0[d], phi), cu, su);
-            const double hre = amp * (ref.h0fac_re[d] * cu - ref.h0fac_im[d] * su);
-            const double him = amp * (ref.h0fac_re[d] * su + ref.h0fac_im[d] * cu);
-            const int64_t o = (int64_t)d * a.n_freq + k;
-            const double dre = a.data[2 * o], dim = a.data[2 * o + 1];
-            const double wk = w / a.psd[o];
-            // d conj(h0) w and |h0|^2 w
-            const double are = (dre * hre + dim * him) * wk;
-            const double aim = (dim * hre - dre * him) * wk;
-            const double hh = (hre * hre + him * him) * wk;
-            acc[d][0] += are;
-            acc[d][1] += aim;
-            acc[d][2] += are * df;
-            acc[d][3] += aim * df;
-            acc[d][4] += hh;
-            acc[d][5] += hh * df;
-            acc[d][6] += hh * df * df;
+            const int64_t oa = (int64_t)d * a.n_freq + ka, ob = oa + 64;
+            ra[d] = v0 ? a.data[2 * oa] : 0.0;
+            ia[d] = v0 ? a.data[2 * oa + 1] : 0.0;
+            pa[d] = v0 ? a.psd[oa] : 1.0;
+            rb[d] = v1 ? a.data[2 * ob] : 0.0;
+            ib[d] = v1 ? a.data[2 * ob + 1] : 0.0;
+            pb[d] = v1 ? a.psd[ob] : 1.0;
         }
+        if (v0) summary_point<ND>(a, ka, fm, ra, ia, pa, acc);
+        if (v1) summary_point<ND>(a, kb, fm, rb, ib, pb, acc);
     }
 #pragma unroll
     for (int d = 0; d < ND; ++d)
 #pragma unroll
-        for (int j = 0; j < 7; ++j) {
-            const double s = wave_sum(acc[d][j]);
-            if (lane == 0) a.partials[(item * ND + d) * 7 + j] = s;
-        }
+        for (int j = 0; j < 7; ++j) red[wid][d * 7 + j][lane] = acc[d][j];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < 7 * ND) {
+        double s = 0.0;
+        for (int l = 0; l < 64; ++l) s += red[wid][lane][l];
+        a.partials[item * (7 * ND) + lane] = s;
+    }
 }
 
 __global__ void k_summary_reduce(const double* __restrict__ partials, const int64_t* __restrict__ bin_first_item,

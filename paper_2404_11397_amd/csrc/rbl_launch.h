@@ -9,12 +9,17 @@ struct Theta13 {
     double v[13];
 };
 
+// One work item of the summary pass: a run of grid points inside one bin, with the bin
+// centre precomputed (one load gives a wavefront everything it needs before its data).
+struct SumItem {
+    int64_t start;
+    int32_t count, bin;
+    double fm;
+};
+
 struct SummaryArgs {
     int64_t n_items;
-    const int32_t* item_bin;
-    const int64_t* item_start;
-    const int32_t* item_count;
-    const int64_t* edges;
+    const SumItem* items;
     double f_low, delta_f;
     int64_t n_freq;
     int32_t n_det, n_bins;

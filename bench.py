@@ -295,6 +295,7 @@ def run_stream(srv, ids, pools, n, rate, precision):
     offs, evs, pidx = synth.serving_stream(n, rate)
     q = queue.Queue()
     lat = np.empty(n)
+    wait_adm = np.empty(n)
     done = np.empty(n, dtype=np.int64)
     chains = np.array([pools[e][k].shape[0] for e, k in zip(evs, pidx)])
 
@@ -302,6 +303,7 @@ def run_stream(srv, ids, pools, n, rate, precision):
         for i in range(n):
             _, _, info = srv.wait(q.get())
             lat[i] = (info["t_done_ns"] - info["t_arrival_ns"]) * 1e-6
+            wait_adm[i] = (info["t_admit_ns"] - info["t_arrival_ns"]) * 1e-6
             done[i] = info["t_done_ns"]
 
     th = threading.Thread(target=waiter)
@@ -320,7 +322,8 @@ def run_stream(srv, ids, pools, n, rate, precision):
     span = (done.max() - t0) * 1e-9
     return {"rate_hz": rate, "requests": n, "precision": precision,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "mean_ms": float(lat.mean()), "evals_per_s": float(chains.sum() / span),
+            "mean_ms": float(lat.mean()), "admit_wait_p50_ms": float(np.percentile(wait_adm, 50)),
+            "service_p50_ms": float(np.percentile(lat - wait_adm, 50)), "evals_per_s": float(chains.sum() / span),
             "offered_evals_per_s": float(chains.sum() / (offs[-1] + 1e-9))}
 
 
@@ -338,8 +341,9 @@ def serving(torch, n_requests):
                        "lnL+grad requests",
            "events_build_s": t_build, "hbm_budget_bytes": budget,
            "nrtv2_events_with_halved_lambda": adjusted}
-    for tag, streams, graphs, prec in (("server", 4, True, "mixed"), ("baseline_fifo_fp64_plain", 1, False, "fp64")):
-        with Server(budget, n_streams=streams, graphs=graphs) as srv:
+    for tag, streams, graphs, spin, prec in (("server", 4, True, True, "mixed"),
+                                             ("baseline_fifo_fp64_plain", 1, False, False, "fp64")):
+        with Server(budget, n_streams=streams, graphs=graphs, spin=spin) as srv:
             ids = [srv.add_event(e) for e in events]
             warm = [srv.submit(ids[e], pools[e][k], precision=prec) for e in range(len(events))
                     for k in range(len(pools[e]))]
@@ -348,7 +352,7 @@ def serving(torch, n_requests):
             r = run_stream(srv, ids, pools, n_requests, synth.SERVE_RATE_HZ, prec)
             r["saturation"] = [run_stream(srv, ids, pools, n_requests, rate, prec) for rate in (2000.0, 20000.0)]
             r["stats"] = srv.stats()
-            r["streams"], r["graphs"] = streams, graphs
+            r["streams"], r["graphs"], r["spin"] = streams, graphs, spin
             res[tag] = r
     res["resident_bytes"] = res["server"]["stats"]["resident_bytes"]
     return res

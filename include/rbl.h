@@ -174,7 +174,9 @@ const char *rbl_last_error(void);
  * Times are host CLOCK_MONOTONIC nanoseconds (rbl_clock_ns). */
 typedef struct rbl_server rbl_server;
 
-#define RBL_SERVE_NO_GRAPHS 0x1u
+#define RBL_SERVE_NO_GRAPHS 0x1u  /* plain launches instead of graph replays */
+#define RBL_SERVE_SPIN      0x2u  /* the worker polls for new requests instead of sleeping
+                                     while idle: lowest admission latency, one busy host core */
 
 typedef struct {
     int64_t t_arrival_ns;  /* as given to rbl_server_submit (or the submit time) */

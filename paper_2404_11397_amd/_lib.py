@@ -22,7 +22,7 @@ EXPORTS = ("rbl_event_create", "rbl_event_free", "rbl_workspace_bytes", "rbl_log
            "rbl_last_error", "rbl_server_create", "rbl_server_add_event", "rbl_server_remove_event",
            "rbl_server_submit", "rbl_server_wait", "rbl_server_get_stats", "rbl_server_destroy", "rbl_clock_ns",
            "rbl_event_footprint_bytes")
-RBL_SERVE_NO_GRAPHS = 0x1
+RBL_SERVE_NO_GRAPHS, RBL_SERVE_SPIN = 0x1, 0x2
 
 
 class RblError(RuntimeError):

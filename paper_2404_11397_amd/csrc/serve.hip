@@ -349,6 +349,12 @@ void worker_main(rbl_server* S) {
             continue;
         }
         if (S->stop) break;
+        if (S->flags & RBL_SERVE_SPIN) {
+            lk.unlock();
+            std::this_thread::yield();
+            lk.lock();
+            continue;
+        }
         S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
     }
 }

@@ -30,9 +30,9 @@ class Ticket:
 
 
 class Server:
-    def __init__(self, hbm_budget_bytes, n_streams=4, graphs=True):
+    def __init__(self, hbm_budget_bytes, n_streams=4, graphs=True, spin=False):
         h = ctypes.c_void_p()
-        flags = 0 if graphs else _lib.RBL_SERVE_NO_GRAPHS
+        flags = (0 if graphs else _lib.RBL_SERVE_NO_GRAPHS) | (_lib.RBL_SERVE_SPIN if spin else 0)
         check(_lib.lib().rbl_server_create(int(hbm_budget_bytes), int(n_streams), flags, ctypes.byref(h)))
         self._h = h
         self._events = {}

@@ -32,14 +32,14 @@ def _alone(gev, th, precision, grad):
     return gev.loglike(t, precision).cpu().numpy(), None
 
 
-@pytest.mark.parametrize("graphs", [True, False])
-def test_alone_equals_mix(events, graphs):
+@pytest.mark.parametrize("graphs,spin", [(True, False), (False, False), (True, True)])
+def test_alone_equals_mix(events, graphs, spin):
     from paper_2404_11397_amd import Server
     rng = np.random.default_rng(11)
     plan = [(int(rng.integers(len(events))), prec, grad)
             for prec in ("fp64", "mixed") for grad in (True, False) for _ in range(6)]
     rng.shuffle(plan)
-    with Server(4 << 30, n_streams=4, graphs=graphs) as srv:
+    with Server(4 << 30, n_streams=4, graphs=graphs, spin=spin) as srv:
         ids = [srv.add_event(gev) for gev, _ in events]
         tickets = [(srv.submit(ids[e], events[e][1], precision=p, grad=g), e, p, g) for e, p, g in plan]
         for t, e, p, g in tickets:

@@ -152,6 +152,13 @@ int rbl_profile_read_summary(double *ms, int64_t *events);
 
 const char *rbl_last_error(void);
 
+/* Failure injection for tests of the error paths: from the count-th next device allocation
+ * (RBL_FAULT_ALLOC) or likelihood launch (RBL_FAULT_LAUNCH) made by the library on, each one
+ * fails as if the device had refused it (the call returns RBL_ENOMEM, resp. RBL_EDEVICE, and
+ * leaves the library usable) until the hook is cleared with count = 0.  Process-wide. */
+enum { RBL_FAULT_ALLOC = 0, RBL_FAULT_LAUNCH = 1 };
+int rbl_debug_inject_fault(int32_t kind, int32_t count);
+
 /* ---------------------------------------------------------------------------------------
  * Serving: continuous batching of likelihood requests over many resident events (the
  * sampler of Sec. II D evaluates thousands of chains per step; a service answers such

@@ -1,6 +1,7 @@
 // Host side of the C-ABI: validation, resident event state, kernel launches.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -25,7 +26,23 @@ int hip_fail(hipError_t e, const char* what) {
     return RBL_EDEVICE;
 }
 
+std::atomic<int> g_fault[2];
+
+bool fault_take(int kind) {
+    int c = g_fault[kind].load();
+    while (c > 1)
+        if (g_fault[kind].compare_exchange_weak(c, c - 1)) return false;
+    return c == 1;  // armed: fails until cleared
+}
+
 }  // namespace rbl
+
+extern "C" int rbl_debug_inject_fault(int32_t kind, int32_t count) {
+    if (kind != RBL_FAULT_ALLOC && kind != RBL_FAULT_LAUNCH) return fail(RBL_EINVAL, "rbl_debug_inject_fault: unknown kind");
+    if (count < 0) return fail(RBL_EINVAL, "rbl_debug_inject_fault: count < 0");
+    g_fault[kind].store(count);
+    return RBL_OK;
+}
 
 namespace {
 
@@ -425,6 +442,7 @@ static int check_call(const char* who, const rbl_event* ev, const double* theta,
     if (((uintptr_t)ws) % kAlign) return fail(RBL_EINVAL, std::string(who) + ": workspace not 256-byte aligned");
     if (precision != RBL_FP64 && precision != RBL_MIXED) return fail(RBL_EINVAL, std::string(who) + ": unknown precision");
     if (B > (int64_t)1 << 31) return fail(RBL_EINVAL, std::string(who) + ": B too large");
+    if (fault_take(RBL_FAULT_LAUNCH)) return hip_fail(hipErrorLaunchFailure, (std::string(who) + ": injected").c_str());
     return RBL_OK;
 }
 

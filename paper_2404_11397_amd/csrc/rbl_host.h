@@ -14,6 +14,9 @@ namespace rbl {
 int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
 
+// Failure injection (rbl_debug_inject_fault): true when this allocation / launch must fail.
+bool fault_take(int kind);
+
 constexpr int64_t kAlign = 256;
 inline int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -21,6 +24,7 @@ inline int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; 
 struct DevList {
     std::vector<void*> ptrs;
     hipError_t alloc(void** p, size_t bytes) {
+        if (fault_take(RBL_FAULT_ALLOC)) return hipErrorOutOfMemory;
         hipError_t e = hipMalloc(p, bytes ? bytes : 1);
         if (e == hipSuccess) ptrs.push_back(*p);
         return e;

@@ -153,6 +153,7 @@ Buffer* allocate_buffer(rbl_server* S, int64_t cap) {
     b->id = S->next_buf++;
     b->cap = cap;
     b->bytes = BufLayout(cap).total;
+    if (fault_take(RBL_FAULT_ALLOC)) return nullptr;
     if (hipMalloc((void**)&b->dev, (size_t)b->bytes) != hipSuccess ||
         hipHostMalloc((void**)&b->h_theta, (size_t)(cap * 13 * sizeof(double)), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&b->h_out, (size_t)(cap * 14 * sizeof(double)), hipHostMallocDefault) != hipSuccess) {

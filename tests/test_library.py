@@ -115,3 +115,35 @@ def test_server_argument_errors_without_gpu():
     a, b = L.rbl_clock_ns(), L.rbl_clock_ns()
     assert 0 < a <= b
     assert L.rbl_event_footprint_bytes(None) == 0
+
+
+def test_fault_injection_on_cpu():
+    """An injected allocation failure surfaces as RBL_ENOMEM before any device work."""
+    from paper_2404_11397_amd import _lib
+    L = _lib.lib()
+    assert L.rbl_debug_inject_fault(7, 1) == -1
+    assert L.rbl_debug_inject_fault(_lib.RBL_FAULT_ALLOC, -1) == -1
+    import synth
+    f_low, df, n, f = synth.frequency_grid(20.0, 60.0, 4.0)
+    psd = synth.analytic_psd(f)[None, :]
+    data = np.zeros((1, n), complex)
+    geo = synth.detector_geometry(0.1, 0.2, 0.3)
+    th0 = np.ascontiguousarray([1.2, 0.8, 0.0, 0.0, 100.0, 100.0, 50.0, 0.0, 0.1, 0.2, 0.3, 0.4, 0.5])
+    edges = np.array([0, n // 2, n - 1])
+    d = np.ascontiguousarray(data)
+    p = np.ascontiguousarray(psd)
+    tens = np.ascontiguousarray(geo[0].reshape(1, 9))
+    vert = np.ascontiguousarray(geo[1].reshape(1, 3))
+    e = np.ascontiguousarray(edges, dtype=np.int64)
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    desc = _lib.EventDesc(n_det=1, waveform=0, n_bins=2, flags=0, n_freq=n, f_low=f_low, delta_f=df, gmst=0.0,
+                          data=vp(d), psd=vp(p), det_tensor=vp(tens), det_vertex=vp(vert), theta_ref=vp(th0),
+                          edges=vp(e))
+    h = ctypes.c_void_p()
+    assert L.rbl_debug_inject_fault(_lib.RBL_FAULT_ALLOC, 1) == 0
+    try:
+        assert L.rbl_event_create(ctypes.byref(desc), None, ctypes.byref(h)) == -4
+        assert not h.value
+        assert b"allocation" in L.rbl_last_error()
+    finally:
+        L.rbl_debug_inject_fault(_lib.RBL_FAULT_ALLOC, 0)

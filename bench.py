@@ -358,6 +358,39 @@ def serving(torch, n_requests):
     return res
 
 
+def mala_rate(torch, ev, w, steps):
+    """Device MALA local steps (proposal, lnL+grad, accept) on the headline batch: chain-steps/s."""
+    from paper_2404_11397_amd import Mala
+    th = w["theta"].copy()
+    z = th.copy()
+    z[:, 9] = np.cos(th[:, 9])
+    z[:, 12] = np.sin(th[:, 12])
+    B = len(z)
+    ch = Mala(ev, torch.as_tensor(z, device="cuda:0"))
+    b = synth.PRIORS["gw170817"]
+    lo = np.array([b["Mc"][0], b["q"][0], b["chi"][0], b["chi"][0], b["L"][0], b["L"][0], b["dL"][0], b["tc"][0],
+                   0.0, -1.0, 0.0, 0.0, -1.0])
+    hi = np.array([b["Mc"][1], b["q"][1], b["chi"][1], b["chi"][1], b["L"][1], b["L"][1], b["dL"][1], b["tc"][1],
+                   2 * np.pi, 1.0, np.pi, 2 * np.pi, 1.0])
+    step = (0.01 * (hi - lo)) ** 2
+    gen = torch.Generator(device="cuda:0").manual_seed(7)
+    xi = torch.randn((steps + 3, B, 13), dtype=torch.float64, device="cuda:0", generator=gen)
+    logu = torch.log(torch.rand((steps + 3, B), dtype=torch.float64, device="cuda:0", generator=gen))
+    acc = torch.zeros(B, dtype=torch.int64, device="cuda:0")
+    for k in range(3):
+        ch.step(step, lo, hi, xi[k], logu[k])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        acc += ch.step(step, lo, hi, xi[k + 3], logu[k + 3])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"chain_steps_per_s": B * steps / dt, "us_per_step": dt / steps * 1e6, "chains": B, "steps": steps,
+            "acceptance": float(acc.sum()) / (B * steps), "precision": "fp64",
+            "what": "rbl_mala_step on the headline event: proposal, setup + lnL+grad kernels, accept (prior box of "
+                    "the GW170817 column, step 1% of each prior width)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -428,6 +461,7 @@ def main():
         "summary_pass": {"us": summ_us, "bytes": summ_bytes, "GB_per_s": summ_bytes / (summ_us * 1e-6) / 1e9,
                          "frac_of_hbm_peak": summ_bytes / (summ_us * 1e-6) / 1e9 / PEAK_HBM_GBS},
     }
+    out["mala"] = mala_rate(torch, ev, w, max(20, args.steps // 4))
     tr = stored_traffic("k_loglike_grad_tf2_3det_128s_8192_fp64")
     if tr is not None:
         out["roofline"]["traffic"] = tr["hbm_bytes_per_launch"]

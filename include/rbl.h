@@ -160,6 +160,31 @@ enum { RBL_FAULT_ALLOC = 0, RBL_FAULT_LAUNCH = 1 };
 int rbl_debug_inject_fault(int32_t kind, int32_t count);
 
 /* ---------------------------------------------------------------------------------------
+ * MALA local step (the gradient-based local sampler of Sec. II D) on the device.
+ *
+ * A chain's state is z [13] = (Mc, q, chi1, chi2, Lambda1, Lambda2, dL, tc, phic, cos iota,
+ * psi, ra, sin delta) -- the coordinates in which Tab. II's priors are uniform -- with its
+ * lnL and gz = d lnL / dz.  All arrays are device float64, row-major [B][13] / [B]. */
+
+/* Bytes of device workspace (256-byte aligned) that rbl_mala_init / rbl_mala_step need. */
+int64_t rbl_mala_workspace_bytes(const rbl_event *ev, int64_t B);
+
+/* lnL and gz at z for B chains (the state before the first step). */
+int rbl_mala_init(const rbl_event *ev, const double *z_dev, int64_t B, int32_t precision, double *lnl_dev,
+                  double *gz_dev, void *workspace, void *hip_stream);
+
+/* One step for B chains, in place on z, lnl, gz: propose z' = z + (s/2) gz + sqrt(s) xi,
+ * evaluate lnL and its gradient at z', accept when z' lies in the prior box [lo, hi] and
+ * log u < lnL' - lnL + log q(z|z') - log q(z'|z), log q(b|a) = -sum (b - a - s g(a)/2)^2 / (2 s).
+ * step (s, > 0), lo, hi: host [13]; xi_dev [B][13] standard normals and logu_dev [B] (log of
+ * uniforms on (0, 1)) are the caller's random numbers; accepted_dev [B] int32 receives 1 / 0.
+ * Asynchronous on hip_stream. */
+int rbl_mala_step(const rbl_event *ev, double *z_dev, double *lnl_dev, double *gz_dev, int64_t B,
+                  int32_t precision, const double *step, const double *lo, const double *hi,
+                  const double *xi_dev, const double *logu_dev, int32_t *accepted_dev, void *workspace,
+                  void *hip_stream);
+
+/* ---------------------------------------------------------------------------------------
  * Serving: continuous batching of likelihood requests over many resident events (the
  * sampler of Sec. II D evaluates thousands of chains per step; a service answers such
  * batches for many events at once).

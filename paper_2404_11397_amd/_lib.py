@@ -21,7 +21,8 @@ EXPORTS = ("rbl_event_create", "rbl_event_free", "rbl_workspace_bytes", "rbl_log
            "rbl_event_info", "rbl_bin_edges", "rbl_profile_enable", "rbl_profile_read", "rbl_profile_read_summary",
            "rbl_last_error", "rbl_server_create", "rbl_server_add_event", "rbl_server_remove_event",
            "rbl_server_submit", "rbl_server_wait", "rbl_server_get_stats", "rbl_server_destroy", "rbl_clock_ns",
-           "rbl_event_footprint_bytes", "rbl_debug_inject_fault")
+           "rbl_event_footprint_bytes", "rbl_debug_inject_fault", "rbl_mala_workspace_bytes", "rbl_mala_init",
+           "rbl_mala_step")
 RBL_FAULT_ALLOC, RBL_FAULT_LAUNCH = 0, 1
 RBL_SERVE_NO_GRAPHS, RBL_SERVE_SPIN = 0x1, 0x2
 
@@ -113,6 +114,12 @@ def lib():
     L.rbl_event_footprint_bytes.restype = i64
     L.rbl_debug_inject_fault.argtypes = [i32, i32]
     L.rbl_debug_inject_fault.restype = ctypes.c_int
+    L.rbl_mala_workspace_bytes.argtypes = [vp, i64]
+    L.rbl_mala_workspace_bytes.restype = i64
+    L.rbl_mala_init.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp]
+    L.rbl_mala_init.restype = ctypes.c_int
+    L.rbl_mala_step.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.rbl_mala_step.restype = ctypes.c_int
     _lib = L
     return L
 

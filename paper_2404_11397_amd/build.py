@@ -6,7 +6,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librbl.so")
-SOURCES = ["kernels.hip", "likelihood.hip", "api.hip", "serve.hip"]
+SOURCES = ["kernels.hip", "likelihood.hip", "api.hip", "serve.hip", "mala.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -303,8 +303,10 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     double* node_block = nullptr;
     // FP64 tables, scales, FP32 tables (2 nd np floats), reference phase / amplitude (2 np), FP32 amplitude
     // tables: 4 edge columns and 5 per-detector columns (FP64), the scales, 5 per-detector
-    // FP32 columns, phi0 and 1/a0 (FP64), 1/a0 (FP32), x^5.78 (FP64); np is a multiple of 64
-    const int64_t node_doubles = np * (4 + 5 * nd) + 2 * kMaxDet + np * 5 * nd / 2 + 2 * np + np / 2 + np;
+    // FP32 columns, phi0 and 1/a0 (FP64), 1/a0 (FP32), x^5.78 (FP64), the phasor table; np is a
+    // multiple of 64
+    const int64_t node_doubles =
+        np * (4 + 5 * nd) + 2 * kMaxDet + np * 5 * nd / 2 + 2 * np + np / 2 + np + 2 * kPhasorN;
     if (ev->mem.alloc((void**)&node_block, sizeof(double) * node_doubles) != hipSuccess)
         return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (node tables)"));
 
@@ -356,18 +358,29 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     na.g_re = node_block + 4 * np;
     na.g_im = na.g_re + nd * np;
     na.mu = na.g_im + nd * np;
-    na.nuL = na.mu + nd * np;
-    na.nuR = na.nuL + nd * np;
-    na.scales = na.nuR + nd * np;
+    na.xL = na.mu + nd * np;
+    na.xR = na.xL + nd * np;
+    na.scales = na.xR + nd * np;
     na.g_re32 = (float*)(na.scales + 2 * kMaxDet);
     na.g_im32 = na.g_re32 + nd * np;
     na.mu32 = na.g_im32 + nd * np;
-    na.nuL32 = na.mu32 + nd * np;
-    na.nuR32 = na.nuL32 + nd * np;
+    na.xL32 = na.mu32 + nd * np;
+    na.xR32 = na.xL32 + nd * np;
     na.phi0 = na.scales + 2 * kMaxDet + np * 5 * nd / 2;  // after the FP32 tables (5 nd np floats)
     na.ia0 = na.phi0 + np;
     na.ia0_32 = (float*)(na.ia0 + np);
     na.node_x578 = na.ia0 + np + np / 2;
+    double* d_phasor = na.node_x578 + np;
+    // cos and sin of 2 pi k / kPhasorN, evaluated in extended precision and rounded once
+    std::vector<double> phasor(2 * kPhasorN);
+    for (int k = 0; k < kPhasorN; ++k) {
+        const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)kPhasorN;
+        phasor[2 * k] = (double)std::cos(a);
+        phasor[2 * k + 1] = (double)std::sin(a);
+    }
+    if ((e = hipMemcpyAsync(d_phasor, phasor.data(), sizeof(double) * 2 * kPhasorN, hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
+        return cleanup(hip_fail(e, "rbl_event_create: copy phasor table"));
     na.ref = ev->ref;
     na.ref_taper = (desc->flags & RBL_REF_TAPER) ? 1 : 0;
     int32_t* d_bad = nullptr;
@@ -400,19 +413,20 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     dv.g_re = na.g_re;
     dv.g_im = na.g_im;
     dv.mu = na.mu;
-    dv.nuL = na.nuL;
-    dv.nuR = na.nuR;
+    dv.xL = na.xL;
+    dv.xR = na.xR;
     dv.g_re32 = na.g_re32;
     dv.g_im32 = na.g_im32;
     dv.mu32 = na.mu32;
-    dv.nuL32 = na.nuL32;
-    dv.nuR32 = na.nuR32;
+    dv.xL32 = na.xL32;
+    dv.xR32 = na.xR32;
     dv.scales = na.scales;
     dv.waveform = desc->waveform;
     dv.phi0 = na.phi0;
     dv.ia0 = na.ia0;
     dv.ia0_32 = na.ia0_32;
     dv.node_x578 = na.node_x578;
+    dv.phasor = d_phasor;
     ev->footprint = (int64_t)sizeof(double) * (nd * nb * 7 + node_doubles) +
                     ((desc->flags & RBL_KEEP_GRID) ? (int64_t)sizeof(double) * 3 * nd * n : 0);
     *out = ev;

@@ -374,7 +374,8 @@ __global__ void k_summary_reduce(const double* __restrict__ partials, const int6
 //   + |q|^2 (B0/4 + B1 w + B2 w^2) + Re(p q*) (B0/2 - 2 B2 w^2) ] / 2
 // with alpha = A0/2 - A1 w, beta = A0/2 + A1 w.  Collecting by edge:
 //   gamma_j = alpha_j + beta_{j-1},  mu_j = (left part of bin j) + (right part of bin j-1),
-//   nu_b = B0/2 - 2 B2 w^2 multiplies Re(r_b r_{b+1}*).
+//   nu_b = B0/2 - 2 B2 w^2 multiplies Re(r_b r_{b+1}*).  The tables hold the cross
+// weights of 2 lnL, xL_j = -nu_{j-1} and xR_j = -nu_j.
 // ---------------------------------------------------------------------------
 __global__ void k_node_tables(NodeArgs a) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;  // edge index
@@ -406,7 +407,7 @@ __global__ void k_node_tables(NodeArgs a) {
         a.ia0_32[pos] = ok ? (float)(1.0 / a0) : 0.0f;
     }
     for (int d = 0; d < a.n_det; ++d) {
-        double gre = 0.0, gim = 0.0, mu = 0.0, nul = 0.0, nur = 0.0;
+        double gre = 0.0, gim = 0.0, mu = 0.0, xl = 0.0, xr = 0.0;
         if (real_node) {
             if (j < nb) {  // bin j lies to the right of edge j
                 const double* s = a.summary + ((int64_t)d * nb + j) * 7;
@@ -415,7 +416,7 @@ __global__ void k_node_tables(NodeArgs a) {
                 gre += 0.5 * s[0] - s[2] * w;
                 gim += 0.5 * s[1] - s[3] * w;
                 mu += 0.25 * s[4] - s[5] * w + b2 * w * w;
-                nur = 0.5 * s[4] - 2.0 * b2 * w * w;
+                xr = 2.0 * b2 * w * w - 0.5 * s[4];
             }
             if (j > 0) {  // bin j-1 lies to the left
                 const double* s = a.summary + ((int64_t)d * nb + (j - 1)) * 7;
@@ -424,20 +425,20 @@ __global__ void k_node_tables(NodeArgs a) {
                 gre += 0.5 * s[0] + s[2] * w;
                 gim += 0.5 * s[1] + s[3] * w;
                 mu += 0.25 * s[4] + s[5] * w + b2 * w * w;
-                nul = 0.5 * s[4] - 2.0 * b2 * w * w;
+                xl = 2.0 * b2 * w * w - 0.5 * s[4];
             }
         }
         const int64_t o = (int64_t)d * a.n_nodes_pad + pos;
         a.g_re[o] = gre;
         a.g_im[o] = gim;
         a.mu[o] = mu;
-        a.nuL[o] = nul;
-        a.nuR[o] = nur;
+        a.xL[o] = xl;
+        a.xR[o] = xr;
         a.g_re32[o] = (float)gre;
         a.g_im32[o] = (float)gim;
         a.mu32[o] = (float)mu;
-        a.nuL32[o] = (float)nul;
-        a.nuR32[o] = (float)nur;
+        a.xL32[o] = (float)xl;
+        a.xR32[o] = (float)xr;
     }
 }
 
@@ -450,7 +451,7 @@ __global__ __launch_bounds__(64) void k_event_scales(NodeArgs a) {
     for (int j = lane; j < a.n_nodes_pad; j += 64) {
         const int64_t o = (int64_t)d * a.n_nodes_pad + j;
         gs += sqrt(a.g_re[o] * a.g_re[o] + a.g_im[o] * a.g_im[o]);
-        hs += fabs(a.mu[o]) + fabs(a.nuL[o]);
+        hs += fabs(a.mu[o]) + fabs(a.xL[o]);
     }
     gs = wave_sum(gs);
     hs = wave_sum(hs);

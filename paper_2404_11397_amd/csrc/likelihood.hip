@@ -5,8 +5,11 @@
 // (k = 0..L-1) in the lane-contiguous table layout.  At each edge the ratio of
 // Eq. (4) is r_d = K_d exp(-2 pi i phi_d), phi_d = sum_b dc_b B_b(x_j) + f_j dtau_d
 // (revolutions), and the binned sum of Eq. (5) is regrouped per edge:
-//   lnL = sum_d sum_j [ Re(gamma_dj r_dj*) - mu_dj |r_dj|^2 / 2 + c_dj Re(r_d,j-1 r_dj*) ],
-//   c_dj = -nuL_dj / 2  (the cross term of the bin left of edge j).
+//   2 lnL = sum_d sum_j [ 2 Re(gamma_dj r_dj*) - mu_dj |r_dj|^2 + xL_dj Re(r_d,j-1 r_dj*) ],
+// xL_dj being the cross weight of the bin left of edge j.
+//
+// FP64 unit phasors come from a kPhasorN-entry table in LDS and a short Taylor
+// rotation (unit_phasor below).
 //
 // Mixed precision: the phase is accumulated in FP64 and reduced to (-1/2, 1/2]
 // revolutions in FP64; sin/cos (hardware, revolution argument), the ratio and the
@@ -19,8 +22,34 @@
 namespace rbl {
 
 // Unit phasor u = exp(-2 pi i phi) for a phase in revolutions.
-__device__ inline void unit_phasor(double phi, double& c, double& s) { expm2pi_rev(phi, c, s); }
-__device__ inline void unit_phasor(double phi, float& c, float& s) {
+//
+// FP64: with N = kPhasorN, N phi = k + t, k = rint(N phi), |t| <= 1/2, so
+// exp(2 pi i phi) = E_k exp(2 pi i t / N) with E_k = exp(2 pi i k / N) from the table.  The
+// rotation angle a = 2 pi t / N is at most pi / N = 0.0061: sin a to degree 5 and cos a
+// to degree 4 of their Taylor series leave truncation errors below 1e-19 and 8e-17.
+// k mod N is read from the low mantissa bits of N phi + 1.5 * 2^52, which holds rint(N phi)
+// in its last place for |N phi| < 2^51; N phi - k is exact.
+namespace phasor_detail {
+constexpr double kW = 2.0 * 3.14159265358979323846 / kPhasorN;
+constexpr double kS0 = kW, kS1 = -kW * kW * kW / 6.0, kS2 = kW * kW * kW * kW * kW / 120.0;
+constexpr double kC1 = -kW * kW / 2.0, kC2 = kW * kW * kW * kW / 24.0;
+constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
+}  // namespace phasor_detail
+
+__device__ inline void unit_phasor(double phi, const double2* tab, double& c, double& s) {
+    using namespace phasor_detail;
+    const double m = fma(phi, (double)kPhasorN, kMagic);
+    const double k = m - kMagic;
+    const double t = fma(phi, (double)kPhasorN, -k);
+    const double2 e = tab[(unsigned)__double2loint(m) & (unsigned)(kPhasorN - 1)];
+    const double t2 = t * t;
+    const double sa = fma(fma(kS2, t2, kS1), t2, kS0) * t;
+    const double ca = fma(fma(kC2, t2, kC1), t2, 1.0);
+    c = fma(e.x, ca, -(e.y * sa));
+    s = -fma(e.y, ca, e.x * sa);
+}
+// Mixed precision: the hardware FP32 sin / cos on the reduced phase.
+__device__ inline void unit_phasor(double phi, const double2*, float& c, float& s) {
     const float t = (float)(phi - rint(phi));  // exact reduction in FP64, then rounded once
     c = __builtin_amdgcn_cosf(t);              // v_cos_f32: cos(2 pi t)
     s = -__builtin_amdgcn_sinf(t);             // v_sin_f32: sin(2 pi t)
@@ -28,13 +57,20 @@ __device__ inline void unit_phasor(double phi, float& c, float& s) {
 
 template <class R>
 struct EdgeTab {
-    const R *gre, *gim, *mu, *nul;
+    const R *gre, *gim, *mu, *xl;
 };
-__device__ inline EdgeTab<double> edge_tab(const EventDev& ev, double) { return {ev.g_re, ev.g_im, ev.mu, ev.nuL}; }
-__device__ inline EdgeTab<float> edge_tab(const EventDev& ev, float) { return {ev.g_re32, ev.g_im32, ev.mu32, ev.nuL32}; }
-// nuR_j = nuL_{j+1}: the cross coefficient of the bin right of edge j
-__device__ inline const double* nur_tab(const EventDev& ev, double) { return ev.nuR; }
-__device__ inline const float* nur_tab(const EventDev& ev, float) { return ev.nuR32; }
+__device__ inline EdgeTab<double> edge_tab(const EventDev& ev, double) { return {ev.g_re, ev.g_im, ev.mu, ev.xL}; }
+__device__ inline EdgeTab<float> edge_tab(const EventDev& ev, float) { return {ev.g_re32, ev.g_im32, ev.mu32, ev.xL32}; }
+// xR_j = xL_{j+1}: the cross weight of the bin right of edge j
+__device__ inline const double* xr_tab(const EventDev& ev, double) { return ev.xR; }
+__device__ inline const float* xr_tab(const EventDev& ev, float) { return ev.xR32; }
+
+// The phasor table, copied into LDS by every block of the likelihood kernels.
+__device__ inline void load_phasor_table(const EventDev& ev, double2* tab) {
+    const double2* src = reinterpret_cast<const double2*>(ev.phasor);
+    for (int i = threadIdx.x; i < kPhasorN; i += blockDim.x) tab[i] = src[i];
+    __syncthreads();
+}
 
 // Table load with a 32-bit byte offset: lets the compiler address every table of a step
 // from its scalar base plus one shared vector offset (global_load ... saddr).
@@ -93,7 +129,7 @@ __device__ inline void edge_phase(const EventDev& ev, const ChainVals<ND>& cv, u
 // lane's first edge needs the last edge of lane - 1: exchanged once at the end.
 // ---------------------------------------------------------------------------
 template <int ND, class R, int WF>
-__device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, int lane) {
+__device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, const double2* tab, int lane) {
     const EdgeTab<R> T = edge_tab(ev, R(0));
     const int npad = ev.n_nodes_pad;
     R kre[ND], kim[ND], pre[ND], pim[ND], fre[ND], fim[ND];
@@ -113,20 +149,21 @@ __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, i
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             R cu, su;
-            unit_phasor(fma(f, cv.dtau[d], ph), cu, su);
+            unit_phasor(fma(f, cv.dtau[d], ph), tab, cu, su);
             cu *= ar;
             su *= ar;
             const R rre = kre[d] * cu - kim[d] * su;
             const R rim = kre[d] * su + kim[d] * cu;
             const unsigned o = (unsigned)(d * npad) + pos;
-            R t = (ld(T.gre, o) * rre + ld(T.gim, o) * rim) - R(0.5) * ld(T.mu, o) * (rre * rre + rim * rim);
+            const R gr = ld(T.gre, o) * rre + ld(T.gim, o) * rim;
+            R h = -(ld(T.mu, o) * (rre * rre + rim * rim));  // the quadratic part of 2 lnL
             if (k > 0) {
-                t -= R(0.5) * ld(T.nul, o) * (pre[d] * rre + pim[d] * rim);
+                h = fma(ld(T.xl, o), pre[d] * rre + pim[d] * rim, h);
             } else {
                 fre[d] = rre;
                 fim[d] = rim;
             }
-            acc += (double)t;
+            acc += (double)fma(R(0.5), h, gr);
             pre[d] = rre;
             pim[d] = rim;
         }
@@ -134,7 +171,7 @@ __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, i
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         const R lre = shift_up(pre[d], R(0), lane), lim = shift_up(pim[d], R(0), lane);
-        acc -= (double)(R(0.5) * ld(T.nul, (unsigned)(d * npad + lane)) * (lre * fre[d] + lim * fim[d]));
+        acc += (double)(R(0.5) * ld(T.xl, (unsigned)(d * npad + lane)) * (lre * fre[d] + lim * fim[d]));
     }
     return acc;
 }
@@ -145,8 +182,8 @@ __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, i
 // The left neighbour of an edge is the previous lane, or for lane 0 the last lane of
 // the previous step (a wave-uniform carry).
 template <int ND, class R>
-__device__ inline void nrt_ratio(const EventDev& ev, const ChainVals<ND>& cv, unsigned pos, const R* kre, const R* kim,
-                                 R* rre, R* rim, double& a, NrtShared* sh = nullptr) {
+__device__ inline void nrt_ratio(const EventDev& ev, const ChainVals<ND>& cv, const double2* tab, unsigned pos,
+                                 const R* kre, const R* kim, R* rre, R* rim, double& a, NrtShared* sh = nullptr) {
     const double f = ld(ev.node_f, pos);
     double ph;
     nrt_node(cv.np, f, ld(ev.node_x, pos), ld(ev.node_ix, pos), ld(ev.node_lx, pos), ld(ev.node_x578, pos), true, ph, a,
@@ -156,7 +193,7 @@ __device__ inline void nrt_ratio(const EventDev& ev, const ChainVals<ND>& cv, un
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         R cu, su;
-        unit_phasor(fma(f, cv.dtau[d], dph), cu, su);
+        unit_phasor(fma(f, cv.dtau[d], dph), tab, cu, su);
         cu *= ar;
         su *= ar;
         rre[d] = kre[d] * cu - kim[d] * su;
@@ -165,7 +202,7 @@ __device__ inline void nrt_ratio(const EventDev& ev, const ChainVals<ND>& cv, un
 }
 
 template <int ND, class R>
-__device__ inline double fwd_walk_natural(const EventDev& ev, const ChainVals<ND>& cv, int lane) {
+__device__ inline double fwd_walk_natural(const EventDev& ev, const ChainVals<ND>& cv, const double2* tab, int lane) {
     const EdgeTab<R> T = edge_tab(ev, R(0));
     const int npad = ev.n_nodes_pad;
     R kre[ND], kim[ND], pre[ND], pim[ND];  // pre/pim: the previous step's ratios
@@ -180,14 +217,14 @@ __device__ inline double fwd_walk_natural(const EventDev& ev, const ChainVals<ND
         const unsigned pos = (unsigned)(k * 64 + lane);
         R rre[ND], rim[ND];
         double a;
-        nrt_ratio<ND, R>(ev, cv, pos, kre, kim, rre, rim, a);
+        nrt_ratio<ND, R>(ev, cv, tab, pos, kre, kim, rre, rim, a);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const R lre = left_neighbour(rre[d], pre[d]), lim = left_neighbour(rim[d], pim[d]);
             const unsigned o = (unsigned)(d * npad) + pos;
-            const R t = (ld(T.gre, o) * rre[d] + ld(T.gim, o) * rim[d]) - R(0.5) * ld(T.mu, o) * (rre[d] * rre[d] + rim[d] * rim[d])
-                      - R(0.5) * ld(T.nul, o) * (lre * rre[d] + lim * rim[d]);
-            acc += (double)t;
+            const R gr = ld(T.gre, o) * rre[d] + ld(T.gim, o) * rim[d];
+            const R h = fma(ld(T.xl, o), lre * rre[d] + lim * rim[d], -(ld(T.mu, o) * (rre[d] * rre[d] + rim[d] * rim[d])));
+            acc += (double)fma(R(0.5), h, gr);
             pre[d] = rre[d];
             pim[d] = rim[d];
         }
@@ -198,6 +235,8 @@ __device__ inline double fwd_walk_natural(const EventDev& ev, const ChainVals<ND
 template <int ND, bool MIXED, int WF>
 __global__ __launch_bounds__(256) void k_loglike_fwd(EventDev ev, const double* __restrict__ recs, int64_t B,
                                                      double* __restrict__ lnl) {
+    __shared__ double2 tab[kPhasorN];
+    load_phasor_table(ev, tab);
     const int lane = threadIdx.x & 63;
     const int64_t chain = (int64_t)blockIdx.x * 4 + wave_id();
     if (chain >= B) return;
@@ -224,14 +263,14 @@ __global__ __launch_bounds__(256) void k_loglike_fwd(EventDev ev, const double* 
     double acc;
     if constexpr (WF == kWfNrtv2) {
         if (MIXED && use_mixed<ND>(ev, cv))
-            acc = fwd_walk_natural<ND, float>(ev, cv, lane);
+            acc = fwd_walk_natural<ND, float>(ev, cv, tab, lane);
         else
-            acc = fwd_walk_natural<ND, double>(ev, cv, lane);
+            acc = fwd_walk_natural<ND, double>(ev, cv, tab, lane);
     } else {
         if (MIXED && use_mixed<ND>(ev, cv))
-            acc = fwd_walk<ND, float, WF>(ev, cv, lane);
+            acc = fwd_walk<ND, float, WF>(ev, cv, tab, lane);
         else
-            acc = fwd_walk<ND, double, WF>(ev, cv, lane);
+            acc = fwd_walk<ND, double, WF>(ev, cv, tab, lane);
     }
     acc = wave_sum(acc);
     if (lane == 0) lnl[chain] = acc;
@@ -240,9 +279,12 @@ __global__ __launch_bounds__(256) void k_loglike_fwd(EventDev ev, const double* 
 // ---------------------------------------------------------------------------
 // Gradient.  d lnL = sum_j Re(conj(Gbar_j) dr_j) with
 //   Gbar_j = gamma_j - mu_j r_j + c_j r_{j-1} + c_{j+1} r_{j+1},   z_j = conj(Gbar_j) r_j,
-//   d lnL / d phi_j = 2 pi Im z_j,   d lnL = Re(Z_d dK_d / K_d),  Z_d = sum_j z_dj.
+//   c_j = xL_j / 2,  d lnL / d phi_j = 2 pi Im z_j,  d lnL = Re(Z_d dK_d / K_d),  Z_d = sum_j z_dj.
 // Each cross term is handled at its later edge: with w = c conj(r_{j-1}) r_j it adds
 // w to z_j and conj(w) to z_{j-1} (2 Re w to Z_d, Im w to Im z_j, -Im w to Im z_{j-1}).
+// Im z_j = Im(conj(gamma_j) r_j) + cross terms (the mu term is real), and
+//   Re Z_d = sum_j [ Re(gamma r*) - mu |r|^2 + 2 (cross) ] = 2 lnL_d - sum_j Re(gamma r*),
+// so lnL = (sum_d Re Z_d + sum_dj Re(gamma_dj r_dj*)) / 2 needs one accumulator more.
 // Per lane: Z_d, T_d = sum_j Im(z_dj) f_j and S_b = sum_j (sum_d Im z_dj) B_b(x_j);
 // an edge's basis term is completed one step later, when the cross term to its right
 // is known.  Each lane first evaluates the ratio at the edge before its first edge
@@ -250,13 +292,14 @@ __global__ __launch_bounds__(256) void k_loglike_fwd(EventDev ev, const double* 
 // ---------------------------------------------------------------------------
 template <int ND, int NA>
 struct GradAcc {
-    double acc;
+    double acc;  // sum_dj Re(gamma_dj r_dj*)
     double zr[ND], zi[ND], ta[ND];
     double sa[NA];  // TaylorF2: S_b (basis);  IMRPhenomD_NRTidalv2: adjoints of the node parameters
 };
 
 template <int ND, class R>
-__device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, int lane, GradAcc<ND, kTf2Basis>& G) {
+__device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, const double2* tab, int lane,
+                                 GradAcc<ND, kTf2Basis>& G) {
     const EdgeTab<R> T = edge_tab(ev, R(0));
     const int npad = ev.n_nodes_pad;
     const int L = ev.L;
@@ -266,7 +309,7 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, in
         kre[d] = (R)cv.kre[d];
         kim[d] = (R)cv.kim[d];
     }
-    // halo edge: the last edge of lane - 1 (lane 0 has none; its first edge has nuL = 0)
+    // halo edge: the last edge of lane - 1 (lane 0 has none; its first edge has xL = 0)
     const unsigned hpos = (unsigned)(lane > 0 ? (L - 1) * 64 + (lane - 1) : npad - 1);
     double fp = ld(ev.node_f, hpos), xp = ld(ev.node_x, hpos), ixp = ld(ev.node_ix, hpos), lxp = ld(ev.node_lx, hpos);
     {
@@ -278,7 +321,7 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, in
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             R ur, ui;
-            unit_phasor(fma(fp, cv.dtau[d], ph), ur, ui);
+            unit_phasor(fma(fp, cv.dtau[d], ph), tab, ur, ui);
             rpr[d] = kre[d] * ur - kim[d] * ui;
             rpi[d] = kre[d] * ui + kim[d] * ur;
         }
@@ -292,37 +335,37 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, in
         double ph = 0.0;
 #pragma unroll
         for (int b = 0; b < kTf2Basis; ++b) ph = fma(cv.dc[b], bas[b], ph);
-        double q = 0.0, p = 0.0;
-        const double df = f - fp;
+        double qz = 0.0, p2 = 0.0;  // sum_d Im(conj(gamma) r), sum_d 2 Im w
+        const double hdf = 0.5 * (f - fp);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             R ur, ui;
-            unit_phasor(fma(f, cv.dtau[d], ph), ur, ui);
+            unit_phasor(fma(f, cv.dtau[d], ph), tab, ur, ui);
             const R rre = kre[d] * ur - kim[d] * ui;
             const R rim = kre[d] * ui + kim[d] * ur;
             const unsigned o = (unsigned)(d * npad) + pos;
-            const R gre = ld(T.gre, o), gim = ld(T.gim, o), mu = ld(T.mu, o);
-            const R c = R(-0.5) * ld(T.nul, o);
-            const R glr = gre - mu * rre, gli = gim - mu * rim;  // local part of Gbar
-            const R reloc = glr * rre + gli * rim, imz = glr * rim - gli * rre;
-            const R rew = c * (rpr[d] * rre + rpi[d] * rim), imw = c * (rpr[d] * rim - rpi[d] * rre);
-            G.acc += (double)(reloc + R(0.5) * mu * (rre * rre + rim * rim) + rew);
-            G.zr[d] += (double)(reloc + R(2) * rew);
+            const R gre = ld(T.gre, o), gim = ld(T.gim, o), mu = ld(T.mu, o), xl = ld(T.xl, o);
+            const R gr = gre * rre + gim * rim;
+            const R zt = fma(xl, rpr[d] * rre + rpi[d] * rim, fma(-mu, rre * rre + rim * rim, gr));
+            const R imz = gre * rim - gim * rre;
+            const R imw2 = xl * (rpr[d] * rim - rpi[d] * rre);
+            G.acc += (double)gr;
+            G.zr[d] += (double)zt;
             G.zi[d] += (double)imz;
-            q += (double)(imz + imw);
-            p += (double)imw;
-            G.ta[d] = fma((double)imz, f, fma((double)imw, df, G.ta[d]));
+            qz += (double)imz;
+            p2 += (double)imw2;
+            G.ta[d] = fma((double)imz, f, fma((double)imw2, hdf, G.ta[d]));
             rpr[d] = rre;
             rpi[d] = rim;
         }
-        {   // the previous edge is now complete: it carries q_prev - p
+        {   // the previous edge is now complete: it carries q_prev - p, p = p2 / 2
             double bp[kTf2Basis];
             tf2_basis(xp, ixp, lxp, bp);
-            const double qp = qprev - p;
+            const double qp = fma(-0.5, p2, qprev);
 #pragma unroll
             for (int b = 0; b < kTf2Basis; ++b) G.sa[b] = fma(qp, bp[b], G.sa[b]);
         }
-        qprev = q;
+        qprev = fma(0.5, p2, qz);
         fp = f; xp = x; ixp = ix; lxp = lx;
     }
     double bp[kTf2Basis];
@@ -338,11 +381,12 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, in
 // ratio of the next step is evaluated first, so that both neighbours of every edge of
 // the current step are known (previous / next lane, or the carry from the previous
 // step / lane 0 of the next step) and W_j is complete when its adjoint runs.  The right
-// cross coefficient c_{j+1} = -nuR_j / 2 is read from the edge's own table.
+// cross coefficient c_{j+1} = xR_j / 2 is read from the edge's own table.
 template <int ND, class R>
-__device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv, int lane, GradAcc<ND, kNrtAdj>& G) {
+__device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv, const double2* tab, int lane,
+                                     GradAcc<ND, kNrtAdj>& G) {
     const EdgeTab<R> T = edge_tab(ev, R(0));
-    const R* nur = nur_tab(ev, R(0));
+    const R* xrt = xr_tab(ev, R(0));
     const int npad = ev.n_nodes_pad;
     const int L = ev.L;
     R kre[ND], kim[ND], rcr[ND], rci[ND], rnr[ND], rni[ND], rpr[ND], rpi[ND];
@@ -354,10 +398,10 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
     }
     double acur, anext = 0.0;
     NrtShared scur, snext{0.0, 0.0, 0.0};
-    nrt_ratio<ND, R>(ev, cv, lane, kre, kim, rcr, rci, acur, &scur);
+    nrt_ratio<ND, R>(ev, cv, tab, lane, kre, kim, rcr, rci, acur, &scur);
     for (int k = 0; k < L; ++k) {
         if (k + 1 < L) {
-            nrt_ratio<ND, R>(ev, cv, (k + 1) * 64 + lane, kre, kim, rnr, rni, anext, &snext);
+            nrt_ratio<ND, R>(ev, cv, tab, (k + 1) * 64 + lane, kre, kim, rnr, rni, anext, &snext);
         } else {
 #pragma unroll
             for (int d = 0; d < ND; ++d) rnr[d] = rni[d] = R(0);
@@ -372,8 +416,8 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
             const R nre = right_neighbour(rre, rnr[d]), nim = right_neighbour(rim, rni[d]);
             const unsigned o = (unsigned)(d * npad) + pos;
             const R gre = ld(T.gre, o), gim = ld(T.gim, o), mu = ld(T.mu, o);
-            const R cl = R(-0.5) * ld(T.nul, o), cr = R(-0.5) * ld(nur, o);
-            G.acc += (double)((gre * rre + gim * rim) - R(0.5) * mu * (rre * rre + rim * rim) + cl * (lre * rre + lim * rim));
+            const R cl = R(0.5) * ld(T.xl, o), cr = R(0.5) * ld(xrt, o);
+            G.acc += (double)(gre * rre + gim * rim);
             const R gbr = gre - mu * rre + cl * lre + cr * nre;
             const R gbi = gim - mu * rim + cl * lim + cr * nim;
             const double zr = (double)(gbr * rre + gbi * rim), zi = (double)(gbr * rim - gbi * rre);
@@ -403,6 +447,8 @@ template <int ND, bool MIXED, int WF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNrtv2 ? 2 : 4))) void k_loglike_grad(
     EventDev ev, const double* __restrict__ recs, const double* __restrict__ jac, int64_t B,
     double* __restrict__ lnl, double* __restrict__ grad) {
+    __shared__ double2 tab[kPhasorN];
+    load_phasor_table(ev, tab);
     const int lane = threadIdx.x & 63;
     const int64_t chain = (int64_t)blockIdx.x * 4 + wave_id();
     if (chain >= B) return;
@@ -440,18 +486,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNr
     for (int b = 0; b < NA; ++b) G.sa[b] = 0.0;
     if constexpr (WF == kWfNrtv2) {
         if (MIXED && use_mixed<ND>(ev, cv))
-            grad_walk_nrt<ND, float>(ev, cv, lane, G);
+            grad_walk_nrt<ND, float>(ev, cv, tab, lane, G);
         else
-            grad_walk_nrt<ND, double>(ev, cv, lane, G);
+            grad_walk_nrt<ND, double>(ev, cv, tab, lane, G);
     } else {
         if (MIXED && use_mixed<ND>(ev, cv))
-            grad_walk<ND, float>(ev, cv, lane, G);
+            grad_walk<ND, float>(ev, cv, tab, lane, G);
         else
-            grad_walk<ND, double>(ev, cv, lane, G);
+            grad_walk<ND, double>(ev, cv, tab, lane, G);
     }
 
     // Wave reductions.  Z'_d = Z_d / K_d is the gradient with respect to K_d.
-    const double acc = wave_sum(G.acc);
+    double acc = wave_sum(G.acc);
     double A[NA], ZR[ND], ZI[ND], Tt[ND];
     constexpr double kAdjScale = WF == kWfNrtv2 ? 1.0 : 2.0 * kPi;  // NRTidalv2 adjoints include 2 pi
 #pragma unroll
@@ -459,11 +505,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNr
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         const double zre = wave_sum(G.zr[d]), zim = wave_sum(G.zi[d]);
+        acc += zre;
         const double k2 = cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d];
         ZR[d] = (zre * cv.kre[d] + zim * cv.kim[d]) / k2;
         ZI[d] = (zim * cv.kre[d] - zre * cv.kim[d]) / k2;
         Tt[d] = 2.0 * kPi * wave_sum(G.ta[d]);
     }
+    acc *= 0.5;  // lnL = (sum_d Re Z_d + sum Re(gamma r*)) / 2
     if (zero_k) {
         // A detector with K_d = 0 has r = 0 everywhere: d lnL / dK_d = sum_j conj(gamma_j) u_j.
         const int npad = ev.n_nodes_pad;

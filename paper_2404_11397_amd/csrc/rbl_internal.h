@@ -11,6 +11,7 @@ constexpr int kMaxDet = 3;
 constexpr int kWfTaylorF2 = 0;  // RBL_TAYLORF2
 constexpr int kWfNrtv2 = 1;     // RBL_PHENOMD_NRTV2
 constexpr int kNodeTile = 64;  // node tables are padded to a multiple of the wavefront
+constexpr int kPhasorN = 512;  // entries of the unit-phasor table exp(2 pi i k / kPhasorN)
 
 // Per-chain record produced by the setup kernels (FP64, 64 doubles, 512 B).
 //   [0]        status: 1 valid, 0 outside the physical domain, NaN if theta has a NaN
@@ -86,26 +87,30 @@ struct EventDev {
     const double* node_x;
     const double* node_ix;
     const double* node_lx;
-    // per (det, node) tables, [n_det][n_nodes_pad]: gamma (re, im), mu, nuL, nuR
+    // per (det, node) tables, [n_det][n_nodes_pad]: gamma (re, im), mu, and the cross
+    // coefficients xL_j = -nu(bin j-1), xR_j = -nu(bin j) = xL_{j+1}: the weights of
+    // Re(r_{j-1} r_j*) and Re(r_j r_{j+1}*) in 2 lnL
     const double* g_re;
     const double* g_im;
     const double* mu;
-    const double* nuL;
-    const double* nuR;
-    // FP32 copies of gamma, mu, nuL for the mixed-precision kernels
+    const double* xL;
+    const double* xR;
+    // FP32 copies for the mixed-precision kernels
     const float* g_re32;
     const float* g_im32;
     const float* mu32;
-    const float* nuL32;
-    const float* nuR32;
+    const float* xL32;
+    const float* xR32;
     // IMRPhenomD_NRTidalv2 events: reference phase [rev] and inverse amplitude factor per edge
     const double* phi0;
     const double* ia0;
     const float* ia0_32;
     const double* node_x578;  // x^5.78 per edge (IMRPhenomD_NRTidalv2 tidal amplitude)
-    // per detector: Gs_d = sum_j |gamma_dj|, Hs_d = sum_j (|mu_dj| + |nuL_dj|)  [2 * kMaxDet]
+    // per detector: Gs_d = sum_j |gamma_dj|, Hs_d = sum_j (|mu_dj| + |xL_dj|)  [2 * kMaxDet]
     // (a chain's binned-sum magnitude is at most sum_d |K_d| Gs_d + |K_d|^2 Hs_d)
     const double* scales;
+    // [kPhasorN][2]: cos and sin of 2 pi k / kPhasorN (read into LDS by the likelihood kernels)
+    const double* phasor;
 };
 
 // Mixed precision is used for a chain while the magnitude bound of its binned sum,

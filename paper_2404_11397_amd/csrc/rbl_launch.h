@@ -41,8 +41,8 @@ struct NodeArgs {
     double f_low, delta_f;
     const double* summary;  // [n_det][n_bins][7]
     double *node_f, *node_x, *node_ix, *node_lx;
-    double *g_re, *g_im, *mu, *nuL, *nuR;
-    float *g_re32, *g_im32, *mu32, *nuL32, *nuR32;
+    double *g_re, *g_im, *mu, *xL, *xR;
+    float *g_re32, *g_im32, *mu32, *xL32, *xR32;
     double* scales;
 };
 

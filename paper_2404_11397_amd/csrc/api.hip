@@ -303,10 +303,10 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     double* node_block = nullptr;
     // FP64 tables, scales, FP32 tables (2 nd np floats), reference phase / amplitude (2 np), FP32 amplitude
     // tables: 4 edge columns and 5 per-detector columns (FP64), the scales, 5 per-detector
-    // FP32 columns, phi0 and 1/a0 (FP64), 1/a0 (FP32), x^5.78 (FP64), the phasor table; np is a
-    // multiple of 64
+    // FP32 columns, phi0 and 1/a0 (FP64), 1/a0 (FP32), x^5.78 (FP64), the phasor table, the
+    // per-detector sums of mu; np is a multiple of 64
     const int64_t node_doubles =
-        np * (4 + 5 * nd) + 2 * kMaxDet + np * 5 * nd / 2 + 2 * np + np / 2 + np + 2 * kPhasorN;
+        np * (4 + 5 * nd) + 2 * kMaxDet + np * 5 * nd / 2 + 2 * np + np / 2 + np + 2 * kPhasorN + kMaxDet;
     if (ev->mem.alloc((void**)&node_block, sizeof(double) * node_doubles) != hipSuccess)
         return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (node tables)"));
 
@@ -371,6 +371,7 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     na.ia0_32 = (float*)(na.ia0 + np);
     na.node_x578 = na.ia0 + np + np / 2;
     double* d_phasor = na.node_x578 + np;
+    na.mu_sum = d_phasor + 2 * kPhasorN;
     // cos and sin of 2 pi k / kPhasorN, evaluated in extended precision and rounded once
     std::vector<double> phasor(2 * kPhasorN);
     for (int k = 0; k < kPhasorN; ++k) {
@@ -427,6 +428,7 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     dv.ia0_32 = na.ia0_32;
     dv.node_x578 = na.node_x578;
     dv.phasor = d_phasor;
+    dv.mu_sum = na.mu_sum;
     ev->footprint = (int64_t)sizeof(double) * (nd * nb * 7 + node_doubles) +
                     ((desc->flags & RBL_KEEP_GRID) ? (int64_t)sizeof(double) * 3 * nd * n : 0);
     *out = ev;

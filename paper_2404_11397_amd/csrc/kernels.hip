@@ -74,7 +74,7 @@ __device__ inline void chain_record(const T* th, const Network& net, const RefCo
     } else {
         Tf2Coeffs<T> c;
         tf2_coeffs<T>(th[0], th[1], th[2], th[3], th[4], th[5], c);
-        for (int b = 0; b < kTf2Basis; ++b) rec[kRecDc + b] = c.c[b] - ref.c0[b];
+        for (int b = 0; b < kTf2Basis; ++b) rec[kRecDc + b] = (c.c[b] - ref.c0[b]) * (double)kPhasorN;
         dconst = c.c_const - ref.c0_const;
         dconst = dconst - rint(val(dconst));  // whole revolutions removed (no derivative)
         amp = c.amp;
@@ -93,7 +93,7 @@ __device__ inline void chain_record(const T* th, const Network& net, const RefCo
             const Cx<T> k = cmul(cmul(p.C, inv0), common);
             rec[kRecK + 2 * d] = k.re;
             rec[kRecK + 2 * d + 1] = k.im;
-            rec[kRecTau + d] = (th[7] + p.dt) - ref.tau0[d];
+            rec[kRecTau + d] = ((th[7] + p.dt) - ref.tau0[d]) * (double)kPhasorN;
         } else {
             rec[kRecK + 2 * d] = T(0.0);
             rec[kRecK + 2 * d + 1] = T(0.0);
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(256) void k_chain_setup_grad(const double* __restri
         J[kJacInt + kJacAmpTf2 * 6 + tg] = c.amp.d[0] / c.amp.v;
         if (tg == 0) {
             out[kRecStatus] = 1.0;
-            for (int k = 0; k < kTf2Basis; ++k) out[kRecDc + k] = c.c[k].v - ref.c0[k];
+            for (int k = 0; k < kTf2Basis; ++k) out[kRecDc + k] = (c.c[k].v - ref.c0[k]) * (double)kPhasorN;
             double dconst = c.c_const.v - ref.c0_const;
             dconst -= rint(dconst);
             const double ang = 2.0 * (t[8] - ref.phic0) - (2.0 * kPi) * dconst;
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(256) void k_chain_setup_grad(const double* __restri
                 if (tg == 0) {
                     out[kRecK + 2 * d] = P.re.v;
                     out[kRecK + 2 * d + 1] = P.im.v;
-                    out[kRecTau + d] = (t[7] + p.dt.v) - ref.tau0[d];
+                    out[kRecTau + d] = ((t[7] + p.dt.v) - ref.tau0[d]) * (double)kPhasorN;
                 }
             } else {
                 J[kJacExt + (d * 3 + 0) * 4 + tg] = J[kJacExt + (d * 3 + 1) * 4 + tg] =
@@ -442,22 +442,25 @@ __global__ void k_node_tables(NodeArgs a) {
     }
 }
 
-// Per-detector magnitude sums of the edge tables (one wavefront per detector,
-// fixed reduction order).
+// Per-detector magnitude sums of the edge tables and M_d = sum_j mu_dj (one wavefront
+// per detector, fixed reduction order).
 __global__ __launch_bounds__(64) void k_event_scales(NodeArgs a) {
     const int d = blockIdx.x;
     const int lane = threadIdx.x;
-    double gs = 0.0, hs = 0.0;
+    double gs = 0.0, hs = 0.0, ms = 0.0;
     for (int j = lane; j < a.n_nodes_pad; j += 64) {
         const int64_t o = (int64_t)d * a.n_nodes_pad + j;
         gs += sqrt(a.g_re[o] * a.g_re[o] + a.g_im[o] * a.g_im[o]);
         hs += fabs(a.mu[o]) + fabs(a.xL[o]);
+        ms += a.mu[o];
     }
     gs = wave_sum(gs);
     hs = wave_sum(hs);
+    ms = wave_sum(ms);
     if (lane == 0) {
         a.scales[2 * d] = gs;
         a.scales[2 * d + 1] = hs;
+        a.mu_sum[d] = ms;
     }
 }
 
@@ -482,13 +485,13 @@ __global__ __launch_bounds__(256) void k_loglike_full(FullArgs a) {
         for (int i = 0; i < kNrtParams; ++i) dst[i] = rec[kRecNrt + i];
     }
     double c[kTf2Basis];
-    for (int k = 0; k < kTf2Basis; ++k) c[k] = ref.c0[k] + rec[kRecDc + k];
+    for (int k = 0; k < kTf2Basis; ++k) c[k] = ref.c0[k] + rec[kRecDc + k] * (1.0 / kPhasorN);
     double fre[kMaxDet], fim[kMaxDet], tau[kMaxDet];
     for (int d = 0; d < a.n_det; ++d) {
         const double kre = rec[kRecK + 2 * d], kim = rec[kRecK + 2 * d + 1];
         fre[d] = ref.amp0 * (ref.h0fac_re[d] * kre - ref.h0fac_im[d] * kim);
         fim[d] = ref.amp0 * (ref.h0fac_re[d] * kim + ref.h0fac_im[d] * kre);
-        tau[d] = ref.tau0[d] + rec[kRecTau + d];
+        tau[d] = ref.tau0[d] + rec[kRecTau + d] * (1.0 / kPhasorN);
     }
     const double w = 4.0 * a.delta_f;
     double acc = 0.0;

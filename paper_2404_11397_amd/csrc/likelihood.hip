@@ -23,12 +23,13 @@ namespace rbl {
 
 // Unit phasor u = exp(-2 pi i phi) for a phase in revolutions.
 //
-// FP64: with N = kPhasorN, N phi = k + t, k = rint(N phi), |t| <= 1/2, so
+// The walks carry phases in table units y = N phi, N = kPhasorN (an exact power-of-two
+// scaling of revolutions).  FP64: y = k + t, k = rint(y), |t| <= 1/2, so
 // exp(2 pi i phi) = E_k exp(2 pi i t / N) with E_k = exp(2 pi i k / N) from the table.  The
 // rotation angle a = 2 pi t / N is at most pi / N = 0.0061: sin a to degree 5 and cos a
 // to degree 4 of their Taylor series leave truncation errors below 1e-19 and 8e-17.
-// k mod N is read from the low mantissa bits of N phi + 1.5 * 2^52, which holds rint(N phi)
-// in its last place for |N phi| < 2^51; N phi - k is exact.
+// k mod N is read from the low mantissa bits of y + 1.5 * 2^52, which holds rint(y) in its
+// last place for |y| < 2^51; y - k is exact.
 namespace phasor_detail {
 constexpr double kW = 2.0 * 3.14159265358979323846 / kPhasorN;
 constexpr double kS0 = kW, kS1 = -kW * kW * kW / 6.0, kS2 = kW * kW * kW * kW * kW / 120.0;
@@ -36,11 +37,11 @@ constexpr double kC1 = -kW * kW / 2.0, kC2 = kW * kW * kW * kW / 24.0;
 constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
 }  // namespace phasor_detail
 
-__device__ inline void unit_phasor(double phi, const double2* tab, double& c, double& s) {
+__device__ inline void unit_phasor(double y, const double2* tab, double& c, double& s) {
     using namespace phasor_detail;
-    const double m = fma(phi, (double)kPhasorN, kMagic);
+    const double m = y + kMagic;
     const double k = m - kMagic;
-    const double t = fma(phi, (double)kPhasorN, -k);
+    const double t = y - k;
     const double2 e = tab[(unsigned)__double2loint(m) & (unsigned)(kPhasorN - 1)];
     const double t2 = t * t;
     const double sa = fma(fma(kS2, t2, kS1), t2, kS0) * t;
@@ -49,7 +50,8 @@ __device__ inline void unit_phasor(double phi, const double2* tab, double& c, do
     s = -fma(e.y, ca, e.x * sa);
 }
 // Mixed precision: the hardware FP32 sin / cos on the reduced phase.
-__device__ inline void unit_phasor(double phi, const double2*, float& c, float& s) {
+__device__ inline void unit_phasor(double y, const double2*, float& c, float& s) {
+    const double phi = y * (1.0 / kPhasorN);
     const float t = (float)(phi - rint(phi));  // exact reduction in FP64, then rounded once
     c = __builtin_amdgcn_cosf(t);              // v_cos_f32: cos(2 pi t)
     s = -__builtin_amdgcn_sinf(t);             // v_sin_f32: sin(2 pi t)
@@ -79,7 +81,7 @@ __device__ inline T ld(const T* base, unsigned idx) {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(T));
 }
 
-// Per-chain values shared by the walks.
+// Per-chain values shared by the walks.  dc and dtau are in table units, as in the record.
 template <int ND>
 struct ChainVals {
     double dc[kTf2Basis];
@@ -101,7 +103,7 @@ __device__ inline bool use_mixed(const EventDev& ev, const ChainVals<ND>& cv) {
     return bound <= kMixedScaleMax;
 }
 
-// Edge phase (revolutions, relative to the reference) and amplitude ratio.
+// Edge phase (table units, relative to the reference) and amplitude ratio.
 //   TaylorF2:  sum_b dc_b B_b(x), ratio 1 (the Mc^(5/6) factor is in K);
 //   IMRPhenomD_NRTidalv2:  Phi(f; theta) - Phi0_j, ratio a(f; theta) / a0_j.
 template <int ND, int WF>
@@ -111,12 +113,12 @@ __device__ inline void edge_phase(const EventDev& ev, const ChainVals<ND>& cv, u
     if (WF == kWfNrtv2) {
         double ph, a;
         nrt_node(cv.np, f, x, ix, lx, ld(ev.node_x578, pos), true, ph, a);
-        dph = ph - ld(ev.phi0, pos);
+        dph = (ph - ld(ev.phi0, pos)) * (double)kPhasorN;
         ar = a * ld(ev.ia0, pos);
     } else {
         double bas[kTf2Basis];
         tf2_basis(x, ix, lx, bas);
-        double ph = 0.0;
+        double ph = -0.0;
 #pragma unroll
         for (int b = 0; b < kTf2Basis; ++b) ph = fma(cv.dc[b], bas[b], ph);
         dph = ph;
@@ -125,10 +127,11 @@ __device__ inline void edge_phase(const EventDev& ev, const ChainVals<ND>& cv, u
 }
 
 // ---------------------------------------------------------------------------
-// Forward walk: this lane's share of lnL.  The cross term of the bin left of a
-// lane's first edge needs the last edge of lane - 1: exchanged once at the end.
+// TaylorF2 forward walk: this lane's share of lnL without the quadratic term, which is
+// -sum_d |K_d|^2 M_d / 2 (|r_dj| = |K_d|).  The cross term of the bin left of a lane's
+// first edge needs the last edge of lane - 1: exchanged once at the end.
 // ---------------------------------------------------------------------------
-template <int ND, class R, int WF>
+template <int ND, class R>
 __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, const double2* tab, int lane) {
     const EdgeTab<R> T = edge_tab(ev, R(0));
     const int npad = ev.n_nodes_pad;
@@ -143,27 +146,26 @@ __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, c
     for (int k = 0; k < ev.L; ++k) {
         const unsigned pos = (unsigned)(k * 64 + lane);
         const double f = ld(ev.node_f, pos);
-        double ph, ard;
-        edge_phase<ND, WF>(ev, cv, pos, f, ph, ard);
-        const R ar = (R)ard;
+        double bas[kTf2Basis];
+        tf2_basis(ld(ev.node_x, pos), ld(ev.node_ix, pos), ld(ev.node_lx, pos), bas);
+        double ph = -0.0;
+#pragma unroll
+        for (int b = 0; b < kTf2Basis; ++b) ph = fma(cv.dc[b], bas[b], ph);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             R cu, su;
             unit_phasor(fma(f, cv.dtau[d], ph), tab, cu, su);
-            cu *= ar;
-            su *= ar;
             const R rre = kre[d] * cu - kim[d] * su;
             const R rim = kre[d] * su + kim[d] * cu;
             const unsigned o = (unsigned)(d * npad) + pos;
-            const R gr = ld(T.gre, o) * rre + ld(T.gim, o) * rim;
-            R h = -(ld(T.mu, o) * (rre * rre + rim * rim));  // the quadratic part of 2 lnL
+            R t = ld(T.gre, o) * rre + ld(T.gim, o) * rim;
             if (k > 0) {
-                h = fma(ld(T.xl, o), pre[d] * rre + pim[d] * rim, h);
+                t = fma(R(0.5) * ld(T.xl, o), pre[d] * rre + pim[d] * rim, t);
             } else {
                 fre[d] = rre;
                 fim[d] = rim;
             }
-            acc += (double)fma(R(0.5), h, gr);
+            acc += (double)t;
             pre[d] = rre;
             pim[d] = rim;
         }
@@ -174,6 +176,15 @@ __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, c
         acc += (double)(R(0.5) * ld(T.xl, (unsigned)(d * npad + lane)) * (lre * fre[d] + lim * fim[d]));
     }
     return acc;
+}
+
+// The quadratic term of a TaylorF2 chain, -sum_d |K_d|^2 M_d / 2.
+template <int ND>
+__device__ inline double tf2_quadratic(const EventDev& ev, const ChainVals<ND>& cv) {
+    double q = 0.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) q = fma(cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d], ev.mu_sum[d], q);
+    return -0.5 * q;
 }
 
 // IMRPhenomD_NRTidalv2 events keep their edge tables in natural order (edge j at
@@ -188,7 +199,7 @@ __device__ inline void nrt_ratio(const EventDev& ev, const ChainVals<ND>& cv, co
     double ph;
     nrt_node(cv.np, f, ld(ev.node_x, pos), ld(ev.node_ix, pos), ld(ev.node_lx, pos), ld(ev.node_x578, pos), true, ph, a,
              sh);
-    const double dph = ph - ld(ev.phi0, pos);
+    const double dph = (ph - ld(ev.phi0, pos)) * (double)kPhasorN;
     const R ar = (R)(a * ld(ev.ia0, pos));
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
@@ -268,11 +279,12 @@ __global__ __launch_bounds__(256) void k_loglike_fwd(EventDev ev, const double* 
             acc = fwd_walk_natural<ND, double>(ev, cv, tab, lane);
     } else {
         if (MIXED && use_mixed<ND>(ev, cv))
-            acc = fwd_walk<ND, float, WF>(ev, cv, tab, lane);
+            acc = fwd_walk<ND, float>(ev, cv, tab, lane);
         else
-            acc = fwd_walk<ND, double, WF>(ev, cv, tab, lane);
+            acc = fwd_walk<ND, double>(ev, cv, tab, lane);
     }
     acc = wave_sum(acc);
+    if constexpr (WF != kWfNrtv2) acc += tf2_quadratic<ND>(ev, cv);
     if (lane == 0) lnl[chain] = acc;
 }
 
@@ -285,6 +297,7 @@ __global__ __launch_bounds__(256) void k_loglike_fwd(EventDev ev, const double* 
 // Im z_j = Im(conj(gamma_j) r_j) + cross terms (the mu term is real), and
 //   Re Z_d = sum_j [ Re(gamma r*) - mu |r|^2 + 2 (cross) ] = 2 lnL_d - sum_j Re(gamma r*),
 // so lnL = (sum_d Re Z_d + sum_dj Re(gamma_dj r_dj*)) / 2 needs one accumulator more.
+// For TaylorF2 the mu part of Re Z_d is -|K_d|^2 M_d and is added after the walk.
 // Per lane: Z_d, T_d = sum_j Im(z_dj) f_j and S_b = sum_j (sum_d Im z_dj) B_b(x_j);
 // an edge's basis term is completed one step later, when the cross term to its right
 // is known.  Each lane first evaluates the ratio at the edge before its first edge
@@ -315,7 +328,7 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, co
     {
         double bas[kTf2Basis];
         tf2_basis(xp, ixp, lxp, bas);
-        double ph = 0.0;
+        double ph = -0.0;
 #pragma unroll
         for (int b = 0; b < kTf2Basis; ++b) ph = fma(cv.dc[b], bas[b], ph);
 #pragma unroll
@@ -332,10 +345,10 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, co
         const double f = ld(ev.node_f, pos), x = ld(ev.node_x, pos), ix = ld(ev.node_ix, pos), lx = ld(ev.node_lx, pos);
         double bas[kTf2Basis];
         tf2_basis(x, ix, lx, bas);
-        double ph = 0.0;
+        double ph = -0.0;
 #pragma unroll
         for (int b = 0; b < kTf2Basis; ++b) ph = fma(cv.dc[b], bas[b], ph);
-        double qz = 0.0, p2 = 0.0;  // sum_d Im(conj(gamma) r), sum_d 2 Im w
+        double qz = -0.0, p2 = -0.0;  // sum_d Im(conj(gamma) r), sum_d 2 Im w
         const double hdf = 0.5 * (f - fp);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
@@ -344,9 +357,9 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, co
             const R rre = kre[d] * ur - kim[d] * ui;
             const R rim = kre[d] * ui + kim[d] * ur;
             const unsigned o = (unsigned)(d * npad) + pos;
-            const R gre = ld(T.gre, o), gim = ld(T.gim, o), mu = ld(T.mu, o), xl = ld(T.xl, o);
+            const R gre = ld(T.gre, o), gim = ld(T.gim, o), xl = ld(T.xl, o);
             const R gr = gre * rre + gim * rim;
-            const R zt = fma(xl, rpr[d] * rre + rpi[d] * rim, fma(-mu, rre * rre + rim * rim, gr));
+            const R zt = fma(xl, rpr[d] * rre + rpi[d] * rim, gr);
             const R imz = gre * rim - gim * rre;
             const R imw2 = xl * (rpr[d] * rim - rpi[d] * rre);
             G.acc += (double)gr;
@@ -441,10 +454,11 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
     }
 }
 
-// Occupancy target: 4 waves per SIMD for TaylorF2; 2 for NRTidalv2, whose 26 adjoint
-// accumulators and per-edge model would otherwise spill.
+// Occupancy target: 3 waves per SIMD for TaylorF2 (the walk needs about 136 vector
+// registers; at 4 waves it would spill); 2 for NRTidalv2, whose 26 adjoint accumulators
+// and per-edge model would otherwise spill.
 template <int ND, bool MIXED, int WF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNrtv2 ? 2 : 4))) void k_loglike_grad(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNrtv2 ? 2 : 3))) void k_loglike_grad(
     EventDev ev, const double* __restrict__ recs, const double* __restrict__ jac, int64_t B,
     double* __restrict__ lnl, double* __restrict__ grad) {
     __shared__ double2 tab[kPhasorN];
@@ -504,9 +518,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNr
     for (int b = 0; b < NA; ++b) A[b] = kAdjScale * wave_sum(G.sa[b]);
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
-        const double zre = wave_sum(G.zr[d]), zim = wave_sum(G.zi[d]);
-        acc += zre;
         const double k2 = cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d];
+        double zre = wave_sum(G.zr[d]);
+        if constexpr (WF != kWfNrtv2) zre = fma(-k2, ev.mu_sum[d], zre);
+        const double zim = wave_sum(G.zi[d]);
+        acc += zre;
         ZR[d] = (zre * cv.kre[d] + zim * cv.kim[d]) / k2;
         ZI[d] = (zim * cv.kre[d] - zre * cv.kim[d]) / k2;
         Tt[d] = 2.0 * kPi * wave_sum(G.ta[d]);
@@ -525,7 +541,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNr
                 double ph, ar;
                 edge_phase<ND, WF>(ev, cv, pos, f, ph, ar);
                 double ur, ui;
-                expm2pi_rev(fma(f, cv.dtau[d], ph), ur, ui);
+                expm2pi_rev(fma(f, cv.dtau[d], ph) * (1.0 / kPhasorN), ur, ui);
                 ur *= ar;
                 ui *= ar;
                 const unsigned o = (unsigned)(d * npad) + pos;

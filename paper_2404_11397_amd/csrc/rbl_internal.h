@@ -15,11 +15,12 @@ constexpr int kPhasorN = 512;  // entries of the unit-phasor table exp(2 pi i k 
 
 // Per-chain record produced by the setup kernels (FP64, 64 doubles, 512 B).
 //   [0]        status: 1 valid, 0 outside the physical domain, NaN if theta has a NaN
-//   [1..10]    dc_b  = c_b(theta) - c_b(theta0), TaylorF2 basis coefficients [rev]
+//   [1..10]    dc_b  = c_b(theta) - c_b(theta0), TaylorF2 basis coefficients, in table units
+//              (kPhasorN rev: an exact power-of-two scaling)
 //   [11..16]   likelihood setup: K_d = P_d G, (re, im) per detector;
 //              gradient setup:   P_d itself (the kernel forms K_d = P_d G), where
 //              P_d = C_d / C_d0 and G = (dL0/dL)(Mc/Mc0)^(5/6) exp(2i (phic - phic0)) exp(-2 pi i dc_const)
-//   [17..19]   dtau_d = (tc + dt_d) - (tc0 + dt_d0)  [s]
+//   [17..19]   dtau_d = (tc + dt_d) - (tc0 + dt_d0), times kPhasorN  [s]
 //   [20..21]   G (re, im)                 (gradient setup only)
 //   [22]       dL                         (gradient setup only)
 //   [24..52]   NrtParams<double> of the chain (IMRPhenomD_NRTidalv2 events; dc and the
@@ -111,6 +112,9 @@ struct EventDev {
     const double* scales;
     // [kPhasorN][2]: cos and sin of 2 pi k / kPhasorN (read into LDS by the likelihood kernels)
     const double* phasor;
+    // [kMaxDet]: M_d = sum_j mu_dj.  A TaylorF2 ratio has |r_dj| = |K_d| at every edge, so its
+    // quadratic term is sum_j mu_dj |r_dj|^2 = |K_d|^2 M_d.
+    const double* mu_sum;
 };
 
 // Mixed precision is used for a chain while the magnitude bound of its binned sum,

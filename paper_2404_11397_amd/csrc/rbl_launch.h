@@ -44,6 +44,7 @@ struct NodeArgs {
     double *g_re, *g_im, *mu, *xL, *xR;
     float *g_re32, *g_im32, *mu32, *xL32, *xR32;
     double* scales;
+    double* mu_sum;
 };
 
 struct FullArgs {

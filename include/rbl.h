@@ -139,12 +139,15 @@ int rbl_event_info(const rbl_event *ev, int32_t *n_det, int32_t *n_bins, int32_t
  * edges_out [n_bins + 1]. */
 int rbl_bin_edges(double f_low, double delta_f, int64_t n_freq, int32_t n_bins, int64_t *edges_out);
 
-/* Kernel timing for benchmarks.  While enabled, every rbl_loglike / rbl_loglike_grad /
- * rbl_loglike_full call records HIP events on its own stream around its setup kernel and
- * its main kernel.  rbl_profile_read waits for the recorded events, returns the summed
- * milliseconds of the main and setup kernels and the number of calls since the last read,
- * and resets the counters.  Not for concurrent use from several threads. */
-int rbl_profile_enable(int32_t on);
+/* Kernel timing for benchmarks.  With every = n > 0, the first and then every n-th
+ * rbl_loglike / rbl_loglike_grad / rbl_loglike_full call records HIP events on its own
+ * stream at the start and end of its setup kernel and of its main kernel (the runtime
+ * stamps the kernels themselves); every = 0 turns timing off.  Each timed call costs a
+ * few microseconds of device time, so a sampled rate disturbs a throughput run less.
+ * rbl_profile_read waits for the recorded events, returns the summed milliseconds of the
+ * main and setup kernels and the number of timed calls since the last read, and resets
+ * the counters.  RBL_EINVAL for every < 0.  Not for concurrent use from several threads. */
+int rbl_profile_enable(int32_t every);
 int rbl_profile_read(double *main_ms, double *setup_ms, int64_t *calls);
 /* Summed milliseconds of the summary-data pass (reference waveform on the grid and the
  * per-bin reductions) of the events created while profiling was enabled; resets. */

@@ -58,6 +58,8 @@ bool theta_in_domain(const double* t) {
 // Benchmark timing: the runtime records start / stop events at the setup kernel's and the
 // main kernel's own start and end (hipExtLaunchKernel), so the times are kernel durations.
 struct ProfState {
+    int32_t every = 0;   // 0: off; n: time every n-th call
+    int64_t calls = 0;   // calls seen while on
     bool on = false;
     std::vector<hipEvent_t> free_events;
     std::vector<std::array<hipEvent_t, 4>> pending;  // setup start, setup stop, main start, main stop
@@ -80,7 +82,7 @@ struct CallTimer {
     std::array<hipEvent_t, 4> ev{{nullptr, nullptr, nullptr, nullptr}};
     bool active = false;
     CallTimer() {
-        if (!g_prof.on) return;
+        if (!g_prof.on || (g_prof.calls++ % g_prof.every) != 0) return;
         for (auto& e : ev) e = g_prof.get();
         active = ev[0] && ev[1] && ev[2] && ev[3];
     }
@@ -93,8 +95,11 @@ struct CallTimer {
 
 }  // namespace
 
-extern "C" int rbl_profile_enable(int32_t on) {
-    g_prof.on = on != 0;
+extern "C" int rbl_profile_enable(int32_t every) {
+    if (every < 0) return fail(RBL_EINVAL, "rbl_profile_enable: every must be >= 0");
+    g_prof.on = every != 0;
+    g_prof.every = every;
+    g_prof.calls = 0;
     return RBL_OK;
 }
 
@@ -351,19 +356,15 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     na.f_low = ev->f_low;
     na.delta_f = ev->delta_f;
     na.summary = ev->d_summary;
-    na.node_f = node_block;
-    na.node_x = node_block + np;
-    na.node_ix = node_block + 2 * np;
-    na.node_lx = node_block + 3 * np;
-    na.g_re = node_block + 4 * np;
-    na.g_im = na.g_re + nd * np;
-    na.mu = na.g_im + nd * np;
+    na.node_fx = node_block;
+    na.node_il = node_block + 2 * np;
+    na.g = node_block + 4 * np;
+    na.mu = na.g + 2 * nd * np;
     na.xL = na.mu + nd * np;
     na.xR = na.xL + nd * np;
     na.scales = na.xR + nd * np;
-    na.g_re32 = (float*)(na.scales + 2 * kMaxDet);
-    na.g_im32 = na.g_re32 + nd * np;
-    na.mu32 = na.g_im32 + nd * np;
+    na.g32 = (float*)(na.scales + 2 * kMaxDet);
+    na.mu32 = na.g32 + 2 * nd * np;
     na.xL32 = na.mu32 + nd * np;
     na.xR32 = na.xL32 + nd * np;
     na.phi0 = na.scales + 2 * kMaxDet + np * 5 * nd / 2;  // after the FP32 tables (5 nd np floats)
@@ -407,17 +408,13 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     dv.n_freq = n;
     dv.f_low = ev->f_low;
     dv.delta_f = ev->delta_f;
-    dv.node_f = na.node_f;
-    dv.node_x = na.node_x;
-    dv.node_ix = na.node_ix;
-    dv.node_lx = na.node_lx;
-    dv.g_re = na.g_re;
-    dv.g_im = na.g_im;
+    dv.node_fx = na.node_fx;
+    dv.node_il = na.node_il;
+    dv.g = na.g;
     dv.mu = na.mu;
     dv.xL = na.xL;
     dv.xR = na.xR;
-    dv.g_re32 = na.g_re32;
-    dv.g_im32 = na.g_im32;
+    dv.g32 = na.g32;
     dv.mu32 = na.mu32;
     dv.xL32 = na.xL32;
     dv.xR32 = na.xR32;

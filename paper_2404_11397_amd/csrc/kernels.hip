@@ -391,10 +391,10 @@ __global__ void k_node_tables(NodeArgs a) {
         ix = 1.0 / x;
         lx = log(x);
     }
-    a.node_f[pos] = f;
-    a.node_x[pos] = x;
-    a.node_ix[pos] = ix;
-    a.node_lx[pos] = lx;
+    a.node_fx[2 * pos] = f;
+    a.node_fx[2 * pos + 1] = x;
+    a.node_il[2 * pos] = ix;
+    a.node_il[2 * pos + 1] = lx;
     if (a.ref.waveform == kWfNrtv2) {
         double phi0 = 0.0, a0 = 1.0;
         const double x578 = exp(5.78 * lx);
@@ -429,13 +429,13 @@ __global__ void k_node_tables(NodeArgs a) {
             }
         }
         const int64_t o = (int64_t)d * a.n_nodes_pad + pos;
-        a.g_re[o] = gre;
-        a.g_im[o] = gim;
+        a.g[2 * o] = gre;
+        a.g[2 * o + 1] = gim;
         a.mu[o] = mu;
         a.xL[o] = xl;
         a.xR[o] = xr;
-        a.g_re32[o] = (float)gre;
-        a.g_im32[o] = (float)gim;
+        a.g32[2 * o] = (float)gre;
+        a.g32[2 * o + 1] = (float)gim;
         a.mu32[o] = (float)mu;
         a.xL32[o] = (float)xl;
         a.xR32[o] = (float)xr;
@@ -450,7 +450,7 @@ __global__ __launch_bounds__(64) void k_event_scales(NodeArgs a) {
     double gs = 0.0, hs = 0.0, ms = 0.0;
     for (int j = lane; j < a.n_nodes_pad; j += 64) {
         const int64_t o = (int64_t)d * a.n_nodes_pad + j;
-        gs += sqrt(a.g_re[o] * a.g_re[o] + a.g_im[o] * a.g_im[o]);
+        gs += sqrt(a.g[2 * o] * a.g[2 * o] + a.g[2 * o + 1] * a.g[2 * o + 1]);
         hs += fabs(a.mu[o]) + fabs(a.xL[o]);
         ms += a.mu[o];
     }

@@ -59,10 +59,10 @@ __device__ inline void unit_phasor(double y, const double2*, float& c, float& s)
 
 template <class R>
 struct EdgeTab {
-    const R *gre, *gim, *mu, *xl;
+    const R *g, *mu, *xl;  // g: gamma as (re, im) pairs
 };
-__device__ inline EdgeTab<double> edge_tab(const EventDev& ev, double) { return {ev.g_re, ev.g_im, ev.mu, ev.xL}; }
-__device__ inline EdgeTab<float> edge_tab(const EventDev& ev, float) { return {ev.g_re32, ev.g_im32, ev.mu32, ev.xL32}; }
+__device__ inline EdgeTab<double> edge_tab(const EventDev& ev, double) { return {ev.g, ev.mu, ev.xL}; }
+__device__ inline EdgeTab<float> edge_tab(const EventDev& ev, float) { return {ev.g32, ev.mu32, ev.xL32}; }
 // xR_j = xL_{j+1}: the cross weight of the bin right of edge j
 __device__ inline const double* xr_tab(const EventDev& ev, double) { return ev.xR; }
 __device__ inline const float* xr_tab(const EventDev& ev, float) { return ev.xR32; }
@@ -79,6 +79,22 @@ __device__ inline void load_phasor_table(const EventDev& ev, double2* tab) {
 template <class T>
 __device__ inline T ld(const T* base, unsigned idx) {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(T));
+}
+// The idx-th (re, im) pair of an interleaved table.
+__device__ inline double2 ld2(const double* base, unsigned idx) {
+    return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(base) + idx * 16u);
+}
+__device__ inline float2 ld2(const float* base, unsigned idx) {
+    return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(base) + idx * 8u);
+}
+
+// One edge of the node table: f, x = f^(1/3), 1/x, ln x.
+struct Node {
+    double f, x, ix, lx;
+};
+__device__ inline Node ld_node(const EventDev& ev, unsigned pos) {
+    const double2 a = ld2(ev.node_fx, pos), b = ld2(ev.node_il, pos);
+    return {a.x, a.y, b.x, b.y};
 }
 
 // Per-chain values shared by the walks.  dc and dtau are in table units, as in the record.
@@ -107,17 +123,16 @@ __device__ inline bool use_mixed(const EventDev& ev, const ChainVals<ND>& cv) {
 //   TaylorF2:  sum_b dc_b B_b(x), ratio 1 (the Mc^(5/6) factor is in K);
 //   IMRPhenomD_NRTidalv2:  Phi(f; theta) - Phi0_j, ratio a(f; theta) / a0_j.
 template <int ND, int WF>
-__device__ inline void edge_phase(const EventDev& ev, const ChainVals<ND>& cv, unsigned pos, double f, double& dph,
+__device__ inline void edge_phase(const EventDev& ev, const ChainVals<ND>& cv, unsigned pos, const Node& n, double& dph,
                                   double& ar) {
-    const double x = ld(ev.node_x, pos), ix = ld(ev.node_ix, pos), lx = ld(ev.node_lx, pos);
     if (WF == kWfNrtv2) {
         double ph, a;
-        nrt_node(cv.np, f, x, ix, lx, ld(ev.node_x578, pos), true, ph, a);
+        nrt_node(cv.np, n.f, n.x, n.ix, n.lx, ld(ev.node_x578, pos), true, ph, a);
         dph = (ph - ld(ev.phi0, pos)) * (double)kPhasorN;
         ar = a * ld(ev.ia0, pos);
     } else {
         double bas[kTf2Basis];
-        tf2_basis(x, ix, lx, bas);
+        tf2_basis(n.x, n.ix, n.lx, bas);
         double ph = -0.0;
 #pragma unroll
         for (int b = 0; b < kTf2Basis; ++b) ph = fma(cv.dc[b], bas[b], ph);
@@ -145,9 +160,10 @@ __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, c
     double acc = 0.0;
     for (int k = 0; k < ev.L; ++k) {
         const unsigned pos = (unsigned)(k * 64 + lane);
-        const double f = ld(ev.node_f, pos);
+        const Node n = ld_node(ev, pos);
+        const double f = n.f;
         double bas[kTf2Basis];
-        tf2_basis(ld(ev.node_x, pos), ld(ev.node_ix, pos), ld(ev.node_lx, pos), bas);
+        tf2_basis(n.x, n.ix, n.lx, bas);
         double ph = -0.0;
 #pragma unroll
         for (int b = 0; b < kTf2Basis; ++b) ph = fma(cv.dc[b], bas[b], ph);
@@ -158,7 +174,8 @@ __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, c
             const R rre = kre[d] * cu - kim[d] * su;
             const R rim = kre[d] * su + kim[d] * cu;
             const unsigned o = (unsigned)(d * npad) + pos;
-            R t = ld(T.gre, o) * rre + ld(T.gim, o) * rim;
+            const auto g = ld2(T.g, o);
+            R t = g.x * rre + g.y * rim;
             if (k > 0) {
                 t = fma(R(0.5) * ld(T.xl, o), pre[d] * rre + pim[d] * rim, t);
             } else {
@@ -195,10 +212,10 @@ __device__ inline double tf2_quadratic(const EventDev& ev, const ChainVals<ND>& 
 template <int ND, class R>
 __device__ inline void nrt_ratio(const EventDev& ev, const ChainVals<ND>& cv, const double2* tab, unsigned pos,
                                  const R* kre, const R* kim, R* rre, R* rim, double& a, NrtShared* sh = nullptr) {
-    const double f = ld(ev.node_f, pos);
+    const Node n = ld_node(ev, pos);
+    const double f = n.f;
     double ph;
-    nrt_node(cv.np, f, ld(ev.node_x, pos), ld(ev.node_ix, pos), ld(ev.node_lx, pos), ld(ev.node_x578, pos), true, ph, a,
-             sh);
+    nrt_node(cv.np, f, n.x, n.ix, n.lx, ld(ev.node_x578, pos), true, ph, a, sh);
     const double dph = (ph - ld(ev.phi0, pos)) * (double)kPhasorN;
     const R ar = (R)(a * ld(ev.ia0, pos));
 #pragma unroll
@@ -233,7 +250,8 @@ __device__ inline double fwd_walk_natural(const EventDev& ev, const ChainVals<ND
         for (int d = 0; d < ND; ++d) {
             const R lre = left_neighbour(rre[d], pre[d]), lim = left_neighbour(rim[d], pim[d]);
             const unsigned o = (unsigned)(d * npad) + pos;
-            const R gr = ld(T.gre, o) * rre[d] + ld(T.gim, o) * rim[d];
+            const auto g = ld2(T.g, o);
+            const R gr = g.x * rre[d] + g.y * rim[d];
             const R h = fma(ld(T.xl, o), lre * rre[d] + lim * rim[d], -(ld(T.mu, o) * (rre[d] * rre[d] + rim[d] * rim[d])));
             acc += (double)fma(R(0.5), h, gr);
             pre[d] = rre[d];
@@ -324,7 +342,8 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, co
     }
     // halo edge: the last edge of lane - 1 (lane 0 has none; its first edge has xL = 0)
     const unsigned hpos = (unsigned)(lane > 0 ? (L - 1) * 64 + (lane - 1) : npad - 1);
-    double fp = ld(ev.node_f, hpos), xp = ld(ev.node_x, hpos), ixp = ld(ev.node_ix, hpos), lxp = ld(ev.node_lx, hpos);
+    const Node hn = ld_node(ev, hpos);
+    double fp = hn.f, xp = hn.x, ixp = hn.ix, lxp = hn.lx;
     {
         double bas[kTf2Basis];
         tf2_basis(xp, ixp, lxp, bas);
@@ -342,7 +361,8 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, co
     double qprev = 0.0;  // Im z of the previous edge without its right cross term (halo: not ours)
     for (int k = 0; k < L; ++k) {
         const unsigned pos = (unsigned)(k * 64 + lane);
-        const double f = ld(ev.node_f, pos), x = ld(ev.node_x, pos), ix = ld(ev.node_ix, pos), lx = ld(ev.node_lx, pos);
+        const Node n = ld_node(ev, pos);
+        const double f = n.f, x = n.x, ix = n.ix, lx = n.lx;
         double bas[kTf2Basis];
         tf2_basis(x, ix, lx, bas);
         double ph = -0.0;
@@ -357,7 +377,8 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, co
             const R rre = kre[d] * ur - kim[d] * ui;
             const R rim = kre[d] * ui + kim[d] * ur;
             const unsigned o = (unsigned)(d * npad) + pos;
-            const R gre = ld(T.gre, o), gim = ld(T.gim, o), xl = ld(T.xl, o);
+            const auto g = ld2(T.g, o);
+            const R gre = g.x, gim = g.y, xl = ld(T.xl, o);
             const R gr = gre * rre + gim * rim;
             const R zt = fma(xl, rpr[d] * rre + rpi[d] * rim, gr);
             const R imz = gre * rim - gim * rre;
@@ -420,7 +441,8 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
             for (int d = 0; d < ND; ++d) rnr[d] = rni[d] = R(0);
         }
         const unsigned pos = (unsigned)(k * 64 + lane);
-        const double f = ld(ev.node_f, pos);
+        const Node n = ld_node(ev, pos);
+        const double f = n.f;
         double wre = 0.0, wim = 0.0;
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
@@ -428,7 +450,8 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
             const R lre = left_neighbour(rre, rpr[d]), lim = left_neighbour(rim, rpi[d]);
             const R nre = right_neighbour(rre, rnr[d]), nim = right_neighbour(rim, rni[d]);
             const unsigned o = (unsigned)(d * npad) + pos;
-            const R gre = ld(T.gre, o), gim = ld(T.gim, o), mu = ld(T.mu, o);
+            const auto g = ld2(T.g, o);
+            const R gre = g.x, gim = g.y, mu = ld(T.mu, o);
             const R cl = R(0.5) * ld(T.xl, o), cr = R(0.5) * ld(xrt, o);
             G.acc += (double)(gre * rre + gim * rim);
             const R gbr = gre - mu * rre + cl * lre + cr * nre;
@@ -440,8 +463,7 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
             wre += zr;
             wim += zi;
         }
-        nrt_node_adjoint(cv.np, f, ld(ev.node_x, pos), ld(ev.node_ix, pos), ld(ev.node_lx, pos), ld(ev.node_x578, pos),
-                         scur, (2.0 * kPi) * wim, acur != 0.0 ? wre / acur : 0.0, G.sa);
+        nrt_node_adjoint(cv.np, f, n.x, n.ix, n.lx, ld(ev.node_x578, pos), scur, (2.0 * kPi) * wim, acur != 0.0 ? wre / acur : 0.0, G.sa);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             rpr[d] = rcr[d];
@@ -454,11 +476,12 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
     }
 }
 
-// Occupancy target: 3 waves per SIMD for TaylorF2 (the walk needs about 136 vector
-// registers; at 4 waves it would spill); 2 for NRTidalv2, whose 26 adjoint accumulators
-// and per-edge model would otherwise spill.
+// Occupancy target: at least 3 waves per SIMD for TaylorF2 in FP64 (the compiler fits the
+// walk in 128 registers, so 4 are resident), 4 for the mixed-precision TaylorF2 kernel
+// (measured faster than 3 despite a few spilled registers outside the walk's hot path), 2
+// for NRTidalv2, whose 26 adjoint accumulators and per-edge model would otherwise spill.
 template <int ND, bool MIXED, int WF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNrtv2 ? 2 : 3))) void k_loglike_grad(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNrtv2 ? 2 : (MIXED ? 4 : 3)))) void k_loglike_grad(
     EventDev ev, const double* __restrict__ recs, const double* __restrict__ jac, int64_t B,
     double* __restrict__ lnl, double* __restrict__ grad) {
     __shared__ double2 tab[kPhasorN];
@@ -537,16 +560,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNr
             double sr = 0.0, si = 0.0;
             for (int k = 0; k < ev.L; ++k) {
                 const unsigned pos = (unsigned)(k * 64 + lane);
-                const double f = ld(ev.node_f, pos);
+                const Node n = ld_node(ev, pos);
                 double ph, ar;
-                edge_phase<ND, WF>(ev, cv, pos, f, ph, ar);
+                edge_phase<ND, WF>(ev, cv, pos, n, ph, ar);
                 double ur, ui;
-                expm2pi_rev(fma(f, cv.dtau[d], ph) * (1.0 / kPhasorN), ur, ui);
+                expm2pi_rev(fma(n.f, cv.dtau[d], ph) * (1.0 / kPhasorN), ur, ui);
                 ur *= ar;
                 ui *= ar;
-                const unsigned o = (unsigned)(d * npad) + pos;
-                sr += ld(ev.g_re, o) * ur + ld(ev.g_im, o) * ui;
-                si += ld(ev.g_re, o) * ui - ld(ev.g_im, o) * ur;
+                const double2 g = ld2(ev.g, (unsigned)(d * npad) + pos);
+                sr += g.x * ur + g.y * ui;
+                si += g.x * ui - g.y * ur;
             }
             ZR[d] = wave_sum(sr);
             ZI[d] = wave_sum(si);

@@ -83,22 +83,20 @@ struct EventDev {
     int32_t waveform;
     int64_t n_freq;
     double f_low, delta_f;
-    // node tables, each [n_nodes_pad] (padding: f = 0, x = ix = 1, lx = 0)
-    const double* node_f;
-    const double* node_x;
-    const double* node_ix;
-    const double* node_lx;
-    // per (det, node) tables, [n_det][n_nodes_pad]: gamma (re, im), mu, and the cross
+    // node tables [n_nodes_pad][2]: (f, x = f^(1/3)) and (1/x, ln x) (padding: f = 0,
+    // x = 1/x = 1, ln x = 0); a wavefront reads a step's four columns with two contiguous
+    // 16-byte-per-lane loads
+    const double* node_fx;
+    const double* node_il;
+    // per (det, node) tables, [n_det][n_nodes_pad]: gamma ([2]: re, im), mu, and the cross
     // coefficients xL_j = -nu(bin j-1), xR_j = -nu(bin j) = xL_{j+1}: the weights of
     // Re(r_{j-1} r_j*) and Re(r_j r_{j+1}*) in 2 lnL
-    const double* g_re;
-    const double* g_im;
+    const double* g;
     const double* mu;
     const double* xL;
     const double* xR;
     // FP32 copies for the mixed-precision kernels
-    const float* g_re32;
-    const float* g_im32;
+    const float* g32;
     const float* mu32;
     const float* xL32;
     const float* xR32;

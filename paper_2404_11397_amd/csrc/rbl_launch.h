@@ -40,9 +40,9 @@ struct NodeArgs {
     const int64_t* edges;
     double f_low, delta_f;
     const double* summary;  // [n_det][n_bins][7]
-    double *node_f, *node_x, *node_ix, *node_lx;
-    double *g_re, *g_im, *mu, *xL, *xR;
-    float *g_re32, *g_im32, *mu32, *xL32, *xR32;
+    double *node_fx, *node_il;  // [n_nodes_pad][2]
+    double *g, *mu, *xL, *xR;  // g: [n_det][n_nodes_pad][2]
+    float *g32, *mu32, *xL32, *xR32;
     double* scales;
     double* mu_sum;
 };

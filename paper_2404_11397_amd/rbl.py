@@ -36,13 +36,14 @@ def _host_f64(x, shape=None):
     return a
 
 
-def profile_enable(on=True):
-    """Record HIP events around the library's kernels (benchmark timing)."""
-    check(_lib.lib().rbl_profile_enable(int(bool(on))))
+def profile_enable(on=True, every=1):
+    """Record HIP events around the library's kernels (benchmark timing) on the first and
+    every `every`-th likelihood call; on=False turns timing off."""
+    check(_lib.lib().rbl_profile_enable(int(every) if on else 0))
 
 
 def profile_read():
-    """(main-kernel ms, setup-kernel ms, calls) summed since the last read."""
+    """(main-kernel ms, setup-kernel ms, timed calls) summed since the last read."""
     m, s, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
     check(_lib.lib().rbl_profile_read(ctypes.byref(m), ctypes.byref(s), ctypes.byref(n)))
     return m.value, s.value, n.value

@@ -97,6 +97,16 @@ def test_null_arguments():
     assert lib.rbl_workspace_bytes(None, 10, 0) == 0
 
 
+def test_profile_sampling_arguments():
+    lib = _lib().lib()
+    assert lib.rbl_profile_enable(-1) == -1
+    assert lib.rbl_profile_enable(8) == 0
+    assert lib.rbl_profile_enable(0) == 0
+    m, s, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    assert lib.rbl_profile_read(ctypes.byref(m), ctypes.byref(s), ctypes.byref(n)) == 0
+    assert n.value == 0
+
+
 def test_server_argument_errors_without_gpu():
     """Argument checks of the server API are synchronous and need no device."""
     import ctypes

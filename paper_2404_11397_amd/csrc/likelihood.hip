@@ -533,22 +533,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNr
             grad_walk<ND, double>(ev, cv, tab, lane, G);
     }
 
-    // Wave reductions.  Z'_d = Z_d / K_d is the gradient with respect to K_d.
-    double acc = wave_sum(G.acc);
+    // Wave reductions of all accumulators at once.  Z'_d = Z_d / K_d is the gradient with
+    // respect to K_d.
+    constexpr int NV = (1 + NA + 3 * ND + 3) / 4 * 4;
+    double part[NV], tot[NV];
+    part[0] = G.acc;
+#pragma unroll
+    for (int b = 0; b < NA; ++b) part[1 + b] = G.sa[b];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        part[1 + NA + d] = G.zr[d];
+        part[1 + NA + ND + d] = G.zi[d];
+        part[1 + NA + 2 * ND + d] = G.ta[d];
+    }
+#pragma unroll
+    for (int i = 1 + NA + 3 * ND; i < NV; ++i) part[i] = 0.0;
+    wave_sum_n<NV>(part, tot);
+    double acc = tot[0];
     double A[NA], ZR[ND], ZI[ND], Tt[ND];
     constexpr double kAdjScale = WF == kWfNrtv2 ? 1.0 : 2.0 * kPi;  // NRTidalv2 adjoints include 2 pi
 #pragma unroll
-    for (int b = 0; b < NA; ++b) A[b] = kAdjScale * wave_sum(G.sa[b]);
+    for (int b = 0; b < NA; ++b) A[b] = kAdjScale * tot[1 + b];
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         const double k2 = cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d];
-        double zre = wave_sum(G.zr[d]);
+        double zre = tot[1 + NA + d];
         if constexpr (WF != kWfNrtv2) zre = fma(-k2, ev.mu_sum[d], zre);
-        const double zim = wave_sum(G.zi[d]);
+        const double zim = tot[1 + NA + ND + d];
         acc += zre;
         ZR[d] = (zre * cv.kre[d] + zim * cv.kim[d]) / k2;
         ZI[d] = (zim * cv.kre[d] - zre * cv.kim[d]) / k2;
-        Tt[d] = 2.0 * kPi * wave_sum(G.ta[d]);
+        Tt[d] = 2.0 * kPi * tot[1 + NA + 2 * ND + d];
     }
     acc *= 0.5;  // lnL = (sum_d Re Z_d + sum Re(gamma r*)) / 2
     if (zero_k) {

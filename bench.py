@@ -181,12 +181,17 @@ KERNEL_SOURCES = ("likelihood.hip", "kernels.hip", "rbl_launch.h", "rbl_internal
 
 
 def kernel_source_hash():
-    """sha256 over the kernel sources: counters taken on other sources do not apply."""
+    """sha256 over the code of the kernel sources (line comments and blank lines removed, so
+    that a comment edit keeps the hash): counters taken on other code do not apply."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2404_11397_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2404_11397_amd", "csrc", f), encoding="utf-8") as fh:
+            for line in fh:
+                code = re.sub(r"\s*//.*$", "", line.rstrip("\n")).rstrip()
+                if code:
+                    h.update(code.encode("utf-8") + b"\n")
     return h.hexdigest()[:16]
 
 

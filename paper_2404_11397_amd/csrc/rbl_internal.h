@@ -118,8 +118,8 @@ struct EventDev {
 // Mixed precision is used for a chain while the magnitude bound of its binned sum,
 // M = sum_d |K_d| Gs_d + |K_d|^2 Hs_d, stays below this value; larger chains take the
 // FP64 path.  Measured on the 3-detector TaylorF2 workload (1024 chains, all forced to
-// the mixed path), the mixed-path error stayed below 4.1e-8 M in every range of M from
-// 1e3 to 1e7, so M <= 5e4 keeps it under 2.1e-3, five times inside the 1e-2 bound.
+// the mixed path), the mixed-path error stayed below 2.2e-8 M in every range of M from
+// 1e3 to 1e7, so M <= 5e4 keeps it under 1.1e-3, nine times inside the 1e-2 bound.
 constexpr double kMixedScaleMax = 5.0e4;
 
 }  // namespace rbl

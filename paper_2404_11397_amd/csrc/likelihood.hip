@@ -328,7 +328,9 @@ struct GradAcc {
     double sa[NA];  // TaylorF2: S_b (basis);  IMRPhenomD_NRTidalv2: adjoints of the node parameters
 };
 
-template <int ND, class R>
+// UNROLL2: two edges per loop iteration (the LDS-table kernel, which then keeps its loop
+// state in registers without copies; measured faster there, not with global tables).
+template <int ND, class R, bool UNROLL2 = false>
 __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, const double2* tab, int lane,
                                  GradAcc<ND, kTf2Basis>& G) {
     const EdgeTab<R> T = edge_tab(ev, R(0));
@@ -359,7 +361,7 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, co
         }
     }
     double qprev = 0.0;  // Im z of the previous edge without its right cross term (halo: not ours)
-    for (int k = 0; k < L; ++k) {
+    auto step = [&](int k) {
         const unsigned pos = (unsigned)(k * 64 + lane);
         const Node n = ld_node(ev, pos);
         const double f = n.f, x = n.x, ix = n.ix, lx = n.lx;
@@ -401,6 +403,12 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, co
         }
         qprev = fma(0.5, p2, qz);
         fp = f; xp = x; ixp = ix; lxp = lx;
+    };
+    if constexpr (UNROLL2) {
+#pragma unroll 2
+        for (int k = 0; k < L; ++k) step(k);
+    } else {
+        for (int k = 0; k < L; ++k) step(k);
     }
     double bp[kTf2Basis];
     tf2_basis(xp, ixp, lxp, bp);
@@ -476,18 +484,56 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
     }
 }
 
+// TaylorF2 edge tables staged in LDS, shared by the workgroup's chains: the node pairs, the
+// gamma pairs and x_L of the first ND detectors (npad (4 + 3 ND) doubles); the walk then
+// reads them with LDS loads instead of vector-memory loads.  ev's pointers are redirected.
+template <int ND>
+__device__ inline void stage_edge_tables(EventDev& ev, double* lds) {
+    const int np = ev.n_nodes_pad;
+    double* fx = lds;
+    double* il = fx + 2 * np;
+    double* g = il + 2 * np;
+    double* xl = g + 2 * ND * np;
+    const double2* sfx = reinterpret_cast<const double2*>(ev.node_fx);
+    const double2* sil = reinterpret_cast<const double2*>(ev.node_il);
+    const double2* sg = reinterpret_cast<const double2*>(ev.g);
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        reinterpret_cast<double2*>(fx)[i] = sfx[i];
+        reinterpret_cast<double2*>(il)[i] = sil[i];
+    }
+    for (int i = threadIdx.x; i < ND * np; i += blockDim.x) {
+        reinterpret_cast<double2*>(g)[i] = sg[i];
+        xl[i] = ev.xL[i];
+    }
+    __syncthreads();
+    ev.node_fx = fx;
+    ev.node_il = il;
+    ev.g = g;
+    ev.xL = xl;
+}
+// LDS bytes of the staged tables.
+inline size_t staged_table_bytes(int nd, int np) { return sizeof(double) * (size_t)np * (4 + 3 * (size_t)nd); }
+constexpr size_t kStageMaxBytes = 56 * 1024;  // with the 8 KB phasor table: two workgroups per CU
+constexpr int kStageChains = 8;               // chains (wavefronts) per workgroup sharing the staged tables
+
 // Occupancy target: at least 3 waves per SIMD for TaylorF2 in FP64 (the compiler fits the
-// walk in 128 registers, so 4 are resident), 4 for the mixed-precision TaylorF2 kernel
+// global-table walk in 128 registers, so 4 are resident; the LDS-table walk, unrolled by two,
+// takes 149 and runs one 8-wave workgroup per CU, which measured as fast as two), 4 for the
+// mixed-precision TaylorF2 kernel
 // (measured faster than 3 despite a few spilled registers outside the walk's hot path), 2
 // for NRTidalv2, whose 26 adjoint accumulators and per-edge model would otherwise spill.
-template <int ND, bool MIXED, int WF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNrtv2 ? 2 : (MIXED ? 4 : 3)))) void k_loglike_grad(
+template <int ND, bool MIXED, int WF, bool LT = false>
+__global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu_waves_per_eu(WF == kWfNrtv2 ? 2 : (MIXED ? 4 : 3)))) void k_loglike_grad(
     EventDev ev, const double* __restrict__ recs, const double* __restrict__ jac, int64_t B,
     double* __restrict__ lnl, double* __restrict__ grad) {
     __shared__ double2 tab[kPhasorN];
     load_phasor_table(ev, tab);
+    if constexpr (LT) {
+        extern __shared__ double lds_tables[];
+        stage_edge_tables<ND>(ev, lds_tables);
+    }
     const int lane = threadIdx.x & 63;
-    const int64_t chain = (int64_t)blockIdx.x * 4 + wave_id();
+    const int64_t chain = (int64_t)blockIdx.x * (LT ? kStageChains : 4) + wave_id();
     if (chain >= B) return;
     const double* rec = recs + chain * kRecStride;
     const double status = rec[kRecStatus];
@@ -530,7 +576,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WF == kWfNr
         if (MIXED && use_mixed<ND>(ev, cv))
             grad_walk<ND, float>(ev, cv, tab, lane, G);
         else
-            grad_walk<ND, double>(ev, cv, tab, lane, G);
+            grad_walk<ND, double, LT>(ev, cv, tab, lane, G);
     }
 
     // Wave reductions of all accumulators at once.  Z'_d = Z_d / K_d is the gradient with
@@ -680,9 +726,14 @@ static void grad_nd(const EventDev& ev, const double* rec, const double* jac, in
             launch_k(k_loglike_grad<ND, false, kWfNrtv2>, dim3(grid), dim3(256), s, kt, ev, rec, jac, B,
                                lnl, grad);
     } else {
+        const size_t lb = staged_table_bytes(ND, ev.n_nodes_pad);
         if (mixed)
             launch_k(k_loglike_grad<ND, true, kWfTaylorF2>, dim3(grid), dim3(256), s, kt, ev, rec, jac,
                                B, lnl, grad);
+        else if (lb <= kStageMaxBytes)
+            launch_k_lds(k_loglike_grad<ND, false, kWfTaylorF2, true>,
+                         dim3((unsigned)((B + kStageChains - 1) / kStageChains)), dim3(64 * kStageChains), lb,
+                         s, kt, ev, rec, jac, B, lnl, grad);
         else
             launch_k(k_loglike_grad<ND, false, kWfTaylorF2>, dim3(grid), dim3(256), s, kt, ev, rec, jac,
                                B, lnl, grad);

@@ -70,6 +70,14 @@ inline void launch_k(F kernel, dim3 grid, dim3 block, hipStream_t s, KTime kt, A
     else
         hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
 }
+// The same with dynamic LDS bytes.
+template <typename F, typename... Args>
+inline void launch_k_lds(F kernel, dim3 grid, dim3 block, size_t lds_bytes, hipStream_t s, KTime kt, Args... args) {
+    if (kt.start || kt.stop)
+        hipExtLaunchKernelGGL(kernel, grid, block, lds_bytes, s, kt.start, kt.stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds_bytes, s, args...);
+}
 
 hipError_t launch_ref_setup(const double* theta_host, const Network& net, int32_t waveform, RefConsts* out_dev,
                             hipStream_t s);

@@ -88,6 +88,16 @@ template <int N> __host__ __device__ inline Dual<N> lift(const Dual<N>& a, doubl
 
 // Scalar overloads so that templated code works for T = double and T = Dual<N>.
 __host__ __device__ inline double val(double x) { return x; }
+
+// 1/b for a finite, normal, nonzero b to about one ulp: the hardware reciprocal estimate
+// refined by two Newton steps (the IEEE division sequence costs about twice as much).
+__device__ inline double rcp_nr(double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    return fma(r, e, r);
+}
 template <int N> __host__ __device__ inline double val(const Dual<N>& x) { return x.v; }
 
 __host__ __device__ inline double dsin(double x) { return sin(x); }

@@ -226,10 +226,10 @@ __device__ inline void nrt_node(const NrtParams<double>& p, double f, double x, 
     } else {
         const double lnmf = p.lnms + 3.0 * lx;
         if (mf < p.f2) {
-            const double im = 1.0 / mf;
+            const double im = rcp_nr(mf);
             ph = p.b[0] + p.b[1] * mf + p.b[2] * lnmf - p.b[3] * (im * im * im) * (1.0 / 3.0);
         } else {
-            ph = p.a[0] + p.a[1] * mf - p.a[2] / mf + (4.0 / 3.0) * p.a[3] * exp(0.75 * lnmf);
+            ph = p.a[0] + p.a[1] * mf - p.a[2] * rcp_nr(mf) + (4.0 / 3.0) * p.a[3] * exp(0.75 * lnmf);
         }
     }
     const double sx = p.s * x;
@@ -237,11 +237,11 @@ __device__ inline void nrt_node(const NrtParams<double>& p, double f, double x, 
     const double xt2 = xt * xt;
     const double num = 1.0 + kTn1 * xt + kTn32 * xt * sx + kTn2 * xt2 + kTn52 * xt2 * sx + kTn3 * xt2 * xt;
     const double den = 1.0 + kTd1 * xt + kTd32 * xt * sx + kTd2 * xt2;
-    const double iden = 1.0 / den;
+    const double iden = rcp_nr(den);
     const double rat = num * iden;
     phi = ph + p.tp * xt2 * sx * rat;
-    const double app = mf < p.fpk ? 1.0 : exp(-(mf - p.fpk) / p.fdp);
-    const double idd = 1.0 / (1.0 + 13477.8 * xt2 * xt2);
+    const double app = mf < p.fpk ? 1.0 : exp(-(mf - p.fpk) * rcp_nr(p.fdp));
+    const double idd = rcp_nr(1.0 + 13477.8 * xt2 * xt2);
     const double at = p.m9k * (xt2 * xt2 * xt) * (1.0 + (449.0 / 108.0) * xt + (22672.0 / 9.0) * (p.s578 * x578)) * idd;
     a = app + at;
     if (sh) *sh = NrtShared{rat, iden, idd};
@@ -251,9 +251,9 @@ __device__ inline void nrt_node(const NrtParams<double>& p, double f, double x, 
             a = 0.0;
         } else if (f > p.fm) {
             const double wd = fe - p.fm;
-            double z = wd / (f - p.fm) + wd / (f - fe);
+            double z = wd * rcp_nr(f - p.fm) + wd * rcp_nr(f - fe);
             z = fmin(fmax(z, -700.0), 700.0);
-            a *= 1.0 - 1.0 / (exp(z) + 1.0);
+            a *= 1.0 - rcp_nr(exp(z) + 1.0);
         }
     }
 }
@@ -284,7 +284,7 @@ __device__ inline void nrt_node_adjoint(const NrtParams<double>& p, double f, do
         acc[kAdjCc] += gphi;
     } else {
         const double lnmf = p.lnms + 3.0 * lx;
-        const double im = 1.0 / mf;
+        const double im = rcp_nr(mf);
         if (mf < p.f2) {
             const double im3 = im * im * im;
             acc[kAdjB + 0] += gphi;
@@ -321,12 +321,12 @@ __device__ inline void nrt_node_adjoint(const NrtParams<double>& p, double f, do
         w = 0.0;
     } else if (f > p.fm) {
         const double wd = fe - p.fm;
-        const double u1 = 1.0 / (f - p.fm), u2 = 1.0 / (f - fe);
+        const double u1 = rcp_nr(f - p.fm), u2 = rcp_nr(f - fe);
         double z = wd * u1 + wd * u2;
         const bool clip = z > 700.0 || z < -700.0;
         z = fmin(fmax(z, -700.0), 700.0);
         const double ez = exp(z);
-        w = 1.0 - 1.0 / (ez + 1.0);
+        w = 1.0 - rcp_nr(ez + 1.0);
         if (!clip) {
             const double dz = 0.2 * u1 + wd * u1 * u1 + 0.2 * u2 + 1.2 * wd * u2 * u2;
             dw = w * (1.0 - w) * dz;
@@ -335,7 +335,7 @@ __device__ inline void nrt_node_adjoint(const NrtParams<double>& p, double f, do
     const double gA = ga * w;  // d lnL / d(a_pp + a_T)
     double app = 1.0;
     if (mf >= p.fpk) {
-        const double id = 1.0 / p.fdp;
+        const double id = rcp_nr(p.fdp);
         app = exp(-(mf - p.fpk) * id);
         const double g = gA * app * id;
         acc[kAdjMs] = fma(-g, f, acc[kAdjMs]);

@@ -210,12 +210,13 @@ __device__ inline double tf2_quadratic(const EventDev& ev, const ChainVals<ND>& 
 // The left neighbour of an edge is the previous lane, or for lane 0 the last lane of
 // the previous step (a wave-uniform carry).
 template <int ND, class R>
-__device__ inline void nrt_ratio(const EventDev& ev, const ChainVals<ND>& cv, const double2* tab, unsigned pos,
+__device__ inline void nrt_ratio(const EventDev& ev, const ChainVals<ND>& cv, const NrtParams<double>& np,
+                                 const double2* tab, unsigned pos,
                                  const R* kre, const R* kim, R* rre, R* rim, double& a, NrtShared* sh = nullptr) {
     const Node n = ld_node(ev, pos);
     const double f = n.f;
     double ph;
-    nrt_node(cv.np, f, n.x, n.ix, n.lx, ld(ev.node_x578, pos), true, ph, a, sh);
+    nrt_node(np, f, n.x, n.ix, n.lx, ld(ev.node_x578, pos), true, ph, a, sh);
     const double dph = (ph - ld(ev.phi0, pos)) * (double)kPhasorN;
     const R ar = (R)(a * ld(ev.ia0, pos));
 #pragma unroll
@@ -245,7 +246,7 @@ __device__ inline double fwd_walk_natural(const EventDev& ev, const ChainVals<ND
         const unsigned pos = (unsigned)(k * 64 + lane);
         R rre[ND], rim[ND];
         double a;
-        nrt_ratio<ND, R>(ev, cv, tab, pos, kre, kim, rre, rim, a);
+        nrt_ratio<ND, R>(ev, cv, cv.np, tab, pos, kre, kim, rre, rim, a);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const R lre = left_neighbour(rre[d], pre[d]), lim = left_neighbour(rim[d], pim[d]);
@@ -425,8 +426,8 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, co
 // step / lane 0 of the next step) and W_j is complete when its adjoint runs.  The right
 // cross coefficient c_{j+1} = xR_j / 2 is read from the edge's own table.
 template <int ND, class R>
-__device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv, const double2* tab, int lane,
-                                     GradAcc<ND, kNrtAdj>& G) {
+__device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv, const NrtParams<double>& np,
+                                     const double2* tab, int lane, GradAcc<ND, kNrtAdj>& G) {
     const EdgeTab<R> T = edge_tab(ev, R(0));
     const R* xrt = xr_tab(ev, R(0));
     const int npad = ev.n_nodes_pad;
@@ -440,10 +441,10 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
     }
     double acur, anext = 0.0;
     NrtShared scur, snext{0.0, 0.0, 0.0};
-    nrt_ratio<ND, R>(ev, cv, tab, lane, kre, kim, rcr, rci, acur, &scur);
+    nrt_ratio<ND, R>(ev, cv, np, tab, lane, kre, kim, rcr, rci, acur, &scur);
     for (int k = 0; k < L; ++k) {
         if (k + 1 < L) {
-            nrt_ratio<ND, R>(ev, cv, tab, (k + 1) * 64 + lane, kre, kim, rnr, rni, anext, &snext);
+            nrt_ratio<ND, R>(ev, cv, np, tab, (k + 1) * 64 + lane, kre, kim, rnr, rni, anext, &snext);
         } else {
 #pragma unroll
             for (int d = 0; d < ND; ++d) rnr[d] = rni[d] = R(0);
@@ -471,7 +472,7 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
             wre += zr;
             wim += zi;
         }
-        nrt_node_adjoint(cv.np, f, n.x, n.ix, n.lx, ld(ev.node_x578, pos), scur, (2.0 * kPi) * wim, acur != 0.0 ? wre / acur : 0.0, G.sa);
+        nrt_node_adjoint(np, f, n.x, n.ix, n.lx, ld(ev.node_x578, pos), scur, (2.0 * kPi) * wim, acur != 0.0 ? wre / acur : 0.0, G.sa);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             rpr[d] = rcr[d];
@@ -542,6 +543,16 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
         if (lane < 13) grad[chain * 13 + lane] = (status == 0.0) ? 0.0 : __builtin_nan("");
         return;
     }
+    // IMRPhenomD_NRTidalv2: the chain's 29 node parameters are read by the walk from LDS
+    // (uniform-address loads) rather than held in scalar registers, which would overflow
+    // into per-step spill reloads next to the table bases, K_d and the delays.
+    __shared__ NrtParams<double> snp[4];
+    if constexpr (WF == kWfNrtv2) {
+        if (lane < kNrtParams) reinterpret_cast<double*>(&snp[wave_id()])[lane] = rec[kRecNrt + lane];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     constexpr int NA = WF == kWfNrtv2 ? kNrtAdj : kTf2Basis;
     ChainVals<ND> cv;
 #pragma unroll
@@ -569,9 +580,9 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
     for (int b = 0; b < NA; ++b) G.sa[b] = 0.0;
     if constexpr (WF == kWfNrtv2) {
         if (MIXED && use_mixed<ND>(ev, cv))
-            grad_walk_nrt<ND, float>(ev, cv, tab, lane, G);
+            grad_walk_nrt<ND, float>(ev, cv, snp[wave_id()], tab, lane, G);
         else
-            grad_walk_nrt<ND, double>(ev, cv, tab, lane, G);
+            grad_walk_nrt<ND, double>(ev, cv, snp[wave_id()], tab, lane, G);
     } else {
         if (MIXED && use_mixed<ND>(ev, cv))
             grad_walk<ND, float>(ev, cv, tab, lane, G);

@@ -262,13 +262,49 @@ __device__ inline double fwd_walk_natural(const EventDev& ev, const ChainVals<ND
     return acc;
 }
 
-template <int ND, bool MIXED, int WF>
-__global__ __launch_bounds__(256) void k_loglike_fwd(EventDev ev, const double* __restrict__ recs, int64_t B,
+// TaylorF2 edge tables staged in LDS, shared by the workgroup's chains: the node pairs, the
+// gamma pairs and x_L of the first ND detectors (npad (4 + 3 ND) doubles); the walk then
+// reads them with LDS loads instead of vector-memory loads.  ev's pointers are redirected.
+template <int ND>
+__device__ inline void stage_edge_tables(EventDev& ev, double* lds) {
+    const int np = ev.n_nodes_pad;
+    double* fx = lds;
+    double* il = fx + 2 * np;
+    double* g = il + 2 * np;
+    double* xl = g + 2 * ND * np;
+    const double2* sfx = reinterpret_cast<const double2*>(ev.node_fx);
+    const double2* sil = reinterpret_cast<const double2*>(ev.node_il);
+    const double2* sg = reinterpret_cast<const double2*>(ev.g);
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        reinterpret_cast<double2*>(fx)[i] = sfx[i];
+        reinterpret_cast<double2*>(il)[i] = sil[i];
+    }
+    for (int i = threadIdx.x; i < ND * np; i += blockDim.x) {
+        reinterpret_cast<double2*>(g)[i] = sg[i];
+        xl[i] = ev.xL[i];
+    }
+    __syncthreads();
+    ev.node_fx = fx;
+    ev.node_il = il;
+    ev.g = g;
+    ev.xL = xl;
+}
+// LDS bytes of the staged tables.
+inline size_t staged_table_bytes(int nd, int np) { return sizeof(double) * (size_t)np * (4 + 3 * (size_t)nd); }
+constexpr size_t kStageMaxBytes = 56 * 1024;  // with the 8 KB phasor table: two workgroups per CU
+constexpr int kStageChains = 8;               // chains (wavefronts) per workgroup sharing the staged tables
+
+template <int ND, bool MIXED, int WF, bool LT = false>
+__global__ __launch_bounds__(LT ? 64 * kStageChains : 256) void k_loglike_fwd(EventDev ev, const double* __restrict__ recs, int64_t B,
                                                      double* __restrict__ lnl) {
     __shared__ double2 tab[kPhasorN];
     load_phasor_table(ev, tab);
+    if constexpr (LT) {
+        extern __shared__ double lds_tables[];
+        stage_edge_tables<ND>(ev, lds_tables);
+    }
     const int lane = threadIdx.x & 63;
-    const int64_t chain = (int64_t)blockIdx.x * 4 + wave_id();
+    const int64_t chain = (int64_t)blockIdx.x * (LT ? kStageChains : 4) + wave_id();
     if (chain >= B) return;
     const double* rec = recs + chain * kRecStride;
     const double status = rec[kRecStatus];
@@ -485,38 +521,6 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
     }
 }
 
-// TaylorF2 edge tables staged in LDS, shared by the workgroup's chains: the node pairs, the
-// gamma pairs and x_L of the first ND detectors (npad (4 + 3 ND) doubles); the walk then
-// reads them with LDS loads instead of vector-memory loads.  ev's pointers are redirected.
-template <int ND>
-__device__ inline void stage_edge_tables(EventDev& ev, double* lds) {
-    const int np = ev.n_nodes_pad;
-    double* fx = lds;
-    double* il = fx + 2 * np;
-    double* g = il + 2 * np;
-    double* xl = g + 2 * ND * np;
-    const double2* sfx = reinterpret_cast<const double2*>(ev.node_fx);
-    const double2* sil = reinterpret_cast<const double2*>(ev.node_il);
-    const double2* sg = reinterpret_cast<const double2*>(ev.g);
-    for (int i = threadIdx.x; i < np; i += blockDim.x) {
-        reinterpret_cast<double2*>(fx)[i] = sfx[i];
-        reinterpret_cast<double2*>(il)[i] = sil[i];
-    }
-    for (int i = threadIdx.x; i < ND * np; i += blockDim.x) {
-        reinterpret_cast<double2*>(g)[i] = sg[i];
-        xl[i] = ev.xL[i];
-    }
-    __syncthreads();
-    ev.node_fx = fx;
-    ev.node_il = il;
-    ev.g = g;
-    ev.xL = xl;
-}
-// LDS bytes of the staged tables.
-inline size_t staged_table_bytes(int nd, int np) { return sizeof(double) * (size_t)np * (4 + 3 * (size_t)nd); }
-constexpr size_t kStageMaxBytes = 56 * 1024;  // with the 8 KB phasor table: two workgroups per CU
-constexpr int kStageChains = 8;               // chains (wavefronts) per workgroup sharing the staged tables
-
 // Occupancy target: at least 3 waves per SIMD for TaylorF2 in FP64 (the compiler fits the
 // global-table walk in 128 registers, so 4 are resident; the LDS-table walk, unrolled by two,
 // takes 149 and runs one 8-wave workgroup per CU, which measured as fast as two), 4 for the
@@ -708,8 +712,13 @@ static void fwd_nd(const EventDev& ev, const double* rec, int64_t B, int mixed, 
         else
             launch_k(k_loglike_fwd<ND, false, kWfNrtv2>, dim3(grid), dim3(256), s, kt, ev, rec, B, lnl);
     } else {
+        const size_t lb = staged_table_bytes(ND, ev.n_nodes_pad);
         if (mixed)
             launch_k(k_loglike_fwd<ND, true, kWfTaylorF2>, dim3(grid), dim3(256), s, kt, ev, rec, B, lnl);
+        else if (lb <= kStageMaxBytes)
+            launch_k_lds(k_loglike_fwd<ND, false, kWfTaylorF2, true>,
+                         dim3((unsigned)((B + kStageChains - 1) / kStageChains)), dim3(64 * kStageChains), lb, s, kt,
+                         ev, rec, B, lnl);
         else
             launch_k(k_loglike_fwd<ND, false, kWfTaylorF2>, dim3(grid), dim3(256), s, kt, ev, rec, B, lnl);
     }

@@ -176,7 +176,7 @@ def calibrate_copy(torch, repeats=10):
             "kernels": ["runtime device copy", "elementwise y = x + 0"]}
 
 
-KERNEL_SOURCES = ("likelihood.hip", "kernels.hip", "rbl_launch.h", "rbl_internal.h", "rbl_wave.h", "rbl_math.h",
+KERNEL_SOURCES = ("likelihood.hip", "kernels.hip", "rbl_launch.h", "rbl_internal.h", "rbl_wave.h", "rbl_math.h", "rbl_phasor.h",
                   "rbl_physics.h", "rbl_nrtv2.h")
 
 

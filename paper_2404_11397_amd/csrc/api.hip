@@ -46,7 +46,7 @@ extern "C" int rbl_debug_inject_fault(int32_t kind, int32_t count) {
 
 namespace {
 
-constexpr int64_t kChunk = 128;     // grid points per summary work item
+constexpr int64_t kChunk = 256;     // grid points per summary work item (one workgroup)
 
 bool theta_in_domain(const double* t) {
     for (int i = 0; i < 13; ++i)
@@ -314,6 +314,19 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
         np * (4 + 5 * nd) + 2 * kMaxDet + np * 5 * nd / 2 + 2 * np + np / 2 + np + 2 * kPhasorN + kMaxDet;
     if (ev->mem.alloc((void**)&node_block, sizeof(double) * node_doubles) != hipSuccess)
         return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (node tables)"));
+    // the phasor table (used by the summary pass and the likelihood kernels) sits after the
+    // other node-block tables: cos and sin of 2 pi k / kPhasorN, evaluated in extended
+    // precision and rounded once
+    double* d_phasor = node_block + node_doubles - 2 * kPhasorN - kMaxDet;
+    std::vector<double> phasor(2 * kPhasorN);
+    for (int k = 0; k < kPhasorN; ++k) {
+        const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)kPhasorN;
+        phasor[2 * k] = (double)std::cos(a);
+        phasor[2 * k + 1] = (double)std::sin(a);
+    }
+    if ((e = hipMemcpyAsync(d_phasor, phasor.data(), sizeof(double) * 2 * kPhasorN, hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
+        return cleanup(hip_fail(e, "rbl_event_create: copy phasor table"));
 
     SummaryArgs sa{};
     sa.n_items = n_items;
@@ -326,6 +339,7 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     sa.data = d_data;
     sa.psd = d_psd;
     sa.partials = d_partials;
+    sa.phasor = d_phasor;
     sa.ref = ev->ref;
     sa.ref_taper = (desc->flags & RBL_REF_TAPER) ? 1 : 0;
     // benchmark timing: the two kernels' own durations, summed
@@ -371,18 +385,7 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     na.ia0 = na.phi0 + np;
     na.ia0_32 = (float*)(na.ia0 + np);
     na.node_x578 = na.ia0 + np + np / 2;
-    double* d_phasor = na.node_x578 + np;
     na.mu_sum = d_phasor + 2 * kPhasorN;
-    // cos and sin of 2 pi k / kPhasorN, evaluated in extended precision and rounded once
-    std::vector<double> phasor(2 * kPhasorN);
-    for (int k = 0; k < kPhasorN; ++k) {
-        const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)kPhasorN;
-        phasor[2 * k] = (double)std::cos(a);
-        phasor[2 * k + 1] = (double)std::sin(a);
-    }
-    if ((e = hipMemcpyAsync(d_phasor, phasor.data(), sizeof(double) * 2 * kPhasorN, hipMemcpyHostToDevice, s)) !=
-        hipSuccess)
-        return cleanup(hip_fail(e, "rbl_event_create: copy phasor table"));
     na.ref = ev->ref;
     na.ref_taper = (desc->flags & RBL_REF_TAPER) ? 1 : 0;
     int32_t* d_bad = nullptr;

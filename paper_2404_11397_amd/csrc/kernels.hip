@@ -3,7 +3,7 @@
 //  k_ref_setup      reference (fiducial) constants for theta0            [1 thread]
 //  k_chain_setup    per-chain record                                     [1 thread / chain]
 //  k_chain_setup_grad  record and partial derivatives (dual numbers)    [1 lane / (chain, tangent)]
-//  k_summary_items  summary-data partial sums over (bin, chunk) items    [1 wave / item]
+//  k_summary_items  summary-data partial sums over (bin, chunk) items    [1 workgroup / item]
 //  k_summary_reduce ordered sum of the partials of each bin              [1 thread / (det, bin, field)]
 //  k_node_tables    per-edge coefficient tables of the binned sum        [1 thread / node]
 //  (k_loglike_fwd and k_loglike_grad, the likelihood kernels, are in likelihood.hip)
@@ -12,6 +12,7 @@
 //
 // All reductions are in a fixed order, so results are bitwise reproducible.
 #include "rbl_launch.h"
+#include "rbl_phasor.h"
 #include "rbl_wave.h"
 
 namespace rbl {
@@ -258,15 +259,17 @@ __global__ __launch_bounds__(256) void k_chain_setup_grad(const double* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Summary data: one wavefront per item (a run of <= 128 grid points inside one bin, two
-// points per lane); the reference waveform is generated inline, once per point, and
-// projected onto every detector.  The loads of both points are issued before the
-// arithmetic.  Each lane's 7 ND partial sums are reduced across the wavefront through
-// LDS (lane t < 7 ND sums row t over the 64 lanes in lane order).  Partials: [item][det][7].
+// Summary data: one workgroup per item (a run of <= 256 grid points inside one bin, one
+// point per thread); the reference waveform is generated inline, once per point, and
+// projected onto every detector, with the unit phasors from the LDS table.  The 7 ND partial
+// sums are reduced across each wavefront (wave_sum_n) and the four wavefront totals added
+// in wave order, so the partials are bitwise reproducible.  Partials: [item][det][7].
+// (A last-item-per-bin reduction inside this kernel needs device-scope fences, which cost
+// far more here than the second kernel.)
 // ---------------------------------------------------------------------------
 template <int ND>
-__device__ inline void summary_point(const SummaryArgs& a, int64_t k, double fm, const double* dre, const double* dim,
-                                     const double* ps, double (&acc)[ND][7]) {
+__device__ inline void summary_point(const SummaryArgs& a, const double2* tab, int64_t k, double fm, const double* dre,
+                                     const double* dim, const double* ps, double (&acc)[ND][7]) {
     const RefConsts& ref = a.ref;
     const double w = 4.0 * a.delta_f;
     const double f = a.f_low + (double)k * a.delta_f;
@@ -289,7 +292,7 @@ __device__ inline void summary_point(const SummaryArgs& a, int64_t k, double fm,
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         double cu, su;
-        expm2pi_rev(fma(f, ref.tau0[d], phi), cu, su);
+        unit_phasor(fma(f, ref.tau0[d], phi) * (double)kPhasorN, tab, cu, su);
         const double hre = amp * (ref.h0fac_re[d] * cu - ref.h0fac_im[d] * su);
         const double him = amp * (ref.h0fac_re[d] * su + ref.h0fac_im[d] * cu);
         const double wk = w / ps[d];
@@ -309,50 +312,48 @@ __device__ inline void summary_point(const SummaryArgs& a, int64_t k, double fm,
 
 template <int ND>
 __global__ __launch_bounds__(256) void k_summary_items(SummaryArgs a) {
-    __shared__ double red[4][7 * ND][65];  // padded rows: no bank conflicts between lanes
-    const int lane = threadIdx.x & 63;
+    constexpr int NV = (7 * ND + 3) / 4 * 4;
+    __shared__ double2 tab[kPhasorN];
+    __shared__ double red[4][NV];
+    load_phasor_table(a.phasor, tab);
+    const int t = threadIdx.x;
+    const int lane = t & 63;
     const int wid = wave_id();
-    const int64_t item = (int64_t)blockIdx.x * 4 + wid;
-    if (item >= a.n_items) return;
+    const int64_t item = blockIdx.x;
     const SumItem it = a.items[item];
-    const int64_t k0 = it.start;
-    const int32_t cnt = it.count;
-    const double fm = it.fm;
     double acc[ND][7];
 #pragma unroll
     for (int d = 0; d < ND; ++d)
 #pragma unroll
         for (int j = 0; j < 7; ++j) acc[d][j] = 0.0;
-    for (int i0 = 0; i0 < cnt; i0 += 128) {
-        const bool v0 = i0 + lane < cnt, v1 = i0 + 64 + lane < cnt;
-        const int64_t ka = k0 + i0 + lane, kb = ka + 64;
-        double ra[ND], ia[ND], pa[ND], rb[ND], ib[ND], pb[ND];
+    if (t < it.count) {
+        const int64_t k = it.start + t;
+        double re[ND], im[ND], ps[ND];
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
-            const int64_t oa = (int64_t)d * a.n_freq + ka, ob = oa + 64;
-            ra[d] = v0 ? a.data[2 * oa] : 0.0;
-            ia[d] = v0 ? a.data[2 * oa + 1] : 0.0;
-            pa[d] = v0 ? a.psd[oa] : 1.0;
-            rb[d] = v1 ? a.data[2 * ob] : 0.0;
-            ib[d] = v1 ? a.data[2 * ob + 1] : 0.0;
-            pb[d] = v1 ? a.psd[ob] : 1.0;
+            const int64_t o = (int64_t)d * a.n_freq + k;
+            re[d] = a.data[2 * o];
+            im[d] = a.data[2 * o + 1];
+            ps[d] = a.psd[o];
         }
-        if (v0) summary_point<ND>(a, ka, fm, ra, ia, pa, acc);
-        if (v1) summary_point<ND>(a, kb, fm, rb, ib, pb, acc);
+        summary_point<ND>(a, tab, k, it.fm, re, im, ps, acc);
     }
+    double part[NV], tot[NV];
 #pragma unroll
     for (int d = 0; d < ND; ++d)
 #pragma unroll
-        for (int j = 0; j < 7; ++j) red[wid][d * 7 + j][lane] = acc[d][j];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (lane < 7 * ND) {
-        double s = 0.0;
-        for (int l = 0; l < 64; ++l) s += red[wid][lane][l];
-        a.partials[item * (7 * ND) + lane] = s;
+        for (int j = 0; j < 7; ++j) part[d * 7 + j] = acc[d][j];
+#pragma unroll
+    for (int i = 7 * ND; i < NV; ++i) part[i] = 0.0;
+    wave_sum_n<NV>(part, tot);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) red[wid][i] = tot[i];
     }
+    __syncthreads();
+    if (t < 7 * ND) a.partials[item * (7 * ND) + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
 }
+
 
 __global__ void k_summary_reduce(const double* __restrict__ partials, const int64_t* __restrict__ bin_first_item,
                                  int32_t n_bins, int32_t n_det, double* __restrict__ summary) {
@@ -583,7 +584,7 @@ hipError_t launch_chain_setup(const double* theta, int64_t B, const Network& net
 
 hipError_t launch_summary(const SummaryArgs& a, const int64_t* bin_first_item, double* summary, hipStream_t s,
                           KTime kt_items, KTime kt_reduce) {
-    const unsigned g1 = (unsigned)((a.n_items + 3) / 4);
+    const unsigned g1 = (unsigned)a.n_items;  // one workgroup per item
     switch (a.n_det) {
         case 1: launch_k(k_summary_items<1>, dim3(g1), dim3(256), s, kt_items, a); break;
         case 2: launch_k(k_summary_items<2>, dim3(g1), dim3(256), s, kt_items, a); break;

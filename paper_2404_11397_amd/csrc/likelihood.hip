@@ -9,7 +9,7 @@
 // xL_dj being the cross weight of the bin left of edge j.
 //
 // FP64 unit phasors come from a kPhasorN-entry table in LDS and a short Taylor
-// rotation (unit_phasor below).
+// rotation (unit_phasor, rbl_phasor.h).
 //
 // Mixed precision: the phase is accumulated in FP64 and reduced to (-1/2, 1/2]
 // revolutions in FP64; sin/cos (hardware, revolution argument), the ratio and the
@@ -17,38 +17,11 @@
 // A chain whose binned-sum magnitude bound exceeds kMixedScaleMax takes the FP64
 // path (a wavefront-uniform branch).
 #include "rbl_launch.h"
+#include "rbl_phasor.h"
 #include "rbl_wave.h"
 
 namespace rbl {
 
-// Unit phasor u = exp(-2 pi i phi) for a phase in revolutions.
-//
-// The walks carry phases in table units y = N phi, N = kPhasorN (an exact power-of-two
-// scaling of revolutions).  FP64: y = k + t, k = rint(y), |t| <= 1/2, so
-// exp(2 pi i phi) = E_k exp(2 pi i t / N) with E_k = exp(2 pi i k / N) from the table.  The
-// rotation angle a = 2 pi t / N is at most pi / N = 0.0061: sin a to degree 5 and cos a
-// to degree 4 of their Taylor series leave truncation errors below 1e-19 and 8e-17.
-// k mod N is read from the low mantissa bits of y + 1.5 * 2^52, which holds rint(y) in its
-// last place for |y| < 2^51; y - k is exact.
-namespace phasor_detail {
-constexpr double kW = 2.0 * 3.14159265358979323846 / kPhasorN;
-constexpr double kS0 = kW, kS1 = -kW * kW * kW / 6.0, kS2 = kW * kW * kW * kW * kW / 120.0;
-constexpr double kC1 = -kW * kW / 2.0, kC2 = kW * kW * kW * kW / 24.0;
-constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
-}  // namespace phasor_detail
-
-__device__ inline void unit_phasor(double y, const double2* tab, double& c, double& s) {
-    using namespace phasor_detail;
-    const double m = y + kMagic;
-    const double k = m - kMagic;
-    const double t = y - k;
-    const double2 e = tab[(unsigned)__double2loint(m) & (unsigned)(kPhasorN - 1)];
-    const double t2 = t * t;
-    const double sa = fma(fma(kS2, t2, kS1), t2, kS0) * t;
-    const double ca = fma(fma(kC2, t2, kC1), t2, 1.0);
-    c = fma(e.x, ca, -(e.y * sa));
-    s = -fma(e.y, ca, e.x * sa);
-}
 // Mixed precision: the hardware FP32 sin / cos on the reduced phase.
 __device__ inline void unit_phasor(double y, const double2*, float& c, float& s) {
     const double phi = y * (1.0 / kPhasorN);
@@ -67,12 +40,7 @@ __device__ inline EdgeTab<float> edge_tab(const EventDev& ev, float) { return {e
 __device__ inline const double* xr_tab(const EventDev& ev, double) { return ev.xR; }
 __device__ inline const float* xr_tab(const EventDev& ev, float) { return ev.xR32; }
 
-// The phasor table, copied into LDS by every block of the likelihood kernels.
-__device__ inline void load_phasor_table(const EventDev& ev, double2* tab) {
-    const double2* src = reinterpret_cast<const double2*>(ev.phasor);
-    for (int i = threadIdx.x; i < kPhasorN; i += blockDim.x) tab[i] = src[i];
-    __syncthreads();
-}
+__device__ inline void load_phasor_table(const EventDev& ev, double2* tab) { load_phasor_table(ev.phasor, tab); }
 
 // Table load with a 32-bit byte offset: lets the compiler address every table of a step
 // from its scalar base plus one shared vector offset (global_load ... saddr).

@@ -26,6 +26,7 @@ struct SummaryArgs {
     const double* data;  // [n_det][n_freq][2]
     const double* psd;   // [n_det][n_freq]
     double* partials;    // [n_items][n_det][7]
+    const double* phasor;  // [kPhasorN][2] unit-phasor table
     RefConsts ref;
     int32_t ref_taper;
 };

@@ -86,10 +86,12 @@ __device__ inline void chain_record(const T* th, const Network& net, const RefCo
     T sa, ca;
     dsincos(ang, sa, ca);
     const Cx<T> common{mag * ca, mag * sa};
+    SkyFrame<T> sky;
+    sky_frame<T>(th[9], th[10], th[11], th[12], net.gmst, sky);
     for (int d = 0; d < kMaxDet; ++d) {
         if (d < net.n_det) {
             Proj<T> p;
-            project<T>(th[9], th[10], th[11], th[12], net.gmst, net.D[d], net.r[d], p);
+            project<T>(sky, net.D[d], net.r[d], p);
             const Cx<T> inv0{T(ref.invC0_re[d]), T(ref.invC0_im[d])};
             const Cx<T> k = cmul(cmul(p.C, inv0), common);
             rec[kRecK + 2 * d] = k.re;
@@ -235,10 +237,12 @@ __global__ __launch_bounds__(256) void k_chain_setup_grad(const double* __restri
             ang[a] = D1(t[9 + a]);
             ang[a].d[0] = (a == tg) ? 1.0 : 0.0;
         }
+        SkyFrame<D1> sky;
+        sky_frame<D1>(ang[0], ang[1], ang[2], ang[3], net.gmst, sky);
         for (int d = 0; d < kMaxDet; ++d) {
             if (d < net.n_det) {
                 Proj<D1> p;
-                project<D1>(ang[0], ang[1], ang[2], ang[3], net.gmst, net.D[d], net.r[d], p);
+                project<D1>(sky, net.D[d], net.r[d], p);
                 const Cx<D1> inv0{D1(ref.invC0_re[d]), D1(ref.invC0_im[d])};
                 const Cx<D1> P = cmul(p.C, inv0);
                 J[kJacExt + (d * 3 + 0) * 4 + tg] = P.re.d[0];

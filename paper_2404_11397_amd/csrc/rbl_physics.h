@@ -165,24 +165,38 @@ struct Proj {
     T dt;     // arrival delay relative to the geocentre [s]
 };
 
+// The source frame, shared by all detectors: n, the polarisation axes p, q and cos(iota).
 template <class T>
-__device__ inline void project(const T& iota, const T& psi, const T& ra, const T& dec, double gmst,
-                                        const double* D /*[9]*/, const double* r /*[3]*/, Proj<T>& out) {
+struct SkyFrame {
+    T n[3], p[3], q[3], ci;
+};
+
+template <class T>
+__device__ inline void sky_frame(const T& iota, const T& psi, const T& ra, const T& dec, double gmst, SkyFrame<T>& s) {
     const T ph = ra - gmst;
     T sph, cph, sd, cd, sp, cp, si, ci;
     dsincos(ph, sph, cph);
     dsincos(dec, sd, cd);
     dsincos(psi, sp, cp);
     dsincos(iota, si, ci);
-    const T n[3] = {cd * cph, cd * sph, sd};
+    s.n[0] = cd * cph;
+    s.n[1] = cd * sph;
+    s.n[2] = sd;
     const T eth[3] = {sd * cph, sd * sph, -cd};
     const T eph[3] = {-sph, cph, T(0.0)};
-    T p[3], qv[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        p[i] = cp * eth[i] + sp * eph[i];
-        qv[i] = sp * eth[i] - cp * eph[i];
+        s.p[i] = cp * eth[i] + sp * eph[i];
+        s.q[i] = sp * eth[i] - cp * eph[i];
     }
+    s.ci = ci;
+}
+
+// One detector's response and delay in a source frame.
+template <class T>
+__device__ inline void project(const SkyFrame<T>& s, const double* D /*[9]*/, const double* r /*[3]*/, Proj<T>& out) {
+    const T* p = s.p;
+    const T* qv = s.q;
     // D p and D q, then the contractions.
     T Dp[3], Dq[3];
 #pragma unroll
@@ -196,9 +210,17 @@ __device__ inline void project(const T& iota, const T& psi, const T& ra, const T
     const T qDp = qv[0] * Dp[0] + qv[1] * Dp[1] + qv[2] * Dp[2];
     const T fplus = pDp - qDq;
     const T fcross = pDq + qDp;
-    out.C.re = 0.5 * (1.0 + ci * ci) * fplus;
-    out.C.im = -(ci * fcross);
-    out.dt = -(r[0] * n[0] + r[1] * n[1] + r[2] * n[2]) / kC;
+    out.C.re = 0.5 * (1.0 + s.ci * s.ci) * fplus;
+    out.C.im = -(s.ci * fcross);
+    out.dt = -(r[0] * s.n[0] + r[1] * s.n[1] + r[2] * s.n[2]) / kC;
+}
+
+template <class T>
+__device__ inline void project(const T& iota, const T& psi, const T& ra, const T& dec, double gmst,
+                               const double* D /*[9]*/, const double* r /*[3]*/, Proj<T>& out) {
+    SkyFrame<T> s;
+    sky_frame(iota, psi, ra, dec, gmst, s);
+    project(s, D, r, out);
 }
 
 }  // namespace rbl

@@ -590,8 +590,9 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
         if constexpr (WF != kWfNrtv2) zre = fma(-k2, ev.mu_sum[d], zre);
         const double zim = tot[1 + NA + ND + d];
         acc += zre;
-        ZR[d] = (zre * cv.kre[d] + zim * cv.kim[d]) / k2;
-        ZI[d] = (zim * cv.kre[d] - zre * cv.kim[d]) / k2;
+        const double ik2 = 1.0 / k2;
+        ZR[d] = (zre * cv.kre[d] + zim * cv.kim[d]) * ik2;
+        ZI[d] = (zim * cv.kre[d] - zre * cv.kim[d]) * ik2;
         Tt[d] = 2.0 * kPi * tot[1 + NA + 2 * ND + d];
     }
     acc *= 0.5;  // lnL = (sum_d Re Z_d + sum Re(gamma r*)) / 2

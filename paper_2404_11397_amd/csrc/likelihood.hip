@@ -73,6 +73,13 @@ struct ChainVals {
     NrtParams<double> np;  // IMRPhenomD_NRTidalv2 events only
 };
 
+// Accumulation helpers of the TaylorF2 walks: fused in FP64; in the mixed form the product
+// is formed in FP32 and added to the FP64 accumulator.
+__device__ inline void acc_dot(double& a, double x1, double y1, double x2, double y2) { a = fma(x1, y1, fma(x2, y2, a)); }
+__device__ inline void acc_dot(double& a, float x1, float y1, float x2, float y2) { a += (double)(x1 * y1 + x2 * y2); }
+__device__ inline void acc_mul(double& a, double x, double y) { a = fma(x, y, a); }
+__device__ inline void acc_mul(double& a, float x, double y) { a = fma((double)x, y, a); }
+
 // The amplitude ratio of an IMRPhenomD_NRTidalv2 chain to the reference stays below
 // about 1.1 in band; the bound takes it as 2.
 template <int ND>
@@ -110,22 +117,25 @@ __device__ inline void edge_phase(const EventDev& ev, const ChainVals<ND>& cv, u
 }
 
 // ---------------------------------------------------------------------------
-// TaylorF2 forward walk: this lane's share of lnL without the quadratic term, which is
-// -sum_d |K_d|^2 M_d / 2 (|r_dj| = |K_d|).  The cross term of the bin left of a lane's
-// first edge needs the last edge of lane - 1: exchanged once at the end.
+// TaylorF2 forward walk.  r_dj = K_d u_dj with u_dj the unit phasor of the edge phase, so
+// K_d factors out of every per-edge product: this lane's share of lnL without the quadratic
+// term is
+//   sum_d [ Re(K_d P_d) + |K_d|^2 X_d / 2 ],  P_d = sum_j conj(gamma_dj) u_dj,
+//   X_d = sum_j xL_dj Re(u_d,j-1 u_dj*),
+// and the quadratic term is -sum_d |K_d|^2 M_d / 2 (|r_dj| = |K_d|).  The cross term of the
+// bin left of a lane's first edge needs the last edge of lane - 1: exchanged once at the end.
 // ---------------------------------------------------------------------------
 template <int ND, class R>
 __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, const double2* tab, int lane) {
     const EdgeTab<R> T = edge_tab(ev, R(0));
     const int npad = ev.n_nodes_pad;
-    R kre[ND], kim[ND], pre[ND], pim[ND], fre[ND], fim[ND];
+    R pre[ND], pim[ND], fre[ND], fim[ND];
+    double Pr[ND], Pi[ND], X[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
-        kre[d] = (R)cv.kre[d];
-        kim[d] = (R)cv.kim[d];
         pre[d] = pim[d] = fre[d] = fim[d] = R(0);
+        Pr[d] = Pi[d] = X[d] = 0.0;
     }
-    double acc = 0.0;
     for (int k = 0; k < ev.L; ++k) {
         const unsigned pos = (unsigned)(k * 64 + lane);
         const Node n = ld_node(ev, pos);
@@ -137,28 +147,30 @@ __device__ inline double fwd_walk(const EventDev& ev, const ChainVals<ND>& cv, c
         for (int b = 0; b < kTf2Basis; ++b) ph = fma(cv.dc[b], bas[b], ph);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
-            R cu, su;
-            unit_phasor(fma(f, cv.dtau[d], ph), tab, cu, su);
-            const R rre = kre[d] * cu - kim[d] * su;
-            const R rim = kre[d] * su + kim[d] * cu;
+            R ur, ui;
+            unit_phasor(fma(f, cv.dtau[d], ph), tab, ur, ui);
             const unsigned o = (unsigned)(d * npad) + pos;
             const auto g = ld2(T.g, o);
-            R t = g.x * rre + g.y * rim;
+            const R gre = g.x, gim = g.y;
+            acc_dot(Pr[d], gre, ur, gim, ui);
+            acc_dot(Pi[d], gre, ui, -gim, ur);
             if (k > 0) {
-                t = fma(R(0.5) * ld(T.xl, o), pre[d] * rre + pim[d] * rim, t);
+                acc_mul(X[d], pre[d] * ur + pim[d] * ui, (double)ld(T.xl, o));
             } else {
-                fre[d] = rre;
-                fim[d] = rim;
+                fre[d] = ur;
+                fim[d] = ui;
             }
-            acc += (double)t;
-            pre[d] = rre;
-            pim[d] = rim;
+            pre[d] = ur;
+            pim[d] = ui;
         }
     }
+    double acc = 0.0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         const R lre = shift_up(pre[d], R(0), lane), lim = shift_up(pim[d], R(0), lane);
-        acc += (double)(R(0.5) * ld(T.xl, (unsigned)(d * npad + lane)) * (lre * fre[d] + lim * fim[d]));
+        acc_mul(X[d], lre * fre[d] + lim * fim[d], (double)ld(T.xl, (unsigned)(d * npad + lane)));
+        const double k2 = cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d];
+        acc = fma(cv.kre[d], Pr[d], fma(-cv.kim[d], Pi[d], fma(0.5 * k2, X[d], acc)));
     }
     return acc;
 }
@@ -319,8 +331,9 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) void k_loglike_fwd(Ev
 // w to z_j and conj(w) to z_{j-1} (2 Re w to Z_d, Im w to Im z_j, -Im w to Im z_{j-1}).
 // Im z_j = Im(conj(gamma_j) r_j) + cross terms (the mu term is real), and
 //   Re Z_d = sum_j [ Re(gamma r*) - mu |r|^2 + 2 (cross) ] = 2 lnL_d - sum_j Re(gamma r*),
-// so lnL = (sum_d Re Z_d + sum_dj Re(gamma_dj r_dj*)) / 2 needs one accumulator more.
-// For TaylorF2 the mu part of Re Z_d is -|K_d|^2 M_d and is added after the walk.
+// so lnL = (sum_d Re Z_d + sum_dj Re(gamma_dj r_dj*)) / 2 needs one accumulator more
+// (IMRPhenomD_NRTidalv2; TaylorF2 accumulates the same sums with K_d factored out, see
+// GradAccTf2, and adds the mu part -|K_d|^2 M_d after the walk).
 // Per lane: Z_d, T_d = sum_j Im(z_dj) f_j and S_b = sum_j (sum_d Im z_dj) B_b(x_j);
 // an edge's basis term is completed one step later, when the cross term to its right
 // is known.  Each lane first evaluates the ratio at the edge before its first edge
@@ -330,22 +343,39 @@ template <int ND, int NA>
 struct GradAcc {
     double acc;  // sum_dj Re(gamma_dj r_dj*)
     double zr[ND], zi[ND], ta[ND];
-    double sa[NA];  // TaylorF2: S_b (basis);  IMRPhenomD_NRTidalv2: adjoints of the node parameters
+    double sa[NA];  // adjoints of the IMRPhenomD_NRTidalv2 node parameters
+};
+
+// TaylorF2 accumulators with K_d factored out, r_dj = K_d u_dj (per lane; reduced after the
+// walk):  P_d = sum_j conj(gamma) u (complex),  X_d = sum_j xL Re(u_{j-1} u_j*),
+// T1_d = sum_j f_j Im(K_d conj(gamma_j) u_j),  T2_d = sum_j xL Im(u_{j-1}* u_j) (f_j - f_{j-1}) / 2,
+// S_b = sum_j q_j B_b(x_j) with q_j = sum_d Im z_dj.  Then
+//   Z_d / K_d = P_d + conj(K_d) (X_d - M_d),
+//   lnL = sum_d [ Re(K_d P_d) + |K_d|^2 (X_d - M_d) / 2 ],
+//   d lnL / d tau_d = 2 pi (T1_d + |K_d|^2 T2_d)   (tau_d the delay in seconds),
+// and K_d = 0 needs no special case.
+template <int ND>
+struct GradAccTf2 {
+    double pr[ND], pi[ND], x[ND], t1[ND], t2[ND];
+    double sa[kTf2Basis];
 };
 
 // UNROLL2: two edges per loop iteration (the LDS-table kernel, which then keeps its loop
 // state in registers without copies; measured faster there, not with global tables).
 template <int ND, class R, bool UNROLL2 = false>
 __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, const double2* tab, int lane,
-                                 GradAcc<ND, kTf2Basis>& G) {
+                                 GradAccTf2<ND>& G) {
     const EdgeTab<R> T = edge_tab(ev, R(0));
     const int npad = ev.n_nodes_pad;
     const int L = ev.L;
-    R kre[ND], kim[ND], rpr[ND], rpi[ND];
+    R upr[ND], upi[ND];  // the previous edge's unit phasors
+    R kre[ND], kim[ND];
+    double k2[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         kre[d] = (R)cv.kre[d];
         kim[d] = (R)cv.kim[d];
+        k2[d] = cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d];
     }
     // halo edge: the last edge of lane - 1 (lane 0 has none; its first edge has xL = 0)
     const unsigned hpos = (unsigned)(lane > 0 ? (L - 1) * 64 + (lane - 1) : npad - 1);
@@ -358,14 +388,9 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, co
 #pragma unroll
         for (int b = 0; b < kTf2Basis; ++b) ph = fma(cv.dc[b], bas[b], ph);
 #pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            R ur, ui;
-            unit_phasor(fma(fp, cv.dtau[d], ph), tab, ur, ui);
-            rpr[d] = kre[d] * ur - kim[d] * ui;
-            rpi[d] = kre[d] * ui + kim[d] * ur;
-        }
+        for (int d = 0; d < ND; ++d) unit_phasor(fma(fp, cv.dtau[d], ph), tab, upr[d], upi[d]);
     }
-    double qprev = 0.0;  // Im z of the previous edge without its right cross term (halo: not ours)
+    double qprev = 0.0;  // q of the previous edge without its right cross term (halo: not ours)
     auto step = [&](int k) {
         const unsigned pos = (unsigned)(k * 64 + lane);
         const Node n = ld_node(ev, pos);
@@ -381,23 +406,21 @@ __device__ inline void grad_walk(const EventDev& ev, const ChainVals<ND>& cv, co
         for (int d = 0; d < ND; ++d) {
             R ur, ui;
             unit_phasor(fma(f, cv.dtau[d], ph), tab, ur, ui);
-            const R rre = kre[d] * ur - kim[d] * ui;
-            const R rim = kre[d] * ui + kim[d] * ur;
             const unsigned o = (unsigned)(d * npad) + pos;
             const auto g = ld2(T.g, o);
             const R gre = g.x, gim = g.y, xl = ld(T.xl, o);
-            const R gr = gre * rre + gim * rim;
-            const R zt = fma(xl, rpr[d] * rre + rpi[d] * rim, gr);
-            const R imz = gre * rim - gim * rre;
-            const R imw2 = xl * (rpr[d] * rim - rpi[d] * rre);
-            G.acc += (double)gr;
-            G.zr[d] += (double)zt;
-            G.zi[d] += (double)imz;
+            const R pr = gre * ur + gim * ui, pi = gre * ui - gim * ur;  // conj(gamma) u
+            G.pr[d] += (double)pr;
+            G.pi[d] += (double)pi;
+            const R imz = kre[d] * pi + kim[d] * pr;  // Im(conj(gamma) r)
             qz += (double)imz;
-            p2 += (double)imw2;
-            G.ta[d] = fma((double)imz, f, fma((double)imw2, hdf, G.ta[d]));
-            rpr[d] = rre;
-            rpi[d] = rim;
+            acc_mul(G.t1[d], imz, f);
+            acc_mul(G.x[d], upr[d] * ur + upi[d] * ui, (double)xl);
+            const R t = xl * (upr[d] * ui - upi[d] * ur);
+            acc_mul(G.t2[d], t, hdf);
+            p2 = fma(k2[d], (double)t, p2);
+            upr[d] = ur;
+            upi[d] = ui;
         }
         {   // the previous edge is now complete: it carries q_prev - p, p = p2 / 2
             double bp[kTf2Basis];
@@ -489,14 +512,13 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
     }
 }
 
-// Occupancy target: at least 3 waves per SIMD for TaylorF2 in FP64 (the compiler fits the
-// global-table walk in 128 registers, so 4 are resident; the LDS-table walk, unrolled by two,
-// takes 149 and runs one 8-wave workgroup per CU, which measured as fast as two), 4 for the
-// mixed-precision TaylorF2 kernel
-// (measured faster than 3 despite a few spilled registers outside the walk's hot path), 2
-// for NRTidalv2, whose 26 adjoint accumulators and per-edge model would otherwise spill.
+// Occupancy target (waves per SIMD): 3 for the TaylorF2 LDS-table walk (unrolled by two, one
+// 8-wave workgroup per CU; two workgroups at 128 registers measured slower) and the mixed
+// walk (which spills at 4); 2 for the TaylorF2 FP64 global-table walk (170 registers: faster
+// than 3 with spills or 4 with more) and for NRTidalv2, whose 26 adjoint accumulators and
+// per-edge model would otherwise spill.
 template <int ND, bool MIXED, int WF, bool LT = false>
-__global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu_waves_per_eu(WF == kWfNrtv2 ? 2 : (MIXED ? 4 : 3)))) void k_loglike_grad(
+__global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu_waves_per_eu((WF == kWfNrtv2 || !(LT || MIXED)) ? 2 : 3))) void k_loglike_grad(
     EventDev ev, const double* __restrict__ recs, const double* __restrict__ jac, int64_t B,
     double* __restrict__ lnl, double* __restrict__ grad) {
     __shared__ double2 tab[kPhasorN];
@@ -544,80 +566,109 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
         cv.dtau[d] = rec[kRecTau + d];
         zero_k = zero_k || !(cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d] > 1e-280);
     }
-    GradAcc<ND, NA> G;
-    G.acc = 0.0;
-#pragma unroll
-    for (int d = 0; d < ND; ++d) G.zr[d] = G.zi[d] = G.ta[d] = 0.0;
-#pragma unroll
-    for (int b = 0; b < NA; ++b) G.sa[b] = 0.0;
+    // Z'_d = Z_d / K_d is the gradient with respect to K_d.
+    double acc, A[NA], ZR[ND], ZI[ND], Tt[ND];
     if constexpr (WF == kWfNrtv2) {
+        GradAcc<ND, NA> G;
+        G.acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) G.zr[d] = G.zi[d] = G.ta[d] = 0.0;
+#pragma unroll
+        for (int b = 0; b < NA; ++b) G.sa[b] = 0.0;
         if (MIXED && use_mixed<ND>(ev, cv))
             grad_walk_nrt<ND, float>(ev, cv, snp[wave_id()], tab, lane, G);
         else
             grad_walk_nrt<ND, double>(ev, cv, snp[wave_id()], tab, lane, G);
+        // Wave reductions of all accumulators at once.
+        constexpr int NV = (1 + NA + 3 * ND + 3) / 4 * 4;
+        double part[NV], tot[NV];
+        part[0] = G.acc;
+#pragma unroll
+        for (int b = 0; b < NA; ++b) part[1 + b] = G.sa[b];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            part[1 + NA + d] = G.zr[d];
+            part[1 + NA + ND + d] = G.zi[d];
+            part[1 + NA + 2 * ND + d] = G.ta[d];
+        }
+#pragma unroll
+        for (int i = 1 + NA + 3 * ND; i < NV; ++i) part[i] = 0.0;
+        wave_sum_n<NV>(part, tot);
+        acc = tot[0];
+#pragma unroll
+        for (int b = 0; b < NA; ++b) A[b] = tot[1 + b];  // the node adjoints include 2 pi
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const double k2 = cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d];
+            const double zre = tot[1 + NA + d], zim = tot[1 + NA + ND + d];
+            acc += zre;
+            const double ik2 = 1.0 / k2;
+            ZR[d] = (zre * cv.kre[d] + zim * cv.kim[d]) * ik2;
+            ZI[d] = (zim * cv.kre[d] - zre * cv.kim[d]) * ik2;
+            Tt[d] = 2.0 * kPi * tot[1 + NA + 2 * ND + d];
+        }
+        acc *= 0.5;  // lnL = (sum_d Re Z_d + sum Re(gamma r*)) / 2
+        if (zero_k) {
+            // A detector with K_d = 0 has r = 0 everywhere: d lnL / dK_d = sum_j conj(gamma_j) u_j.
+            const int npad = ev.n_nodes_pad;
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                if (cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d] > 1e-280) continue;
+                double sr = 0.0, si = 0.0;
+                for (int k = 0; k < ev.L; ++k) {
+                    const unsigned pos = (unsigned)(k * 64 + lane);
+                    const Node n = ld_node(ev, pos);
+                    double ph, ar;
+                    edge_phase<ND, WF>(ev, cv, pos, n, ph, ar);
+                    double ur, ui;
+                    expm2pi_rev(fma(n.f, cv.dtau[d], ph) * (1.0 / kPhasorN), ur, ui);
+                    ur *= ar;
+                    ui *= ar;
+                    const double2 g = ld2(ev.g, (unsigned)(d * npad) + pos);
+                    sr += g.x * ur + g.y * ui;
+                    si += g.x * ui - g.y * ur;
+                }
+                ZR[d] = wave_sum(sr);
+                ZI[d] = wave_sum(si);
+            }
+        }
     } else {
+        GradAccTf2<ND> G;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) G.pr[d] = G.pi[d] = G.x[d] = G.t1[d] = G.t2[d] = 0.0;
+#pragma unroll
+        for (int b = 0; b < kTf2Basis; ++b) G.sa[b] = 0.0;
         if (MIXED && use_mixed<ND>(ev, cv))
             grad_walk<ND, float>(ev, cv, tab, lane, G);
         else
             grad_walk<ND, double, LT>(ev, cv, tab, lane, G);
-    }
-
-    // Wave reductions of all accumulators at once.  Z'_d = Z_d / K_d is the gradient with
-    // respect to K_d.
-    constexpr int NV = (1 + NA + 3 * ND + 3) / 4 * 4;
-    double part[NV], tot[NV];
-    part[0] = G.acc;
+        constexpr int NV = (kTf2Basis + 5 * ND + 3) / 4 * 4;
+        double part[NV], tot[NV];
 #pragma unroll
-    for (int b = 0; b < NA; ++b) part[1 + b] = G.sa[b];
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-        part[1 + NA + d] = G.zr[d];
-        part[1 + NA + ND + d] = G.zi[d];
-        part[1 + NA + 2 * ND + d] = G.ta[d];
-    }
-#pragma unroll
-    for (int i = 1 + NA + 3 * ND; i < NV; ++i) part[i] = 0.0;
-    wave_sum_n<NV>(part, tot);
-    double acc = tot[0];
-    double A[NA], ZR[ND], ZI[ND], Tt[ND];
-    constexpr double kAdjScale = WF == kWfNrtv2 ? 1.0 : 2.0 * kPi;  // NRTidalv2 adjoints include 2 pi
-#pragma unroll
-    for (int b = 0; b < NA; ++b) A[b] = kAdjScale * tot[1 + b];
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-        const double k2 = cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d];
-        double zre = tot[1 + NA + d];
-        if constexpr (WF != kWfNrtv2) zre = fma(-k2, ev.mu_sum[d], zre);
-        const double zim = tot[1 + NA + ND + d];
-        acc += zre;
-        const double ik2 = 1.0 / k2;
-        ZR[d] = (zre * cv.kre[d] + zim * cv.kim[d]) * ik2;
-        ZI[d] = (zim * cv.kre[d] - zre * cv.kim[d]) * ik2;
-        Tt[d] = 2.0 * kPi * tot[1 + NA + 2 * ND + d];
-    }
-    acc *= 0.5;  // lnL = (sum_d Re Z_d + sum Re(gamma r*)) / 2
-    if (zero_k) {
-        // A detector with K_d = 0 has r = 0 everywhere: d lnL / dK_d = sum_j conj(gamma_j) u_j.
-        const int npad = ev.n_nodes_pad;
+        for (int b = 0; b < kTf2Basis; ++b) part[b] = G.sa[b];
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
-            if (cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d] > 1e-280) continue;
-            double sr = 0.0, si = 0.0;
-            for (int k = 0; k < ev.L; ++k) {
-                const unsigned pos = (unsigned)(k * 64 + lane);
-                const Node n = ld_node(ev, pos);
-                double ph, ar;
-                edge_phase<ND, WF>(ev, cv, pos, n, ph, ar);
-                double ur, ui;
-                expm2pi_rev(fma(n.f, cv.dtau[d], ph) * (1.0 / kPhasorN), ur, ui);
-                ur *= ar;
-                ui *= ar;
-                const double2 g = ld2(ev.g, (unsigned)(d * npad) + pos);
-                sr += g.x * ur + g.y * ui;
-                si += g.x * ui - g.y * ur;
-            }
-            ZR[d] = wave_sum(sr);
-            ZI[d] = wave_sum(si);
+            part[kTf2Basis + d] = G.pr[d];
+            part[kTf2Basis + ND + d] = G.pi[d];
+            part[kTf2Basis + 2 * ND + d] = G.x[d];
+            part[kTf2Basis + 3 * ND + d] = G.t1[d];
+            part[kTf2Basis + 4 * ND + d] = G.t2[d];
+        }
+#pragma unroll
+        for (int i = kTf2Basis + 5 * ND; i < NV; ++i) part[i] = 0.0;
+        wave_sum_n<NV>(part, tot);
+#pragma unroll
+        for (int b = 0; b < NA; ++b) A[b] = (2.0 * kPi) * tot[b];
+        acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const double kr = cv.kre[d], ki = cv.kim[d], k2 = kr * kr + ki * ki;
+            const double pr = tot[kTf2Basis + d], pi = tot[kTf2Basis + ND + d];
+            const double xm = tot[kTf2Basis + 2 * ND + d] - ev.mu_sum[d];
+            acc = fma(kr, pr, fma(-ki, pi, fma(0.5 * k2, xm, acc)));
+            ZR[d] = fma(kr, xm, pr);
+            ZI[d] = fma(-ki, xm, pi);
+            Tt[d] = (2.0 * kPi) * fma(k2, tot[kTf2Basis + 4 * ND + d], tot[kTf2Basis + 3 * ND + d]);
         }
     }
     // Chain rule through the setup: d lnL = sum_b A_b d dc_b + sum_d Re(Z'_d dK_d) + sum_d T_d d dtau_d,

@@ -58,3 +58,43 @@ def test_autograd_wrapper_returns_library_gradient():
     (lnl * w).sum().backward()
     _, g = gev.loglike_grad(th.detach())
     assert torch.equal(th.grad, w[:, None] * g)
+
+
+@pytest.mark.parametrize("approximant", ["taylorf2", "phenomd_nrtv2"])
+def test_near_null_response(approximant):
+    """Chains for which the first detector's response C_0 nearly vanishes (edge-on, iota =
+    pi/2, and psi on the zero of F+): |K_0| ~ 1e-17, where the phase of K_0 is set by
+    rounding.  lnL and gradient must still match the oracle."""
+    from oracle import detector as Det
+    ev = small_event(approximant=approximant, n_det=3, duration=4.0, f_high=512.0, n_bins=40)
+    L.prepare(ev)
+    gev = gpu_event(ev)
+    th = near_draws(ev.theta_ref, 8, 91, scale=0.5)
+    for i in range(0, 8, 2):
+        ra, dec = th[i, 11], th[i, 12]
+        a, _ = Det.antenna_patterns(ev.tensors[0], ra, dec, 0.0, ev.gmst)
+        b, _ = Det.antenna_patterns(ev.tensors[0], ra, dec, np.pi / 4, ev.gmst)
+        th[i, 9] = np.pi / 2
+        th[i, 10] = 0.5 * np.arctan2(-a, b) % np.pi  # F+ of detector 0 vanishes
+    c0 = [abs(W_proj) for W_proj in _response0(ev, th)]
+    assert max(c0[0::2]) < 1e-14 and min(c0[1::2]) > 1e-3
+    t = _cuda(th)
+    want, wg = L.loglike_rb_grad(ev, th)
+    scale = np.maximum(np.abs(want), rb_condition_scale(ev, th))
+    lg, g = gev.loglike_grad(t)
+    lg, g = lg.cpu().numpy(), g.cpu().numpy()
+    assert np.all(np.abs(lg - want) <= 1e-8 * scale)
+    assert np.all(np.abs(gev.loglike(t).cpu().numpy() - want) <= 1e-8 * scale)
+    gs, ws = g * WIDTHS, wg * WIDTHS
+    rel = np.abs(gs - ws).max(axis=1) / np.maximum(np.abs(ws).max(axis=1), 1e-300)
+    say(approximant, "near-null |C_0|", max(c0[0::2]), "grad", rel.max())
+    assert np.all(rel <= 1e-5)
+
+
+def _response0(ev, th):
+    from oracle import waveform as W
+    out = []
+    for row in th:
+        (c0, _), *_ = W.projection(W.unpack(row[None, :]), ev.tensors, ev.vertices, ev.gmst)
+        out.append(complex(np.asarray(c0).ravel()[0]))
+    return out

@@ -1,7 +1,7 @@
 // HIP kernels of the relative-binned likelihood (gfx950, wave64).
 //
 //  k_ref_setup      reference (fiducial) constants for theta0            [1 thread]
-//  k_chain_setup    per-chain record                                     [1 thread / chain]
+//  k_chain_setup    per-chain record                                     [1 thread / (chain, half)]
 //  k_chain_setup_grad  record and partial derivatives (dual numbers)    [1 lane / (chain, tangent)]
 //  k_summary_items  summary-data partial sums over (bin, chunk) items    [1 workgroup / item]
 //  k_summary_reduce ordered sum of the partials of each bin              [1 thread / (det, bin, field)]
@@ -66,45 +66,6 @@ __global__ void k_ref_setup(Theta13 th, Network net, int32_t waveform, NrtConsts
 // ---------------------------------------------------------------------------
 // Per-chain setup: record (and, for the gradient, d record / d theta).
 // ---------------------------------------------------------------------------
-template <class T>
-__device__ inline void chain_record(const T* th, const Network& net, const RefConsts& ref, T* rec /*[kRecUsed]*/) {
-    T dconst(0.0), amp;
-    if (ref.waveform == kWfNrtv2) {
-        for (int b = 0; b < kTf2Basis; ++b) rec[kRecDc + b] = T(0.0);
-        amp = tf2_amp<T>(th[0]);
-    } else {
-        Tf2Coeffs<T> c;
-        tf2_coeffs<T>(th[0], th[1], th[2], th[3], th[4], th[5], c);
-        for (int b = 0; b < kTf2Basis; ++b) rec[kRecDc + b] = (c.c[b] - ref.c0[b]) * (double)kPhasorN;
-        dconst = c.c_const - ref.c0_const;
-        dconst = dconst - rint(val(dconst));  // whole revolutions removed (no derivative)
-        amp = c.amp;
-    }
-    // common complex factor (dL0/dL)(amp/amp0) exp(2i(phic - phic0)) exp(-2 pi i dconst)
-    const T ang = 2.0 * (th[8] - ref.phic0) - (2.0 * kPi) * dconst;
-    const T mag = (ref.dl0 / th[6]) * (amp / ref.amp0);
-    T sa, ca;
-    dsincos(ang, sa, ca);
-    const Cx<T> common{mag * ca, mag * sa};
-    SkyFrame<T> sky;
-    sky_frame<T>(th[9], th[10], th[11], th[12], net.gmst, sky);
-    for (int d = 0; d < kMaxDet; ++d) {
-        if (d < net.n_det) {
-            Proj<T> p;
-            project<T>(sky, net.D[d], net.r[d], p);
-            const Cx<T> inv0{T(ref.invC0_re[d]), T(ref.invC0_im[d])};
-            const Cx<T> k = cmul(cmul(p.C, inv0), common);
-            rec[kRecK + 2 * d] = k.re;
-            rec[kRecK + 2 * d + 1] = k.im;
-            rec[kRecTau + d] = ((th[7] + p.dt) - ref.tau0[d]) * (double)kPhasorN;
-        } else {
-            rec[kRecK + 2 * d] = T(0.0);
-            rec[kRecK + 2 * d + 1] = T(0.0);
-            rec[kRecTau + d] = T(0.0);
-        }
-    }
-}
-
 __device__ inline int theta_status(const double* t) {
     bool nan = false;
     for (int i = 0; i < 13; ++i) nan = nan || isnan(t[i]);
@@ -116,28 +77,74 @@ __device__ inline int theta_status(const double* t) {
     return ok ? 1 : 0;
 }
 
+// Record for the likelihood alone.  Two kinds of blocks, one thread per chain in each:
+// intrinsic blocks write the status, the TaylorF2 coefficients (or the IMRPhenomD_NRTidalv2
+// node parameters), G and dL; extrinsic blocks write P_d and the delays.  The two halves of a
+// chain's setup run concurrently (the kernel is latency-bound); the likelihood kernels form
+// K_d = P_d G.
 __global__ __launch_bounds__(64) void k_chain_setup(const double* __restrict__ theta, int64_t B, Network net,
-                                                    RefConsts ref, double* __restrict__ rec) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                    RefConsts ref, double* __restrict__ rec, int64_t n_int_blocks) {
+    const bool intrinsic = (int64_t)blockIdx.x < n_int_blocks;
+    const int64_t b = ((int64_t)blockIdx.x - (intrinsic ? 0 : n_int_blocks)) * blockDim.x + threadIdx.x;
     if (b >= B) return;
     double t[13];
+#pragma unroll
     for (int i = 0; i < 13; ++i) t[i] = theta[b * 13 + i];
     double* out = rec + b * kRecStride;
     const int st = theta_status(t);
-    if (st != 1) {
-        out[kRecStatus] = st < 0 ? __builtin_nan("") : 0.0;
-        for (int i = 1; i < kRecUsed; ++i) out[i] = 0.0;
-        return;
-    }
-    out[kRecStatus] = 1.0;
-    double r[kRecUsed];
-    chain_record<double>(t, net, ref, r);
-    for (int i = 1; i < kRecUsed; ++i) out[i] = r[i];
-    if (ref.waveform == kWfNrtv2) {
-        NrtParams<double> np;
-        nrt_params<double>(t[0], t[1], t[2], t[3], t[4], t[5], ref.nc, np);
-        const double* src = reinterpret_cast<const double*>(&np);
-        for (int i = 0; i < kNrtParams; ++i) out[kRecNrt + i] = src[i];
+    if (intrinsic) {
+        if (st != 1) {
+            out[kRecStatus] = st < 0 ? __builtin_nan("") : 0.0;
+            for (int i = kRecDc; i < kRecDc + kTf2Basis; ++i) out[i] = 0.0;
+            out[kRecG] = out[kRecG + 1] = out[kRecDl] = 0.0;
+            return;
+        }
+        out[kRecStatus] = 1.0;
+        double dconst = 0.0, amp;
+        if (ref.waveform == kWfNrtv2) {
+            for (int k = 0; k < kTf2Basis; ++k) out[kRecDc + k] = 0.0;
+            amp = tf2_amp<double>(t[0]);
+            NrtParams<double> np;
+            nrt_params<double>(t[0], t[1], t[2], t[3], t[4], t[5], ref.nc, np);
+            const double* src = reinterpret_cast<const double*>(&np);
+            for (int i = 0; i < kNrtParams; ++i) out[kRecNrt + i] = src[i];
+        } else {
+            Tf2Coeffs<double> c;
+            tf2_coeffs<double>(t[0], t[1], t[2], t[3], t[4], t[5], c);
+            for (int k = 0; k < kTf2Basis; ++k) out[kRecDc + k] = (c.c[k] - ref.c0[k]) * (double)kPhasorN;
+            dconst = c.c_const - ref.c0_const;
+            dconst -= rint(dconst);  // whole revolutions removed
+            amp = c.amp;
+        }
+        // G = (dL0/dL)(amp/amp0) exp(2i(phic - phic0)) exp(-2 pi i dconst)
+        const double ang = 2.0 * (t[8] - ref.phic0) - (2.0 * kPi) * dconst;
+        const double mag = (ref.dl0 / t[6]) * (amp / ref.amp0);
+        double sa, ca;
+        dsincos(ang, sa, ca);
+        out[kRecG] = mag * ca;
+        out[kRecG + 1] = mag * sa;
+        out[kRecDl] = t[6];
+    } else {
+        if (st != 1) {
+            for (int i = kRecK; i < kRecTau + kMaxDet; ++i) out[i] = 0.0;
+            return;
+        }
+        SkyFrame<double> sky;
+        sky_frame<double>(t[9], t[10], t[11], t[12], net.gmst, sky);
+        for (int d = 0; d < kMaxDet; ++d) {
+            double pr = 0.0, pi = 0.0, tau = 0.0;
+            if (d < net.n_det) {
+                Proj<double> p;
+                project<double>(sky, net.D[d], net.r[d], p);
+                const Cx<double> P = cmul(p.C, Cx<double>{ref.invC0_re[d], ref.invC0_im[d]});
+                pr = P.re;
+                pi = P.im;
+                tau = ((t[7] + p.dt) - ref.tau0[d]) * (double)kPhasorN;
+            }
+            out[kRecK + 2 * d] = pr;
+            out[kRecK + 2 * d + 1] = pi;
+            out[kRecTau + d] = tau;
+        }
     }
 }
 
@@ -494,8 +501,10 @@ __global__ __launch_bounds__(256) void k_loglike_full(FullArgs a) {
     double c[kTf2Basis];
     for (int k = 0; k < kTf2Basis; ++k) c[k] = ref.c0[k] + rec[kRecDc + k] * (1.0 / kPhasorN);
     double fre[kMaxDet], fim[kMaxDet], tau[kMaxDet];
+    const double g_re = rec[kRecG], g_im = rec[kRecG + 1];
     for (int d = 0; d < a.n_det; ++d) {
-        const double kre = rec[kRecK + 2 * d], kim = rec[kRecK + 2 * d + 1];
+        const double pr = rec[kRecK + 2 * d], pi = rec[kRecK + 2 * d + 1];
+        const double kre = pr * g_re - pi * g_im, kim = pr * g_im + pi * g_re;  // K_d = P_d G
         fre[d] = ref.amp0 * (ref.h0fac_re[d] * kre - ref.h0fac_im[d] * kim);
         fim[d] = ref.amp0 * (ref.h0fac_re[d] * kim + ref.h0fac_im[d] * kre);
         tau[d] = ref.tau0[d] + rec[kRecTau + d] * (1.0 / kPhasorN);
@@ -583,7 +592,8 @@ hipError_t launch_chain_setup(const double* theta, int64_t B, const Network& net
         launch_k(k_chain_setup_grad, dim3((unsigned)(n_int + n_ext)), dim3(64), s, kt, theta, B, net, ref,
                            rec, jac, n_int);
     } else {
-        launch_k(k_chain_setup, dim3((unsigned)((B + 63) / 64)), dim3(64), s, kt, theta, B, net, ref, rec);
+        const int64_t n_half = (B + 63) / 64;
+        launch_k(k_chain_setup, dim3((unsigned)(2 * n_half)), dim3(64), s, kt, theta, B, net, ref, rec, n_half);
     }
     return hipGetLastError();
 }

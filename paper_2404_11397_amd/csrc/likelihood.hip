@@ -295,10 +295,12 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) void k_loglike_fwd(Ev
     ChainVals<ND> cv;
 #pragma unroll
     for (int j = 0; j < kTf2Basis; ++j) cv.dc[j] = rec[kRecDc + j];
+    const double g_re = rec[kRecG], g_im = rec[kRecG + 1];
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
-        cv.kre[d] = rec[kRecK + 2 * d];
-        cv.kim[d] = rec[kRecK + 2 * d + 1];
+        const double pr = rec[kRecK + 2 * d], pi = rec[kRecK + 2 * d + 1];
+        cv.kre[d] = pr * g_re - pi * g_im;  // K_d = P_d G
+        cv.kim[d] = pr * g_im + pi * g_re;
         cv.dtau[d] = rec[kRecTau + d];
     }
     if (WF == kWfNrtv2) {

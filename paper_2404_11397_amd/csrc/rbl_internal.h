@@ -17,12 +17,10 @@ constexpr int kPhasorN = 512;  // entries of the unit-phasor table exp(2 pi i k 
 //   [0]        status: 1 valid, 0 outside the physical domain, NaN if theta has a NaN
 //   [1..10]    dc_b  = c_b(theta) - c_b(theta0), TaylorF2 basis coefficients, in table units
 //              (kPhasorN rev: an exact power-of-two scaling)
-//   [11..16]   likelihood setup: K_d = P_d G, (re, im) per detector;
-//              gradient setup:   P_d itself (the kernel forms K_d = P_d G), where
-//              P_d = C_d / C_d0 and G = (dL0/dL)(Mc/Mc0)^(5/6) exp(2i (phic - phic0)) exp(-2 pi i dc_const)
+//   [11..16]   P_d = C_d / C_d0, (re, im) per detector (the likelihood kernels form K_d = P_d G)
 //   [17..19]   dtau_d = (tc + dt_d) - (tc0 + dt_d0), times kPhasorN  [s]
-//   [20..21]   G (re, im)                 (gradient setup only)
-//   [22]       dL                         (gradient setup only)
+//   [20..21]   G = (dL0/dL)(Mc/Mc0)^(5/6) exp(2i (phic - phic0)) exp(-2 pi i dc_const), (re, im)
+//   [22]       dL
 //   [24..52]   NrtParams<double> of the chain (IMRPhenomD_NRTidalv2 events; dc and the
 //              constant phase are then unused: the edge phase is taken absolutely)
 constexpr int kRecStride = 64;
@@ -32,7 +30,6 @@ constexpr int kRecK = 11;
 constexpr int kRecTau = 17;
 constexpr int kRecG = 20;
 constexpr int kRecDl = 22;
-constexpr int kRecUsed = 20;                 // entries 1..19 are used by the likelihood kernels
 constexpr int kRecNrt = 24;
 
 // Partial derivatives stored per chain for the gradient (FP64, 200 doubles):

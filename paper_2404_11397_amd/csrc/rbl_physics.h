@@ -42,6 +42,7 @@ struct Tf2Coeffs {
 template <class T>
 struct Tf2Pn {
     T eta, x1, x2, mtot;     // symmetric mass ratio, mass fractions, total mass [Msun]
+    T lmc, lmtot;            // ln Mc, ln M
     T p[8];                  // p_0 .. p_7 (p_1 = 0)
     T l5;                    // log coefficient of k = 5 (l6 is a constant)
     T p10, p12;              // tidal
@@ -59,7 +60,9 @@ __host__ __device__ inline void tf2_pn(const T& mc, const T& q, const T& chi1, c
     o.eta = eta;
     o.x1 = x1;
     o.x2 = x2;
-    o.mtot = mc * dexp(-0.6 * dlog(eta));
+    o.lmc = dlog(mc);
+    o.lmtot = o.lmc - 0.6 * dlog(eta);
+    o.mtot = dexp(o.lmtot);
     const T dm = x1 - x2;  // signed (m1 - m2)/M
     const T cs = 0.5 * (chi1 + chi2);
     const T ca = 0.5 * (chi1 - chi2);
@@ -114,17 +117,20 @@ __host__ __device__ inline void tf2_coeffs(const T& mc, const T& q, const T& chi
     Tf2Pn<T> pn;
     tf2_pn<T>(mc, q, chi1, chi2, lam1, lam2, pn);
     // v = s x: fold powers of s into the coefficients; divide by 2 pi for revolutions.
-    const T s = dcbrt(kPi * kTsun * pn.mtot);
-    const T ls = dlog(s);
+    // ln s = (ln(pi Tsun) + ln M) / 3 from the logarithms already at hand (no cube root).
+    const T ls = (1.0 / 3.0) * (pn.lmtot + log(kPi * kTsun));
+    const T s = dexp(ls);
+    const T is = 1.0 / s;
     const T s2 = s * s;
-    const T s3 = s2 * s;
-    const T s5 = s3 * s2;
+    const T s5 = s2 * s2 * s;
     const T s7 = s5 * s2;
+    const T is2 = is * is;
+    const T is3 = is2 * is;
     const T P = (3.0 / (128.0 * 2.0 * kPi)) / pn.eta;
-    out.c[0] = P / s5;                         // x^-5   (k = 0)
-    out.c[1] = P * pn.p[2] / s3;               // x^-3   (k = 2)
-    out.c[2] = P * pn.p[3] / s2;               // x^-2   (k = 3)
-    out.c[3] = P * pn.p[4] / s;                // x^-1   (k = 4)
+    out.c[0] = P * (is3 * is2);                // x^-5   (k = 0)
+    out.c[1] = P * pn.p[2] * is3;              // x^-3   (k = 2)
+    out.c[2] = P * pn.p[3] * is2;              // x^-2   (k = 3)
+    out.c[3] = P * pn.p[4] * is;               // x^-1   (k = 4)
     out.c[4] = P * pn.l5;                      // ln x   (k = 5, log)
     out.c[5] = P * (pn.p[6] + kTf2L6 * ls) * s;  // x    (k = 6)
     out.c[6] = P * (kTf2L6 * s);               // x ln x (k = 6, log)
@@ -132,7 +138,8 @@ __host__ __device__ inline void tf2_coeffs(const T& mc, const T& q, const T& chi
     out.c[8] = P * pn.p10 * s5;                // x^5    (tidal 5PN)
     out.c[9] = P * pn.p12 * s7;                // x^7    (tidal 6PN)
     out.c_const = P * (pn.p[5] + pn.l5 * ls) - 0.125;
-    out.amp = tf2_amp<T>(mc);
+    // tf2_amp from ln Mc: (Mc Tsun)^(5/6) = exp(5/6 (ln Mc + ln Tsun))
+    out.amp = dexp((5.0 / 6.0) * (pn.lmc + log(kTsun))) * (sqrt(5.0 / 24.0) * pow(kPi, -2.0 / 3.0) * (kC / kMpc));
 }
 
 // Basis values at x = f^(1/3) given x, 1/x and ln x.

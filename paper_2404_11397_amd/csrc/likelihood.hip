@@ -1,12 +1,15 @@
 // Relative-binned likelihood kernels (gfx950, wave64): lnL, and lnL with the adjoint
 // gradient, each in FP64 or mixed precision.
 //
-// One wavefront per chain.  Lane l walks its L consecutive bin edges j = l L + k
-// (k = 0..L-1) in the lane-contiguous table layout.  At each edge the ratio of
+// One wavefront per chain.  TaylorF2: lane l walks its L consecutive bin edges
+// j = l L + k (k = 0..L-1) in the lane-contiguous table layout; IMRPhenomD_NRTidalv2:
+// step k covers edges 64k .. 64k+63 (natural order).  At each edge the ratio of
 // Eq. (4) is r_d = K_d exp(-2 pi i phi_d), phi_d = sum_b dc_b B_b(x_j) + f_j dtau_d
-// (revolutions), and the binned sum of Eq. (5) is regrouped per edge:
+// (revolutions; times a / a0 for IMRPhenomD_NRTidalv2), and the binned sum of Eq. (5)
+// is regrouped per edge:
 //   2 lnL = sum_d sum_j [ 2 Re(gamma_dj r_dj*) - mu_dj |r_dj|^2 + xL_dj Re(r_d,j-1 r_dj*) ],
-// xL_dj being the cross weight of the bin left of edge j.
+// xL_dj being the cross weight of the bin left of edge j.  The TaylorF2 walks keep K_d
+// out of the per-edge products and apply it after the wavefront reduction.
 //
 // FP64 unit phasors come from a kPhasorN-entry table in LDS and a short Taylor
 // rotation (unit_phasor, rbl_phasor.h).

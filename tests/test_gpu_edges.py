@@ -89,6 +89,9 @@ def test_near_null_response(approximant):
     rel = np.abs(gs - ws).max(axis=1) / np.maximum(np.abs(ws).max(axis=1), 1e-300)
     say(approximant, "near-null |C_0|", max(c0[0::2]), "grad", rel.max())
     assert np.all(rel <= 1e-5)
+    gm = gev.loglike(t, precision="mixed").cpu().numpy()
+    lm, _ = gev.loglike_grad(t, precision="mixed")
+    assert np.all(np.abs(gm - want) <= 1e-2) and np.all(np.abs(lm.cpu().numpy() - want) <= 1e-2)
 
 
 def _response0(ev, th):

@@ -272,6 +272,42 @@ __device__ inline void stage_edge_tables(EventDev& ev, double* lds) {
     ev.g = g;
     ev.xL = xl;
 }
+// IMRPhenomD_NRTidalv2 edge tables staged in LDS for the gradient walk: the gamma pairs,
+// mu, x_L and x_R of the first ND detectors (5 ND npad doubles), natural order.
+template <int ND>
+__device__ inline void stage_nrt_tables(EventDev& ev, double* lds) {
+    const int np = ev.n_nodes_pad;
+    double* g = lds;
+    double* mu = g + 2 * ND * np;
+    double* xl = mu + ND * np;
+    double* xr = xl + ND * np;
+    double* p0 = xr + ND * np;
+    double* a0 = p0 + np;
+    double* x5 = a0 + np;
+    const double2* sg = reinterpret_cast<const double2*>(ev.g);
+    for (int i = threadIdx.x; i < ND * np; i += blockDim.x) {
+        reinterpret_cast<double2*>(g)[i] = sg[i];
+        mu[i] = ev.mu[i];
+        xl[i] = ev.xL[i];
+        xr[i] = ev.xR[i];
+    }
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        p0[i] = ev.phi0[i];
+        a0[i] = ev.ia0[i];
+        x5[i] = ev.node_x578[i];
+    }
+    __syncthreads();
+    ev.phi0 = p0;
+    ev.ia0 = a0;
+    ev.node_x578 = x5;
+    ev.g = g;
+    ev.mu = mu;
+    ev.xL = xl;
+    ev.xR = xr;
+}
+inline size_t staged_nrt_table_bytes(int nd, int np) { return sizeof(double) * (size_t)np * (5 * (size_t)nd + 3); }
+constexpr size_t kNrtStageMaxBytes = 144 * 1024;  // with the phasor table and node parameters: one workgroup per CU
+
 // LDS bytes of the staged tables.
 inline size_t staged_table_bytes(int nd, int np) { return sizeof(double) * (size_t)np * (4 + 3 * (size_t)nd); }
 constexpr size_t kStageMaxBytes = 56 * 1024;  // with the 8 KB phasor table: two workgroups per CU
@@ -530,7 +566,10 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
     load_phasor_table(ev, tab);
     if constexpr (LT) {
         extern __shared__ double lds_tables[];
-        stage_edge_tables<ND>(ev, lds_tables);
+        if constexpr (WF == kWfNrtv2)
+            stage_nrt_tables<ND>(ev, lds_tables);
+        else
+            stage_edge_tables<ND>(ev, lds_tables);
     }
     const int lane = threadIdx.x & 63;
     const int64_t chain = (int64_t)blockIdx.x * (LT ? kStageChains : 4) + wave_id();
@@ -545,7 +584,7 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
     // IMRPhenomD_NRTidalv2: the chain's 29 node parameters are read by the walk from LDS
     // (uniform-address loads) rather than held in scalar registers, which would overflow
     // into per-step spill reloads next to the table bases, K_d and the delays.
-    __shared__ NrtParams<double> snp[4];
+    __shared__ NrtParams<double> snp[LT ? kStageChains : 4];
     if constexpr (WF == kWfNrtv2) {
         if (lane < kNrtParams) reinterpret_cast<double*>(&snp[wave_id()])[lane] = rec[kRecNrt + lane];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -764,9 +803,14 @@ static void grad_nd(const EventDev& ev, const double* rec, const double* jac, in
                     double* grad, hipStream_t s, KTime kt) {
     const unsigned grid = (unsigned)((B + 3) / 4);
     if (ev.waveform == kWfNrtv2) {
+        const size_t lb = staged_nrt_table_bytes(ND, ev.n_nodes_pad);
         if (mixed)
             launch_k(k_loglike_grad<ND, true, kWfNrtv2>, dim3(grid), dim3(256), s, kt, ev, rec, jac, B,
                                lnl, grad);
+        else if (lb <= kNrtStageMaxBytes)
+            launch_k_lds(k_loglike_grad<ND, false, kWfNrtv2, true>,
+                         dim3((unsigned)((B + kStageChains - 1) / kStageChains)), dim3(64 * kStageChains), lb,
+                         s, kt, ev, rec, jac, B, lnl, grad);
         else
             launch_k(k_loglike_grad<ND, false, kWfNrtv2>, dim3(grid), dim3(256), s, kt, ev, rec, jac, B,
                                lnl, grad);

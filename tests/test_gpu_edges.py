@@ -1,6 +1,6 @@
 """Edge cases of the binned likelihood on the GPU against the oracle: bin counts around
-the 64-edge step (1, 63, 64, 65 bins) and on both sides of the LDS-table limit (500, 700),
-two detectors, a single chain and a ragged batch,
+the 64-edge step (1, 63, 64, 65 bins) and on both sides of the LDS-table limits (500, 700
+for TaylorF2; 1100 for IMRPhenomD_NRTidalv2), two detectors, a single chain and a ragged batch,
 for both waveforms, FP64 lnL and gradient and mixed lnL; and the autograd wrapper."""
 import numpy as np
 import pytest
@@ -23,8 +23,11 @@ def _cuda(a):
 
 @pytest.mark.parametrize("approximant", ["taylorf2", "phenomd_nrtv2"])
 # 500 bins with 3 detectors: the TaylorF2 FP64 gradient stages the edge tables in LDS
-# (512 padded edges); 700 bins: too large for LDS, the global-table kernel.
-@pytest.mark.parametrize("n_bins,n_det,B", [(1, 1, 1), (63, 2, 5), (64, 3, 64), (65, 2, 257), (500, 3, 9), (700, 3, 17)])
+# (512 padded edges); 700 bins: too large for LDS, the global-table kernel.  The
+# IMRPhenomD_NRTidalv2 FP64 gradient stages its tables up to 1024 padded edges at 3
+# detectors; 1100 bins take its global-table kernel.
+@pytest.mark.parametrize("n_bins,n_det,B", [(1, 1, 1), (63, 2, 5), (64, 3, 64), (65, 2, 257), (500, 3, 9), (700, 3, 17),
+                                            (1100, 3, 5)])
 def test_edge_shapes(approximant, n_bins, n_det, B):
     ev = small_event(approximant=approximant, n_det=n_det, duration=4.0, f_high=512.0, n_bins=n_bins)
     L.prepare(ev)

@@ -306,6 +306,41 @@ __device__ inline void stage_nrt_tables(EventDev& ev, double* lds) {
     ev.xR = xr;
 }
 inline size_t staged_nrt_table_bytes(int nd, int np) { return sizeof(double) * (size_t)np * (5 * (size_t)nd + 3); }
+// The mixed-precision walk's FP32 tables (gamma pairs, mu, x_L, x_R) and the FP64 reference
+// phase, inverse amplitude and x^5.78; a chain that takes the FP64 branch reads the FP64
+// tables from global memory.
+template <int ND>
+__device__ inline void stage_nrt_tables32(EventDev& ev, double* lds) {
+    const int np = ev.n_nodes_pad;
+    double* p0 = lds;
+    double* a0 = p0 + np;
+    double* x5 = a0 + np;
+    float* g = reinterpret_cast<float*>(x5 + np);
+    float* mu = g + 2 * ND * np;
+    float* xl = mu + ND * np;
+    float* xr = xl + ND * np;
+    const float2* sg = reinterpret_cast<const float2*>(ev.g32);
+    for (int i = threadIdx.x; i < ND * np; i += blockDim.x) {
+        reinterpret_cast<float2*>(g)[i] = sg[i];
+        mu[i] = ev.mu32[i];
+        xl[i] = ev.xL32[i];
+        xr[i] = ev.xR32[i];
+    }
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        p0[i] = ev.phi0[i];
+        a0[i] = ev.ia0[i];
+        x5[i] = ev.node_x578[i];
+    }
+    __syncthreads();
+    ev.phi0 = p0;
+    ev.ia0 = a0;
+    ev.node_x578 = x5;
+    ev.g32 = g;
+    ev.mu32 = mu;
+    ev.xL32 = xl;
+    ev.xR32 = xr;
+}
+inline size_t staged_nrt_table32_bytes(int nd, int np) { return (size_t)np * (20 * (size_t)nd + 24); }
 constexpr size_t kNrtStageMaxBytes = 144 * 1024;  // with the phasor table and node parameters: one workgroup per CU
 
 // LDS bytes of the staged tables.
@@ -566,7 +601,9 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
     load_phasor_table(ev, tab);
     if constexpr (LT) {
         extern __shared__ double lds_tables[];
-        if constexpr (WF == kWfNrtv2)
+        if constexpr (WF == kWfNrtv2 && MIXED)
+            stage_nrt_tables32<ND>(ev, lds_tables);
+        else if constexpr (WF == kWfNrtv2)
             stage_nrt_tables<ND>(ev, lds_tables);
         else
             stage_edge_tables<ND>(ev, lds_tables);
@@ -804,7 +841,12 @@ static void grad_nd(const EventDev& ev, const double* rec, const double* jac, in
     const unsigned grid = (unsigned)((B + 3) / 4);
     if (ev.waveform == kWfNrtv2) {
         const size_t lb = staged_nrt_table_bytes(ND, ev.n_nodes_pad);
-        if (mixed)
+        const size_t lb32 = staged_nrt_table32_bytes(ND, ev.n_nodes_pad);
+        if (mixed && lb32 <= kNrtStageMaxBytes)
+            launch_k_lds(k_loglike_grad<ND, true, kWfNrtv2, true>,
+                         dim3((unsigned)((B + kStageChains - 1) / kStageChains)), dim3(64 * kStageChains), lb32,
+                         s, kt, ev, rec, jac, B, lnl, grad);
+        else if (mixed)
             launch_k(k_loglike_grad<ND, true, kWfNrtv2>, dim3(grid), dim3(256), s, kt, ev, rec, jac, B,
                                lnl, grad);
         else if (lb <= kNrtStageMaxBytes)

@@ -7,7 +7,7 @@
 //  k_summary_reduce ordered sum of the partials of each bin              [1 thread / (det, bin, field)]
 //  k_node_tables    per-edge coefficient tables of the binned sum        [1 thread / node]
 //  (k_loglike_fwd and k_loglike_grad, the likelihood kernels, are in likelihood.hip)
-//  k_loglike_full   full-grid likelihood (validation)                    [1 block / chain]
+//  k_loglike_full   full-grid likelihood (validation)                    [1 workgroup / chain]
 //  k_strain         projected strain on a grid (injections)              [1 thread / grid point]
 //
 // All reductions are in a fixed order, so results are bitwise reproducible.
@@ -482,8 +482,12 @@ __global__ __launch_bounds__(64) void k_event_scales(NodeArgs a) {
 // Full-grid likelihood (no binning), FP64: one block of 256 per chain.
 // h_d(f) = h0fac_d K_d amp0 f^(-7/6) exp(-2 pi i (sum_b (c0_b + dc_b) B_b(x) + f (tau0_d + dtau_d)))
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_loglike_full(FullArgs a) {
-    __shared__ double red[4];
+// One 512-thread workgroup per chain (8 wavefronts: two per SIMD, so a batch of a few hundred
+// chains keeps every SIMD busy; the node model needs more registers than four per SIMD allow);
+// the wavefront sums are added in a fixed order.
+constexpr int kFullThreads = 512;
+__global__ __launch_bounds__(kFullThreads) void k_loglike_full(FullArgs a) {
+    __shared__ double red[kFullThreads / 64];
     const int64_t chain = blockIdx.x;
     const double* rec = a.recs + chain * kRecStride;
     const double status = rec[kRecStatus];
@@ -538,7 +542,11 @@ __global__ __launch_bounds__(256) void k_loglike_full(FullArgs a) {
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) a.lnl[chain] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kFullThreads / 64; ++i) t += red[i];
+        a.lnl[chain] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -619,7 +627,7 @@ hipError_t launch_node_tables(const NodeArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_loglike_full(const FullArgs& a, int64_t B, hipStream_t s, KTime kt) {
-    launch_k(k_loglike_full, dim3((unsigned)B), dim3(256), s, kt, a);
+    launch_k(k_loglike_full, dim3((unsigned)B), dim3(kFullThreads), s, kt, a);
     return hipGetLastError();
 }
 

@@ -10,7 +10,7 @@ import torch
 
 from . import _lib
 from ._lib import check
-from .rbl import PRECISIONS, _ptr, _stream_handle
+from .rbl import PRECISIONS, _ptr, _stream_handle, check_buffers
 
 
 def _host13(x):
@@ -42,6 +42,7 @@ class Mala:
         B = self.z.shape[0]
         xi = xi.contiguous()
         logu = logu.contiguous()
+        check_buffers(self.z, ((xi, (B, 13)), (logu, (B,))), None, 0)
         s, sp = _host13(step)
         l, lp = _host13(lo)
         h, hp = _host13(hi)

@@ -36,6 +36,28 @@ def _host_f64(x, shape=None):
     return a
 
 
+def check_buffers(theta, outs, workspace, workspace_bytes):
+    """Reject, before anything is enqueued, output and workspace buffers the library would
+    overrun: the C calls take no buffer sizes.  outs: ((tensor, shape), ...), each a
+    contiguous float64 tensor of exactly that shape on theta's device; workspace: a
+    contiguous uint8 tensor on that device with at least workspace_bytes bytes (None when
+    the call needs none)."""
+    dev = theta.device
+    for t, shape in outs:
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("output buffers must be tensors")
+        if t.device != dev or t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+            raise ValueError(f"output buffer must be a contiguous float64 tensor of shape {tuple(shape)} on {dev}; "
+                             f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+    if workspace is not None:
+        if not isinstance(workspace, torch.Tensor):
+            raise TypeError("workspace must be a tensor")
+        if workspace.device != dev or workspace.dtype != torch.uint8 or not workspace.is_contiguous():
+            raise ValueError(f"workspace must be a contiguous uint8 tensor on {dev}")
+        if workspace.numel() < workspace_bytes:
+            raise ValueError(f"workspace holds {workspace.numel()} bytes; this call needs {workspace_bytes}")
+
+
 def profile_enable(on=True, every=1):
     """Record HIP events around the library's kernels (benchmark timing) on the first and
     every `every`-th likelihood call; on=False turns timing off."""
@@ -144,9 +166,11 @@ class Event:
         check(_lib.lib().rbl_event_info(self._h, None, None, None, ctypes.byref(fb)))
         return fb.value
 
+    def workspace_bytes(self, B, with_grad=False):
+        return int(_lib.lib().rbl_workspace_bytes(self._h, int(B), int(bool(with_grad))))
+
     def workspace(self, B, with_grad=False):
-        n = _lib.lib().rbl_workspace_bytes(self._h, int(B), int(bool(with_grad)))
-        return torch.empty(max(n, 256), dtype=torch.uint8, device=self.device)
+        return torch.empty(max(self.workspace_bytes(B, with_grad), 256), dtype=torch.uint8, device=self.device)
 
     # -- evaluation -----------------------------------------------------------------
     def _theta(self, theta):
@@ -161,6 +185,7 @@ class Event:
         B = theta.shape[0]
         lnl = torch.empty(B, dtype=torch.float64, device=theta.device) if out is None else out
         ws = self.workspace(B) if workspace is None else workspace
+        check_buffers(theta, ((lnl, (B,)),), ws, self.workspace_bytes(B))
         check(_lib.lib().rbl_loglike(self._h, _ptr(theta), B, PRECISIONS[precision], _ptr(lnl),
                                      _ptr(ws), _stream_handle(theta.device)))
         return lnl
@@ -174,6 +199,7 @@ class Event:
         else:
             lnl, grad = out
         ws = self.workspace(B, True) if workspace is None else workspace
+        check_buffers(theta, ((lnl, (B,)), (grad, (B, 13))), ws, self.workspace_bytes(B, True))
         check(_lib.lib().rbl_loglike_grad(self._h, _ptr(theta), B, PRECISIONS[precision], _ptr(lnl),
                                           _ptr(grad), _ptr(ws), _stream_handle(theta.device)))
         return lnl, grad
@@ -183,6 +209,7 @@ class Event:
         B = theta.shape[0]
         lnl = torch.empty(B, dtype=torch.float64, device=theta.device) if out is None else out
         ws = self.workspace(B) if workspace is None else workspace
+        check_buffers(theta, ((lnl, (B,)),), ws, self.workspace_bytes(B))
         check(_lib.lib().rbl_loglike_full(self._h, _ptr(theta), B, _ptr(lnl), _ptr(ws),
                                           _stream_handle(theta.device)))
         return lnl

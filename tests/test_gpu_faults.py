@@ -69,3 +69,23 @@ def test_injected_allocation_failure_in_server(lib):
         lnl, grad, _ = srv.wait(srv.submit(eid, w["theta"], precision="fp64"))
         want_l, want_g = gev.loglike_grad(torch.as_tensor(w["theta"], dtype=torch.float64, device="cuda"))
         assert np.array_equal(lnl, want_l.cpu().numpy()) and np.array_equal(grad, want_g.cpu().numpy())
+
+
+def test_binding_refuses_undersized_workspace_and_short_outputs():
+    """A workspace sized for the lnL alone, or a short output, is refused by the binding
+    before anything is enqueued; the library then still gives the same results."""
+    ev, w = oracle_event("tf2_1det_32s", batch=64)
+    gev = gpu_event(ev)
+    t = torch.as_tensor(w["theta"], dtype=torch.float64, device="cuda")
+    B = t.shape[0]
+    want_l, want_g = gev.loglike_grad(t)
+    small = gev.workspace(B, with_grad=False)
+    with pytest.raises(ValueError):
+        gev.loglike_grad(t, workspace=small)
+    with pytest.raises(ValueError):
+        gev.loglike(t, out=torch.empty(B - 1, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        gev.loglike_grad(t, out=(torch.empty(B, dtype=torch.float64, device="cuda"),
+                                 torch.empty((B, 13), dtype=torch.float32, device="cuda")))
+    got_l, got_g = gev.loglike_grad(t)
+    assert torch.equal(got_l, want_l) and torch.equal(got_g, want_g)

@@ -157,3 +157,28 @@ def test_fault_injection_on_cpu():
         assert b"allocation" in L.rbl_last_error()
     finally:
         L.rbl_debug_inject_fault(_lib.RBL_FAULT_ALLOC, 0)
+
+
+def test_binding_rejects_undersized_or_wrong_buffers_before_any_call():
+    """The C calls take no buffer sizes, so the binding refuses buffers they would overrun
+    (checked with host tensors: the rule is the same on the device)."""
+    import torch
+    from paper_2404_11397_amd.rbl import check_buffers
+    B = 8
+    th = torch.zeros((B, 13), dtype=torch.float64)
+    ok_l, ok_g = torch.zeros(B, dtype=torch.float64), torch.zeros((B, 13), dtype=torch.float64)
+    ws = torch.zeros(1000, dtype=torch.uint8)
+    check_buffers(th, ((ok_l, (B,)), (ok_g, (B, 13))), ws, 1000)
+    bad = [
+        (((ok_l, (B,)),), ws, 1001),                                              # workspace too small
+        (((ok_l, (B,)),), torch.zeros(1000, dtype=torch.float32), 10),            # workspace dtype
+        (((ok_l, (B,)),), torch.zeros(2000, dtype=torch.uint8)[::2], 10),         # not contiguous
+        (((torch.zeros(B - 1, dtype=torch.float64), (B,)),), ws, 10),             # short output
+        (((torch.zeros(B, dtype=torch.float32), (B,)),), ws, 10),                 # float32 output
+        (((torch.zeros((13, B), dtype=torch.float64).t(), (B, 13)),), ws, 10),    # transposed view
+    ]
+    for outs, w, need in bad:
+        with pytest.raises(ValueError):
+            check_buffers(th, outs, w, need)
+    with pytest.raises(TypeError):
+        check_buffers(th, ((np.zeros(B), (B,)),), ws, 10)

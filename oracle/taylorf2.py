@@ -21,9 +21,11 @@ f^(-7/6) c / (1 Mpc); no spin or tidal amplitude corrections and no
 high-frequency cut-off (the ratio of the relative-binning scheme needs a
 non-zero reference across the band).
 
-The point-particle and spin-orbit coefficients are pinned in the tests by
-re-deriving them from the PN binding energy and flux; the tidal ones by the
-paper's Eq. (8) form.  The 3PN spin-spin terms are not pinned (parity unpinned).
+Pins (tests/test_oracle_taylorf2.py): every point-particle, spin-orbit and spin-spin
+coefficient is re-derived from the PN binding energy and flux (which are in turn checked
+against the Kerr test-mass limit); the tidal ones against the paper's Eq. (8) form; the
+amplitude against the stationary-phase amplitude of the Newtonian quadrupole chirp; the
+mass conversion by the round trip from component masses.
 """
 import numpy as np
 

@@ -113,6 +113,25 @@ int rbl_loglike(const rbl_event *ev, const double *theta_dev, int64_t B, int32_t
 int rbl_loglike_grad(const rbl_event *ev, const double *theta_dev, int64_t B, int32_t precision,
                      double *lnl_dev, double *grad_dev, void *workspace, void *hip_stream);
 
+/* Largest batch of rbl_loglike_grad_noalloc. */
+#define RBL_NOALLOC_MAX_CHAINS 16384
+
+/* rbl_loglike_grad for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): no workspace argument and
+ * no allocation.  Same arguments otherwise, same kernels, same results as rbl_loglike_grad.
+ * The per-chain records and Jacobians live in a static device array of the library, sized
+ * for RBL_NOALLOC_MAX_CHAINS chains (33 MiB), of which each GPU holds its own copy from
+ * library load until the process ends.  The call makes no hipMalloc, hipFree or other
+ * allocating call; its first call on a device looks up that device's copy of the array once.
+ * Every call on one GPU uses that GPU's array: calls that overlap on one GPU (on different
+ * streams or from several threads) race and corrupt each other's results, so serialise them
+ * (calls on one stream are serial).  The array keeps the last call's contents; nothing in it
+ * needs clearing before a call.  Errors: RBL_EINVAL for B > RBL_NOALLOC_MAX_CHAINS, B < 0,
+ * a null pointer, an unknown precision, or a current device other than the one the event was
+ * created on; RBL_EDEVICE for HIP errors.  B = 0 is a no-op. */
+int rbl_loglike_grad_noalloc(const rbl_event *ev, const double *theta_dev, int64_t B, int32_t precision,
+                             double *lnl_dev, double *grad_dev, void *hip_stream);
+
 /* Full-grid lnL (Eqs. (2)-(3) without binning), FP64; needs RBL_KEEP_GRID.
  * Workspace as for rbl_loglike.  Used for validation and to report the binning error. */
 int rbl_loglike_full(const rbl_event *ev, const double *theta_dev, int64_t B, double *lnl_dev,

@@ -22,8 +22,9 @@ EXPORTS = ("rbl_event_create", "rbl_event_free", "rbl_workspace_bytes", "rbl_log
            "rbl_last_error", "rbl_server_create", "rbl_server_add_event", "rbl_server_remove_event",
            "rbl_server_submit", "rbl_server_wait", "rbl_server_get_stats", "rbl_server_destroy", "rbl_clock_ns",
            "rbl_event_footprint_bytes", "rbl_debug_inject_fault", "rbl_mala_workspace_bytes", "rbl_mala_init",
-           "rbl_mala_step")
+           "rbl_mala_step", "rbl_loglike_grad_noalloc")
 RBL_FAULT_ALLOC, RBL_FAULT_LAUNCH = 0, 1
+RBL_NOALLOC_MAX_CHAINS = 16384
 RBL_SERVE_NO_GRAPHS, RBL_SERVE_SPIN = 0x1, 0x2
 
 
@@ -76,6 +77,8 @@ def lib():
     L.rbl_loglike.restype = ctypes.c_int
     L.rbl_loglike_grad.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp]
     L.rbl_loglike_grad.restype = ctypes.c_int
+    L.rbl_loglike_grad_noalloc.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+    L.rbl_loglike_grad_noalloc.restype = ctypes.c_int
     L.rbl_loglike_full.argtypes = [vp, vp, i64, vp, vp, vp]
     L.rbl_loglike_full.restype = ctypes.c_int
     L.rbl_strain.argtypes = [i32, i32, vp, vp, dbl, dbl, dbl, i64, vp, i32, vp, vp]

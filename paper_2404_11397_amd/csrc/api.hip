@@ -431,6 +431,7 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     dv.mu_sum = na.mu_sum;
     ev->footprint = (int64_t)sizeof(double) * (nd * nb * 7 + node_doubles) +
                     ((desc->flags & RBL_KEEP_GRID) ? (int64_t)sizeof(double) * 3 * nd * n : 0);
+    if (hipGetDevice(&ev->device) != hipSuccess) ev->device = -1;
     *out = ev;
     return RBL_OK;
 }

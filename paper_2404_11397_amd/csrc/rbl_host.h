@@ -47,6 +47,7 @@ inline int64_t workspace_bytes(int64_t B, bool with_grad) {
 // A resident event: immutable after rbl_event_create.
 struct rbl_event {
     int32_t n_det = 0, n_bins = 0, n_nodes = 0, n_nodes_pad = 0, waveform = 0;
+    int32_t device = -1;  // the device current at rbl_event_create (holds the event's buffers)
     uint32_t flags = 0;
     int64_t n_freq = 0;
     double f_low = 0, delta_f = 0, gmst = 0;

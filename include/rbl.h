@@ -220,9 +220,11 @@ int rbl_mala_step(const rbl_event *ev, double *z_dev, double *lnl_dev, double *g
  * or can be allocated within the budget (idle buffers of other classes are released to
  * make room); otherwise they wait (back-pressure).  Admitted requests run concurrently,
  * one per stream.  Each runs as one persistent hipGraph replay (copy in, per-chain setup,
- * likelihood kernel, copy out), captured on first use for its (buffer, event, B,
- * precision, gradient) and reused afterwards; RBL_SERVE_NO_GRAPHS makes plain launches
- * instead.  Results are bitwise identical to rbl_loglike / rbl_loglike_grad on the same
+ * likelihood kernel, copy out) kept per (buffer, event, B, precision, gradient); a request
+ * with no graph yet runs as plain launches, and its graph is captured the next time the
+ * worker is idle, so that no capture delays a request; RBL_SERVE_NO_GRAPHS makes plain
+ * launches always.  While requests are in flight the worker polls their completion
+ * events (yielding the core between polls).  Results are bitwise identical to rbl_loglike / rbl_loglike_grad on the same
  * theta: no value is reduced across chains or requests.
  *
  * Times are host CLOCK_MONOTONIC nanoseconds (rbl_clock_ns). */

@@ -35,6 +35,23 @@ from f_merger to 1.2 f_merger (McKechan et al. 2010), with the merger frequency
 M f_merger = 0.3586 / (2 pi) sqrt(X_min/X_max) (1 + 3.354e-2 kappa + 4.315e-5 kappa^2)
 / (1 + 7.542e-2 kappa + 2.236e-4 kappa^2).
 
+Sources of the recalled constants (restated from memory of the publications; the
+publications are not available here, so their equation and table numbers are not
+checked, and the stand-in's parity with the published IMRPhenomD_NRTidalv2 is unpinned):
+  * N52, N3, D1, D2 -- the Pade fit of the NRTidalv2 tidal phase, and the tidal amplitude
+    correction (449/108, 22672/9, 2.89, 13477.8): Dietrich, Samajdar, Khan et al. 2019,
+    "Improving the NRTidal model for binary neutron star systems", Phys. Rev. D 100, 044003;
+  * the merger-frequency fit (0.3586, 3.354e-2, 4.315e-5, 7.542e-2, 2.236e-4): Dietrich,
+    Bernuzzi & Tichy 2017 ("Closed-form tidal approximants for binary neutron star
+    gravitational waveforms", Phys. Rev. D 96, 121501), as used by NRTidal;
+  * S4, S5, T0, T2, T3 -- aligned-spin final-spin fit: Barausse & Rezzolla 2009, ApJ 704 L40;
+  * QNM_F, QNM_Q -- l = m = 2, n = 0 fits of Berti, Cardoso & Will 2006, Phys. Rev. D 73,
+    064030.
+What is pinned (tests/test_oracle_nrtv2.py): the C1 region joins, the reduction to TaylorF2
+below Mf = 0.018, the Pade expansion against the PN tidal series and the TaylorF2 5PN term,
+zero deformability, the taper limits, the ringdown fits against Schwarzschild and the
+equal-mass final spin (to the fits' accuracy), and the likelihood identities.
+
 All functions accept numpy arrays or oracle.ad Duals for the parameters.
 """
 import numpy as np

@@ -17,6 +17,10 @@
 // / (1 + 13477.8 x^4); w the Planck taper from f_merger to 1.2 f_merger with
 // M f_merger = 0.3586/(2 pi) sqrt(X_min/X_max) (1 + 3.354e-2 k + 4.315e-5 k^2)
 // / (1 + 7.542e-2 k + 2.236e-4 k^2).
+// The fit constants are restated from the publications named above (the NRTidalv2 Pade and
+// amplitude fits: Dietrich, Samajdar, Khan et al. 2019; the merger frequency: Dietrich,
+// Bernuzzi & Tichy 2017); with no calibration tables at hand this is a structural stand-in
+// of IMRPhenomD_NRTidalv2 whose agreement with the published model is not established.
 #pragma once
 #include "rbl_physics.h"
 

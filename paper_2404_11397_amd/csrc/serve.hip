@@ -4,9 +4,14 @@
 // Callers queue requests (rbl_server_submit) and block on tickets (rbl_server_wait).
 // The worker loop: (1) reap finished requests (event query per stream), copying the
 // results from pinned staging to the caller's buffers; (2) admit queued requests in
-// FIFO order while a stream is free and a buffer fits the HBM budget; (3) sleep on a
-// condition variable when nothing is queued or running, otherwise yield and poll.
-// Every launch is either one graph replay or the same operations issued one by one.
+// FIFO order while a stream is free and a buffer fits the HBM budget; (3) while requests
+// are in flight, poll their completion events, yielding the core between polls; when
+// nothing is queued or running, capture one pending graph if any, else sleep on a
+// condition variable (or keep polling with RBL_SERVE_SPIN).
+// Every launch is either one graph replay or the same operations issued one by one.  A
+// request whose (buffer, event, batch, precision, gradient) has no graph yet runs as plain
+// launches, and its graph is captured later, when the worker is idle: a capture never
+// delays a request in flight.
 #include <time.h>
 
 #include <algorithm>
@@ -89,6 +94,13 @@ struct Slot {
 
 using GraphKey = std::tuple<uint64_t, int32_t, int64_t, int32_t, int32_t>;  // buffer, event, B, precision, grad
 
+// A graph to capture when the worker is idle: what enqueue() needs of the request.
+struct PendingCapture {
+    GraphKey key;
+    const rbl_event* ev;
+    Buffer* buf;
+};
+
 }  // namespace
 
 struct rbl_server {
@@ -109,6 +121,7 @@ struct rbl_server {
     std::vector<std::unique_ptr<Buffer>> bufs;
     uint64_t next_buf = 1;
     std::map<GraphKey, hipGraphExec_t> graphs;
+    std::vector<PendingCapture> pending;  // graphs to capture when idle
     rbl_server_stats st{};
     bool stop = false;
     std::thread worker;
@@ -127,6 +140,11 @@ void drop_graphs_if(rbl_server* S, uint64_t buf_id, int32_t event) {
             ++it;
         }
     }
+    S->pending.erase(std::remove_if(S->pending.begin(), S->pending.end(),
+                                    [&](const PendingCapture& p) {
+                                        return std::get<0>(p.key) == buf_id || std::get<1>(p.key) == event;
+                                    }),
+                     S->pending.end());
 }
 
 void free_buffer_memory(Buffer* b) {
@@ -255,9 +273,9 @@ void launch(rbl_server* S, Request* r, Buffer* b, int si) {
         auto it = S->graphs.find(k);
         if (it != S->graphs.end()) {
             ex = it->second;
-        } else if ((ex = capture(r, b, sl.s)) != nullptr) {
-            S->graphs.emplace(k, ex);
-            S->st.graphs++;
+        } else if (std::none_of(S->pending.begin(), S->pending.end(),
+                                [&](const PendingCapture& p) { return p.key == k; })) {
+            S->pending.push_back(PendingCapture{k, r->ev, b});
         }
     }
     if (ex) {
@@ -278,6 +296,23 @@ void launch(rbl_server* S, Request* r, Buffer* b, int si) {
     sl.cur = r;
     S->st.in_flight++;
     S->st.max_in_flight = std::max(S->st.max_in_flight, S->st.in_flight);
+}
+
+// Capture one pending graph on an idle stream (called only with nothing in flight).
+void capture_one(rbl_server* S) {
+    const PendingCapture p = S->pending.back();
+    S->pending.pop_back();
+    if (S->graphs.count(p.key)) return;
+    Request r;
+    r.event = std::get<1>(p.key);
+    r.ev = p.ev;
+    r.B = std::get<2>(p.key);
+    r.precision = std::get<3>(p.key);
+    r.grad = std::get<4>(p.key) != 0;
+    if (hipGraphExec_t ex = capture(&r, p.buf, S->slots[0].s)) {
+        S->graphs.emplace(p.key, ex);
+        S->st.graphs++;
+    }
 }
 
 bool reap(rbl_server* S) {
@@ -347,6 +382,10 @@ void worker_main(rbl_server* S) {
             S->queue.pop_front();
             complete(S, r, fail(RBL_ENOMEM, "rbl_server: request buffer does not fit in the HBM budget"));
             S->cv_done.notify_all();
+            continue;
+        }
+        if (!S->pending.empty() && !S->stop) {
+            capture_one(S);
             continue;
         }
         if (S->stop) break;

@@ -56,3 +56,31 @@ def rb_condition_scale(ev, theta):
         tot = tot + (np.abs(s["A0"][d]) * np.abs(r0) + np.abs(s["A1"][d]) * np.abs(r1)
                      + 0.5 * s["B0"][d] * np.abs(r0) ** 2 + np.abs(s["B1"][d]) * np.abs(r0) * np.abs(r1)).sum(-1)
     return tot
+
+
+def serving_oracle_event(eid):
+    """Serving event `eid` with its configured injection, made by the oracle.  An
+    IMRPhenomD_NRTidalv2 event whose untapered reference amplitude reaches zero inside the
+    band (the ratio of Eq. (4) would be undefined there) is analysed on a band that ends at
+    the last grid point where the tapered injection is non-zero, i.e. just below the end
+    of the reference's taper.  Returns (oracle Event, spec, theta pool, band cut [Hz] or
+    None)."""
+    from oracle import phenomd_nrtv2
+    sp = synth.serving_event(eid)
+    x = synth.serving_inputs(sp)
+    f_low, df, n = x["f_low"], x["delta_f"], x["n_freq"]
+    f = f_low + df * np.arange(n)
+    th0 = sp["theta_inj"]
+    h = np.stack([y[0] for y in W.strain(f, th0, x["tensors"], x["vertices"], sp["gmst"], sp["waveform"], True)])
+    cut = None
+    if sp["waveform"] == "phenomd_nrtv2":
+        a0 = np.ravel(phenomd_nrtv2.amplitude_factor(f, *th0[:6], taper=False))
+        if np.any(a0 <= 0.0):
+            n = int(np.nonzero(np.any(np.abs(h) > 0.0, axis=0))[0][-1]) + 1
+            cut = float(f[n - 1])
+    ev = L.Event(f=f[:n], delta_f=df, psd=x["psd"][:, :n], data=h[:, :n] + x["noise"][:, :n],
+                 tensors=x["tensors"], vertices=x["vertices"], gmst=sp["gmst"], approximant=sp["waveform"])
+    ev.theta_ref = th0
+    ev.edges = binning.pn_bin_edges(f_low, df, n, sp["n_bins"])
+    L.prepare(ev)
+    return ev, sp, x["pool"], cut

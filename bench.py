@@ -27,6 +27,8 @@ import synth  # noqa: E402
 
 # Peaks of one MI355X (vendor figures): FP64 vector 78.6 TFLOP/s, HBM 8 TB/s.
 PEAK_FP64_TFLOPS = 78.6
+NRTV2_NOTE = ("unpinned: IMRPhenomD_NRTidalv2 here is a structural stand-in (the published calibration "
+              "tables are not available); GPU parity is against the oracle's identical stand-in")
 PEAK_HBM_GBS = 8000.0
 
 
@@ -59,6 +61,36 @@ def flops_per_eval(n_nodes, n_det, grad, waveform="taylorf2"):
     return n_nodes * per_node, setup
 
 
+def flops_mixed_split(n_nodes, n_det, grad, waveform="taylorf2"):
+    """(FP64, FP32) flops per eval of the mixed form, the split of the same operations as
+    flops_per_eval: FP64 keeps the edge phase (TaylorF2 basis 28 / IMRPhenomD_NRTidalv2 node
+    model 110), per detector the delay term (2), the exact reduction to revolutions (2) and
+    the FP64 accumulation of the per-edge terms (4; gradient 6 more), the gradient's basis or
+    node-parameter accumulations (20 / 180) and the per-chain setup; FP32 takes per detector
+    the hardware sin/cos (two quarter-rate instructions: 8), the ratio (6; NRTidalv2 + 2 for
+    the amplitude ratio) and the remaining binned products (10; gradient 20)."""
+    amp = 0 if waveform == "taylorf2" else 2
+    f64 = (28 if waveform == "taylorf2" else 110) + n_det * (2 + 2 + 4)
+    f32 = n_det * (8 + 6 + amp + 10)
+    if grad:
+        f64 += (20 if waveform == "taylorf2" else 180) + 6 * n_det
+        f32 += 20 * n_det
+    _, setup = flops_per_eval(n_nodes, n_det, grad, waveform)
+    return n_nodes * f64, n_nodes * f32, setup
+
+
+PEAK_FP32_TFLOPS = 157.3
+
+
+def mixed_roofline(n_nodes, n_det, grad, waveform, chains, kernel_us):
+    """Roofline of a mixed-form kernel: t_bound = F64 / P64 + F32 / P32 for its modelled
+    flop split; frac = t_bound / measured kernel time."""
+    f64, f32, _ = flops_mixed_split(n_nodes, n_det, grad, waveform)
+    t_bound = chains * (f64 / (PEAK_FP64_TFLOPS * 1e12) + f32 / (PEAK_FP32_TFLOPS * 1e12))
+    return {"f64_flops_per_eval": f64, "f32_flops_per_eval": f32, "t_bound_us": t_bound * 1e6,
+            "frac": t_bound / (kernel_us * 1e-6)}
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -66,7 +98,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--no-nrtv2", action="store_true", help="skip the IMRPhenomD_NRTidalv2 forms")
     p.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     p.add_argument("--serve-requests", type=int, default=2000)
@@ -99,101 +131,207 @@ def build_event(torch, workload, keep_grid=False):
     return ev, w, edges, data
 
 
-def cpu_baseline(w, edges, data_host, theta, seconds):
-    """Time the FP64 oracle (lnL + dual-number gradient) on a bounded sample."""
+def _oracle_event(workload):
+    """The workload's event built entirely by the oracle (its own injection and bins)."""
+    from oracle import binning
     from oracle import likelihood as L
-    ev = L.Event(f=w["f"], delta_f=w["delta_f"], psd=w["psd"], data=data_host, tensors=w["tensors"],
-                 vertices=w["vertices"], gmst=w["gmst"], approximant=w["waveform"],
-                 edges=np.asarray(edges), theta_ref=w["theta_inj"])
+    from oracle import waveform as W
+    w = synth.workload(workload)
+    ev = L.Event(f=w["f"], delta_f=w["delta_f"], psd=w["psd"], data=None, tensors=w["tensors"],
+                 vertices=w["vertices"], gmst=w["gmst"], approximant=w["waveform"])
+    h = W.strain(w["f"], w["theta_inj"], w["tensors"], w["vertices"], w["gmst"], w["waveform"], True)
+    ev.data = np.stack([x[0] for x in h]) + w["noise"]
+    ev.theta_ref = w["theta_inj"]
+    ev.edges = binning.pn_bin_edges(w["f_low"], w["delta_f"], w["n_freq"], w["n_bins"])
     L.prepare(ev)
-    chunk = 32
-    done = 0
-    t0 = time.perf_counter()
+    return ev, w["theta"]
+
+
+_CPU = {}
+CPU_CHUNK = 32
+
+
+def _cpu_worker(args):
+    """Oracle lnL + dual-number gradient on chunks of the batch for `seconds` (one process)."""
+    from oracle import likelihood as L
+    offset, seconds = args
+    ev, theta = _CPU["ev"], _CPU["theta"]
+    done, t0 = 0, time.perf_counter()
     while time.perf_counter() - t0 < seconds:
-        lo = done % len(theta)
-        L.loglike_rb_grad(ev, theta[lo:lo + chunk])
-        done += chunk
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} chain evaluations cycling through the batch in chunks of {chunk} "
-                      f"(lnL + dual-number gradient), {dt:.1f} s, numpy FP64 single thread"}
+        lo = (offset + done) % (len(theta) - CPU_CHUNK)
+        L.loglike_rb_grad(ev, theta[lo:lo + CPU_CHUNK])
+        done += CPU_CHUNK
+    return done, time.perf_counter() - t0
 
 
-TIMING_EVERY = 8  # kernel start/stop events on the first and every 8th call of a timed region
+def cpu_baseline(workload, seconds):
+    """The FP64 oracle (lnL + dual-number gradient) timed on a bounded sample of the workload:
+    once in one process, once in a pool of processes over the host cores this job may use
+    (at most 16, the host share of one GPU).  Runs before the GPU is initialised, on the
+    oracle's own injection of the same workload (its timing does not depend on the data)."""
+    import multiprocessing as mp
+    _CPU["ev"], _CPU["theta"] = _oracle_event(workload)
+    one, dt1 = _cpu_worker((0, seconds))
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_cpu_worker, [(k * 997, seconds) for k in range(cores)])
+    wall = time.perf_counter() - t0
+    total = sum(r[0] for r in res)
+    return {"value": total / wall, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"{total} chain evaluations (lnL + dual-number gradient, chunks of {CPU_CHUNK} chains cycling "
+                      f"through the {workload} batch) in {wall:.1f} s by {cores} processes of numpy FP64, one "
+                      f"thread each",
+            "single_core": {"value": one / dt1, "unit": "evals/s", "cores": 1,
+                            "sample": f"{one} chain evaluations in {dt1:.1f} s, one process"}}
+
+
+KERNEL_PASS_CALLS = 50  # calls of the separate pass that takes the kernel times
 
 
 def time_calls(torch, fn, steps, warmup):
-    """Wall time per call and HIP-event kernel times (main, setup) per timed call.  The events
-    are taken inside the timed region on a sample of the calls (TIMING_EVERY): each timed call
-    costs a few microseconds of device time."""
+    """Wall time of `steps` calls (no kernel timing inside the timed region), then the
+    average kernel durations (main, setup) [us] from a separate pass of
+    min(steps, KERNEL_PASS_CALLS) calls, each stamped with HIP start/stop events that the
+    runtime records at the kernels' own start and end on the launch stream."""
     from paper_2404_11397_amd import profile_enable, profile_read
     for _ in range(warmup):
         fn()
-    torch.cuda.synchronize()
-    profile_enable(True, every=TIMING_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         fn()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    profile_enable(True, every=1)
+    for _ in range(min(steps, KERNEL_PASS_CALLS)):
+        fn()
+    torch.cuda.synchronize()
     main_ms, setup_ms, calls = profile_read()
     profile_enable(False)
     return elapsed, main_ms / calls * 1e3, setup_ms / calls * 1e3
 
 
-def flops_full_point(n_det):
-    """Algorithmic FP64 flops per grid point of the full-band TaylorF2 lnL (Eqs. (2)-(3)):
-    x = f^(1/3) (20), 1/x (10), ln x (20), amplitude x^-3.5 (23), basis phase (28); per
-    detector the phase with delay (2), sin/cos (36), the projected strain (8), 1/S (10) and
-    the two inner-product terms (8)."""
-    return 101 + n_det * 64
+def full_flops(n_freq, chains, n_det, waveform="taylorf2"):
+    """Algorithmic FP64 flops of a full-band lnL batch (Eqs. (2)-(3) on every grid point).
+    Per grid point, shared by the batch: x = f^(1/3) (20), 1/x (10), ln x (20), f^(-7/6) (23),
+    the TaylorF2 basis (8) or x^5.78 (20 + 1), and per detector 1/S (10).  Per point and
+    chain: the TaylorF2 basis phase (20) or the IMRPhenomD_NRTidalv2 node model (110) and its
+    amplitude factor (1); per detector the phase with delay (2), sin/cos of a phase in
+    revolutions (36), the strain (8) and the two inner-product terms with their weight and
+    sum (10)."""
+    if waveform == "taylorf2":
+        shared, per_chain = 81 + 10 * n_det, 20 + 56 * n_det
+    else:
+        shared, per_chain = 94 + 10 * n_det, 111 + 56 * n_det
+    return n_freq * shared + n_freq * chains * per_chain
 
 
-def full_band(torch, steps):
-    """Full-band lnL (every grid point, no binning) on the 1-detector 32 s workload beside the
-    binned FP64 lnL on the same batch: throughput, and the binning error of Eq. (5)."""
-    ev, w, edges, data = build_event(torch, "tf2_1det_32s", keep_grid=True)
-    th = torch.as_tensor(w["theta"], device="cuda:0")
-    B = th.shape[0]
-    ws = ev.workspace(B, False)
-    full = torch.empty(B, dtype=torch.float64, device="cuda:0")
-    rb = torch.empty_like(full)
-    el_f, ku_f, su_f = time_calls(torch, lambda: ev.loglike_full(th, out=full, workspace=ws), steps, 3)
-    el_b, ku_b, su_b = time_calls(torch, lambda: ev.loglike(th, out=rb, workspace=ws), steps, 3)
-    torch.cuda.synchronize()
-    err = (rb - full).abs()
-    # The binning error where a sampler spends its time: draws around the injection with the
-    # spread of a diagonal inverse-Fisher estimate (sigma_i = 1 / |d lnL / d theta_i| there).
+def _near_draws(ev, w, B, rng):
+    """B draws around the injection with spreads 1/sqrt(-d2 lnL/dtheta_i2) there (the diagonal
+    of the observed information, from the library gradient)."""
     th0 = w["theta_inj"]
-    rng = np.random.default_rng(91)
-    probe = torch.as_tensor(th0 + 1e-9 * np.abs(th0) * rng.standard_normal((64, 13)), device="cuda:0")
-    g = ev.loglike_grad(probe)[1].cpu().numpy()
-    sigma = np.minimum(1.0 / np.sqrt(np.mean(g * g, axis=0) + 1e-300), 0.05 * np.abs(th0) + 1e-3)
+    sigma = diag_information_sigma(
+        lambda x: ev.loglike_grad(torch_mod().as_tensor(x, device="cuda:0"))[1].cpu().numpy(), th0, WIDTHS,
+        0.05 * np.abs(th0) + 1e-3)
     near = th0 + sigma * rng.standard_normal((B, 13))
     near[:, 1] = np.clip(near[:, 1], 0.05, 1.0)
     near[:, 2:4] = np.clip(near[:, 2:4], -0.99, 0.99)
     near[:, 4:6] = np.maximum(near[:, 4:6], 0.0)
     near[:, 9] = np.clip(near[:, 9], 1e-3, np.pi - 1e-3)
     near[:, 12] = np.clip(near[:, 12], -np.pi / 2 + 1e-3, np.pi / 2 - 1e-3)
-    tn = torch.as_tensor(near, device="cuda:0")
-    full_n = ev.loglike_full(tn)
-    err_n = (ev.loglike(tn) - full_n).abs()
-    fl = flops_full_point(len(w["tensors"])) * w["n_freq"] * B
-    return {"workload": "TaylorF2 lnL, 1 det, 32 s, 20-1024 Hz (%d points), %d bins, %d chains" % (w["n_freq"], w["n_bins"], B),
-            "full_evals_per_s": B * steps / el_f, "full_kernel_us": ku_f,
-            "full_est_tflops": fl / (ku_f * 1e-6) / 1e12,
-            "full_est_frac_fp64_peak": fl / (ku_f * 1e-6) / 1e12 / PEAK_FP64_TFLOPS,
-            "binned_evals_per_s": B * steps / el_b, "binned_kernel_us": ku_b,
-            "kernel_speedup": ku_f / ku_b,
-            "binning_error_near_injection": {
-                "max_abs": float(err_n.max()), "median_abs": float(err_n.median()),
-                "lnl_range": [float(full_n.min()), float(full_n.max())],
-                "what": "chains drawn around the injection with the inverse-Fisher diagonal spread"},
+    return near
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+FULL_BAND_CASES = (("tf2_1det_32s", 256, None), ("tf2_3det_128s", 4096, None), ("nrtv2_3det_256s", 1024, 2048))
+
+
+def full_band(torch, steps):
+    """Full-band lnL (every grid point, no binning) beside the binned FP64 lnL on the same batch,
+    on the 1-detector 32 s, 3-detector 128 s and 3-detector 256 s workloads: throughput, the
+    full-band kernel against its roofline, and the binning error of Eq. (5) over each
+    workload's prior draws and around its injection."""
+    out = {}
+    for name, B, B_err in FULL_BAND_CASES:
+        ev, w, edges, data = build_event(torch, name, keep_grid=True)
+        nd = len(w["tensors"])
+        th_all = torch.as_tensor(w["theta"], device="cuda:0")
+        th = th_all[:B].contiguous()
+        ws = ev.workspace(max(B, B_err or 0), False)
+        full = torch.empty(B, dtype=torch.float64, device="cuda:0")
+        rb = torch.empty_like(full)
+        n_steps = steps if nd == 1 else max(3, steps // 4)
+        el_f, ku_f, su_f = time_calls(torch, lambda: ev.loglike_full(th, out=full, workspace=ws[:ev.workspace_bytes(B)]),
+                                      n_steps, 2)
+        el_b, ku_b, su_b = time_calls(torch, lambda: ev.loglike(th, out=rb, workspace=ws[:ev.workspace_bytes(B)]),
+                                      n_steps, 2)
+        fl = full_flops(w["n_freq"], B, nd, w["waveform"])
+        # binning error over the workload's prior draws and around the injection
+        the = th_all[:B_err].contiguous() if B_err else th
+        err_p = (ev.loglike(the) - ev.loglike_full(the)).abs()
+        near = torch.as_tensor(_near_draws(ev, w, min(B, 1024), np.random.default_rng(91)), device="cuda:0")
+        full_n = ev.loglike_full(near)
+        err_n = (ev.loglike(near) - full_n).abs()
+        out[name] = {
+            "workload": f"{w['waveform']}, {nd} det, {w['duration']:.0f} s, {w['n_freq']} points per detector, "
+                        f"{w['n_bins']} bins, {B} chains",
+            "full_evals_per_s": B * n_steps / el_f, "full_kernel_us": ku_f, "full_setup_us": su_f,
+            "roofline": {"bound": "alu", "achieved": fl / (ku_f * 1e-6) / 1e12, "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": fl / (ku_f * 1e-6) / 1e12 / PEAK_FP64_TFLOPS,
+                         "flops_per_launch": fl, "kernel": "k_full_tiles"},
+            "binned_evals_per_s": B * n_steps / el_b, "binned_kernel_us": ku_b, "kernel_speedup": ku_f / ku_b,
             "binning_error_prior_draws": {
-                "max_abs": float(err.max()), "median_abs": float(err.median()),
-                "what": "the workload's prior-wide draws, far from the reference, where the linear "
-                        "model of Eq. (5) is not meant to hold"}}
+                "chains": int(the.shape[0]), "max_abs": float(err_p.max()), "median_abs": float(err_p.median()),
+                "what": "the workload's prior draws; far from the reference the linear model of Eq. (5) is not "
+                        "meant to hold"},
+            "binning_error_near_injection": {
+                "chains": int(near.shape[0]), "max_abs": float(err_n.max()), "median_abs": float(err_n.median()),
+                "lnl_range": [float(full_n.min()), float(full_n.max())],
+                "what": "draws around the injection with spreads 1/sqrt(-d2 lnL/dtheta_i2) there (diagonal of the "
+                        "observed information, central differences of the library gradient)"}}
+        del ev, data
+        progress(f"full band {name} done")
+    return out
+
+
+def reference_search(torch, lam=2048, generations=250):
+    """The CMA-ES reference-parameter search (rbl_ref_search) on a noise-free injection into the
+    3-detector 128 s TaylorF2 workload, over the GW170817 prior box from its centre: wall time,
+    candidate evaluations per second, and how far below the peak (<h, h>/2 at the injection)
+    the best candidate ends."""
+    from paper_2404_11397_amd import Event, bin_edges, ref_search, strain
+    w = synth.workload("tf2_3det_128s", batch=1)
+    dev = torch.device("cuda:0")
+    th0 = w["theta_inj"]
+    h = strain("taylorf2", w["tensors"], w["vertices"], w["gmst"], w["f_low"], w["delta_f"], w["n_freq"], th0,
+               device=dev)
+    ev = Event(h, torch.as_tensor(w["psd"], device=dev), w["tensors"], w["vertices"], w["gmst"], w["f_low"],
+               w["delta_f"], th0, bin_edges(w["f_low"], w["delta_f"], w["n_freq"], w["n_bins"]), keep_grid=True,
+               device=dev)
+    b = synth.PRIORS["gw170817"]
+    lo = np.array([b["Mc"][0], b["q"][0], b["chi"][0], b["chi"][0], b["L"][0], b["L"][0], b["dL"][0], b["tc"][0],
+                   0.0, 0.0, 0.0, 0.0, -np.pi / 2])
+    hi = np.array([b["Mc"][1], b["q"][1], b["chi"][1], b["chi"][1], b["L"][1], b["L"][1], b["dL"][1], b["tc"][1],
+                   2 * np.pi, np.pi, np.pi, 2 * np.pi, np.pi / 2])
+    normals = np.random.default_rng(9).standard_normal((generations, lam, 13))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    best, best_l, trace = ref_search(ev, lo, hi, 0.5 * (lo + hi), 0.3, normals)
+    dt = time.perf_counter() - t0
+    peak = float(ev.loglike_full(torch.as_tensor(th0[None, :], device=dev))[0])
+    return {"workload": "noise-free TaylorF2 injection, 3 det, 128 s, 259585 points per detector; GW170817 prior box, "
+                        "start at its centre",
+            "lambda": lam, "generations": generations, "seconds": dt, "candidate_evals_per_s": lam * generations / dt,
+            "lnl_peak": peak, "lnl_found": best_l, "delta_lnl": peak - best_l,
+            "generation_of_best": int(np.argmax(trace[:, 0] >= best_l)),
+            "found_minus_injection": (best - th0).tolist(),
+            "what": "rbl_ref_search: CMA-ES over the full-band lnL on the device, update on the host"}
 
 
 def summary_pass(torch, w, edges, data, psd, repeats=3):
@@ -264,8 +402,35 @@ def stored_traffic(kernel_tag):
     return None
 
 
-def forms_on(torch, ev, theta, lnl, grad, ws, steps, with_grad=True):
-    """evals/s and HIP-event kernel times of lnL and lnL+grad, FP64 and mixed."""
+WIDTHS = np.array([0.03, 0.875, 0.1, 0.1, 5000.0, 5000.0, 74.0, 0.2, 2 * np.pi, np.pi, np.pi, 2 * np.pi, np.pi])
+
+
+def mixed_error(torch, ev, theta, with_grad):
+    """The mixed form against the FP64 form on the same batch (the FP64 GPU path is the
+    oracle-pinned one): max and median |dlnL|, the largest prior-width-scaled gradient error
+    relative to the chain's largest scaled component, and the chains the mixed form's guard
+    computed in FP64 (results bitwise equal to the FP64 ones)."""
+    if with_grad:
+        l64, g64 = (x.clone() for x in ev.loglike_grad(theta, "fp64"))
+        l32, g32 = ev.loglike_grad(theta, "mixed")
+    else:
+        l64, l32 = ev.loglike(theta, "fp64").clone(), ev.loglike(theta, "mixed")
+    d = (l32 - l64).abs()
+    ok = torch.isfinite(d)
+    out = {"max_abs_dlnl": float(d[ok].max()), "median_abs_dlnl": float(d[ok].median()),
+           "chains": int(theta.shape[0]), "chains_guarded_to_fp64": int((l32 == l64).sum())}
+    if with_grad:
+        w = torch.as_tensor(WIDTHS, device=theta.device)
+        gs, ws = g32 * w, g64 * w
+        rel = (gs - ws).abs().max(dim=1).values / ws.abs().max(dim=1).values
+        out["max_grad_rel_err"] = float(rel[torch.isfinite(rel)].max())
+    return out
+
+
+def forms_on(torch, ev, theta, lnl, grad, ws, steps, with_grad=True, n_nodes=None, n_det=None,
+             waveform="taylorf2"):
+    """evals/s and kernel times of lnL and lnL+grad, FP64 and mixed; for the mixed rows
+    the error against FP64 and the mixed-form roofline."""
     B = theta.shape[0]
     out = {}
     combos = [("lnl", False), ("lnl_grad", True)] if with_grad else [("lnl", False)]
@@ -276,8 +441,12 @@ def forms_on(torch, ev, theta, lnl, grad, ws, steps, with_grad=True):
             else:
                 fn = lambda p=prec: ev.loglike(theta, p, out=lnl[:B], workspace=ws)  # noqa: E731
             el, ku, su = time_calls(torch, fn, steps, 3)
-            out[f"{tag}_{prec}"] = {"evals_per_s": B * steps / el, "us_per_call": el / steps * 1e6,
-                                    "kernel_us": ku, "setup_us": su}
+            row = {"evals_per_s": B * steps / el, "us_per_call": el / steps * 1e6, "kernel_us": ku, "setup_us": su}
+            if prec == "mixed":
+                row["error_vs_fp64"] = mixed_error(torch, ev, theta, g)
+                if n_nodes is not None:
+                    row["roofline_mixed"] = mixed_roofline(n_nodes, n_det, g, waveform, B, ku)
+            out[f"{tag}_{prec}"] = row
     return out
 
 
@@ -287,16 +456,18 @@ def nrtv2_forms(torch, steps):
     ev, w, edges, data = build_event(torch, "nrtv2_3det_256s_grad8192")
     nd, n_nodes = len(w["tensors"]), w["n_bins"] + 1
     res = {"workload": "IMRPhenomD_NRTidalv2: 3 det, 256 s, 20-2048 Hz (519169 pts/det), 1000 bins, SNR 12 "
-                       "injection; lnL+grad at 8192 chains (GW190425 prior, Mc window +-0.0025), lnL at 16384"}
+                       "injection; lnL+grad at 8192 chains (GW190425 prior, Mc window +-0.0025), lnL at 16384",
+           "parity_vs_published_model": NRTV2_NOTE}
     th = torch.as_tensor(w["theta"], device="cuda:0")
     B = th.shape[0]
     lnl = torch.empty(2 * B, dtype=torch.float64, device="cuda:0")
     grad = torch.empty((B, 13), dtype=torch.float64, device="cuda:0")
     ws = ev.workspace(2 * B, with_grad=True)
-    f = forms_on(torch, ev, th, lnl[:B], grad, ws, steps)
+    f = forms_on(torch, ev, th, lnl[:B], grad, ws, steps, n_nodes=n_nodes, n_det=nd, waveform="phenomd_nrtv2")
     w3 = synth.workload("nrtv2_3det_256s")
     th3 = torch.as_tensor(w3["theta"], device="cuda:0")
-    f.update({k + "_16384": v for k, v in forms_on(torch, ev, th3, lnl, grad, ws, steps, with_grad=False).items()})
+    f.update({k + "_16384": v for k, v in forms_on(torch, ev, th3, lnl, grad, ws, steps, with_grad=False,
+                                                    n_nodes=n_nodes, n_det=nd, waveform="phenomd_nrtv2").items()})
     for k, v in f.items():
         g = "grad" in k
         per, _ = flops_per_eval(n_nodes, nd, grad=g, waveform="phenomd_nrtv2")
@@ -313,42 +484,42 @@ def nrtv2_forms(torch, steps):
 
 
 def build_serving_events(torch):
-    """The 64 serving events.  An IMRPhenomD_NRTidalv2 event whose untapered reference
-    amplitude reaches zero inside the band (large tidal deformabilities: the tidal
-    amplitude correction outgrows the point-particle amplitude) is rejected by the
-    library (RBL_EREF); its injection then has Lambda1 and Lambda2 halved until the
-    reference is valid.  Returns the events, their theta pools, specs and the number
-    of events so adjusted."""
+    """The 64 serving events with their configured injections (library waveform + seeded
+    noise).  An IMRPhenomD_NRTidalv2 event whose untapered reference amplitude reaches zero
+    inside 20-2048 Hz is refused by the library (RBL_EREF: the ratio of Eq. (4) is undefined
+    there); it is analysed on a band that ends at the last grid point where the tapered
+    injection is non-zero, just below the end of the reference's taper (1.2 f_merger), with
+    its bins placed on that band.  Returns the events, their theta pools, specs and the
+    {event id: band end [Hz]} of the events so cut."""
     from paper_2404_11397_amd import Event, RblError, bin_edges, strain
     events, pools, specs = [], [], []
-    adjusted = 0
+    cuts = {}
     dev = torch.device("cuda:0")
     for eid in range(synth.N_SERVE_EVENTS):
         sp = synth.serving_event(eid)
         x = synth.serving_inputs(sp)
-        edges = bin_edges(x["f_low"], x["delta_f"], x["n_freq"], sp["n_bins"])
+        n = x["n_freq"]
         psd = torch.as_tensor(x["psd"], device=dev)
         noise = torch.as_tensor(x["noise"], device=dev)
-        th = sp["theta_inj"].copy()
-        for attempt in range(12):
-            h = strain(sp["waveform"], x["tensors"], x["vertices"], sp["gmst"], x["f_low"], x["delta_f"],
-                       x["n_freq"], th, device=dev)
-            try:
-                ev = Event(h + noise, psd, x["tensors"], x["vertices"], sp["gmst"], x["f_low"], x["delta_f"], th,
-                           edges, waveform=sp["waveform"], device=dev)
-                break
-            except RblError as e:
-                if e.code != -6 or sp["waveform"] != "phenomd_nrtv2" or attempt == 11:
-                    raise
-                th[4] *= 0.5
-                th[5] *= 0.5
-        adjusted += int(attempt > 0)
-        sp["theta_inj"] = th
+        th = sp["theta_inj"]
+        h = strain(sp["waveform"], x["tensors"], x["vertices"], sp["gmst"], x["f_low"], x["delta_f"], n, th,
+                   device=dev)
+        try:
+            ev = Event(h + noise, psd, x["tensors"], x["vertices"], sp["gmst"], x["f_low"], x["delta_f"], th,
+                       bin_edges(x["f_low"], x["delta_f"], n, sp["n_bins"]), waveform=sp["waveform"], device=dev)
+        except RblError as e:
+            if e.code != -6 or sp["waveform"] != "phenomd_nrtv2":
+                raise
+            n = int(torch.nonzero((h.abs() > 0).any(dim=0))[-1]) + 1
+            cuts[eid] = x["f_low"] + (n - 1) * x["delta_f"]
+            ev = Event((h + noise)[:, :n], psd[:, :n], x["tensors"], x["vertices"], sp["gmst"], x["f_low"],
+                       x["delta_f"], th, bin_edges(x["f_low"], x["delta_f"], n, sp["n_bins"]),
+                       waveform=sp["waveform"], device=dev)
         events.append(ev)
         pools.append([np.ascontiguousarray(p) for p in x["pool"]])
         specs.append(sp)
         del h, psd, noise
-    return events, pools, specs, adjusted
+    return events, pools, specs, cuts
 
 
 def run_stream(srv, ids, pools, n, rate, precision):
@@ -397,22 +568,29 @@ def serving(torch, n_requests):
     graph replays) and, for comparison, one FIFO with FP64 plain launches."""
     from paper_2404_11397_amd import Server
     t_build = time.perf_counter()
-    events, pools, specs, adjusted = build_serving_events(torch)
+    events, pools, specs, cuts = build_serving_events(torch)
     t_build = time.perf_counter() - t_build
     budget = 32 << 30
     res = {"workload": f"{synth.N_SERVE_EVENTS} resident events (1-3 det, 32-256 s, 100-1000 bins, TaylorF2 / "
                        f"IMRPhenomD_NRTidalv2, 256-4096 chains each); Poisson {synth.SERVE_RATE_HZ:.0f} req/s of "
                        "lnL+grad requests",
            "events_build_s": t_build, "hbm_budget_bytes": budget,
-           "nrtv2_events_with_halved_lambda": adjusted}
+           "injections": "as configured (no parameter changed)",
+           "nrtv2_events_with_band_cut": len(cuts),
+           "nrtv2_band_cut": "untapered reference amplitude reaches zero in band: the band ends at the last grid "
+                             "point of the tapered injection (below 1.2 f_merger); band ends [Hz]: "
+                             + ", ".join(f"{k}: {v:.0f}" for k, v in sorted(cuts.items())),
+           "nrtv2_parity_vs_published_model": NRTV2_NOTE}
     for tag, streams, graphs, spin, prec in (("server", 4, True, True, "mixed"),
                                              ("baseline_fifo_fp64_plain", 1, False, False, "fp64")):
         with Server(budget, n_streams=streams, graphs=graphs, spin=spin) as srv:
             ids = [srv.add_event(e) for e in events]
-            warm = [srv.submit(ids[e], pools[e][k], precision=prec) for e in range(len(events))
-                    for k in range(len(pools[e]))]
-            for t in warm:
-                srv.wait(t)
+            # warm-up: every (event, pool) once, one at a time (the buffers a light load
+            # uses), then a pause in which the idle worker captures their graphs
+            for e in range(len(events)):
+                for k in range(len(pools[e])):
+                    srv.wait(srv.submit(ids[e], pools[e][k], precision=prec))
+            time.sleep(1.0)
             r = run_stream(srv, ids, pools, n_requests, synth.SERVE_RATE_HZ, prec)
             r["saturation"] = [run_stream(srv, ids, pools, n_requests, rate, prec) for rate in (2000.0, 20000.0)]
             r["stats"] = srv.stats()
@@ -425,10 +603,9 @@ def serving(torch, n_requests):
 def mala_rate(torch, ev, w, steps):
     """Device MALA local steps (proposal, lnL+grad, accept) on the headline event: chain-steps/s.
 
-    Chains start around the injection with the spread of a diagonal Fisher estimate
-    (sigma_i = 1 / rms of dlnL/dz_i at the injection, i.e. inverse-Fisher), the step is
-    s_i = (f sigma_i)^2, and f is adapted during the untimed warm-up towards an acceptance
-    of about 0.6; the timed steps keep f fixed."""
+    Chains start around the injection with spreads sigma_i = 1/sqrt(-d2 lnL/dz_i2) there (the
+    diagonal of the observed information), the step is s_i = (f sigma_i)^2, and f is adapted
+    during the untimed warm-up towards an acceptance of about 0.6; the timed steps keep f fixed."""
     from paper_2404_11397_amd import Mala
     th0 = w["theta_inj"]
     z0 = th0.copy()
@@ -441,10 +618,8 @@ def mala_rate(torch, ev, w, steps):
     hi = np.array([b["Mc"][1], b["q"][1], b["chi"][1], b["chi"][1], b["L"][1], b["L"][1], b["dL"][1], b["tc"][1],
                    2 * np.pi, 1.0, np.pi, 2 * np.pi, 1.0])
     rng = np.random.default_rng(77)
-    probe = np.clip(z0 + 1e-7 * (hi - lo) * rng.standard_normal((B, 13)), lo, hi)
-    g = Mala(ev, torch.as_tensor(probe, device="cuda:0")).gz.cpu().numpy()
-    sigma = 1.0 / np.sqrt(np.mean(g * g, axis=0) + 1e-300)
-    sigma = np.minimum(sigma, 0.05 * (hi - lo))
+    sigma = diag_information_sigma(lambda x: Mala(ev, torch.as_tensor(x, device="cuda:0")).gz.cpu().numpy(),
+                                   z0, hi - lo, 0.05 * (hi - lo))
     start = np.clip(z0 + sigma * rng.standard_normal((B, 13)), lo, hi)
     ch = Mala(ev, torch.as_tensor(start, device="cuda:0"))
     gen = torch.Generator(device="cuda:0").manual_seed(7)
@@ -467,7 +642,13 @@ def mala_rate(torch, ev, w, steps):
     return {"chain_steps_per_s": B * steps / dt, "us_per_step": dt / steps * 1e6, "chains": B, "steps": steps,
             "acceptance": float(acc.sum()) / (B * steps), "step_factor": f, "precision": "fp64",
             "what": "rbl_mala_step on the headline event (proposal, setup + lnL+grad kernels, accept), chains "
-                    "around the injection, diagonal inverse-Fisher preconditioning, step adapted in warm-up"}
+                    "around the injection, preconditioned by the diagonal observed information, step adapted in "
+                    "warm-up"}
+
+
+def progress(msg):
+    """One line per finished section on stderr (stdout carries only the JSON result)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -477,9 +658,11 @@ def main():
                                    "chains with no exchange, so no multi-GPU figure is measured",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    workload = "tf2_3det_128s_grad8192"
+    cpu = None if args.no_cpu_baseline else cpu_baseline(workload, args.cpu_seconds)
+    progress("oracle CPU baseline done")
     import torch
 
-    workload = "tf2_3det_128s_grad8192"
     ev, w, edges, data = build_event(torch, workload)
     theta_np = w["theta"]
     B = theta_np.shape[0]
@@ -492,6 +675,7 @@ def main():
         ev.loglike_grad(theta, args.precision, out=(lnl, grad), workspace=ws)
 
     elapsed, kern_us, setup_us = time_calls(torch, step, args.steps, args.warmup)
+    progress(f"headline done: {B * args.steps / elapsed:.4g} evals/s")
 
     # per-call latency of a synchronised batch call
     lat = []
@@ -502,7 +686,8 @@ def main():
         lat.append((time.perf_counter() - t1) * 1e3)
     lat = np.array(lat)
 
-    forms = forms_on(torch, ev, theta, lnl, grad, ws, max(20, args.steps // 4))
+    forms = forms_on(torch, ev, theta, lnl, grad, ws, max(20, args.steps // 4), n_nodes=w["n_bins"] + 1,
+                     n_det=len(w["tensors"]))
 
     nd = len(w["tensors"])
     psd = torch.as_tensor(w["psd"], device="cuda:0")
@@ -533,8 +718,9 @@ def main():
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": None, "flops_per_eval": fl_kernel,
                      "avg_kernel_us": kern_us, "avg_setup_us": setup_us,
-                     "kernel_timing": f"HIP start/stop events on the kernel's own stream, on the first and every "
-                                      f"{TIMING_EVERY}th call of the timed region",
+                     "kernel_timing": f"HIP start/stop events recorded by the runtime at the kernel's own start "
+                                      f"and end on its launch stream, in a separate pass of "
+                                      f"{min(args.steps, KERNEL_PASS_CALLS)} calls after the timed region",
                      "kernel_source_hash": kernel_source_hash()},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "what": "one synchronised rbl_loglike_grad call over the 8192-chain batch"},
@@ -542,16 +728,22 @@ def main():
         "summary_pass": {"us": summ_us, "bytes": summ_bytes, "GB_per_s": summ_bytes / (summ_us * 1e-6) / 1e9,
                          "frac_of_hbm_peak": summ_bytes / (summ_us * 1e-6) / 1e9 / PEAK_HBM_GBS},
     }
+    progress("forms and summary pass done")
     out["mala"] = mala_rate(torch, ev, w, max(20, args.steps // 4))
+    progress("MALA done")
     out["full_band"] = full_band(torch, max(10, args.steps // 10))
+    out["reference_search"] = reference_search(torch)
+    progress("reference search done")
     tr = stored_traffic("k_loglike_grad_tf2_3det_128s_8192_fp64")
     if tr is not None:
         out["roofline"]["traffic"] = tr["hbm_bytes_per_launch"]
         out["roofline"]["traffic_detail"] = tr
     if not args.no_nrtv2:
         out["nrtv2"] = nrtv2_forms(torch, max(20, args.steps // 4))
+        progress("IMRPhenomD_NRTidalv2 forms done")
     if not args.no_serve:
         sv = serving(torch, args.serve_requests)
+        progress("serving done")
         out["serving"] = sv
         out["latency_ms"] = {"p50": sv["server"]["p50_ms"], "p99": sv["server"]["p99_ms"],
                              "what": "request latency (arrival to results in host memory) under the "
@@ -560,9 +752,8 @@ def main():
                              "batch_call_p99": float(np.percentile(lat, 99))}
     if args.calibrate_copy:
         out["copy_calibration"] = calibrate_copy(torch)
-    if not args.no_cpu_baseline:
-        data_host = data.cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(w, edges, data_host, theta_np, args.cpu_seconds)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

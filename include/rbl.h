@@ -66,6 +66,10 @@ enum { RBL_FP64 = 0, RBL_MIXED = 1 };
                                       pipeline does not, Sec. II C 1) */
 #define RBL_KEEP_GRID        0x4u  /* keep data and PSD resident for rbl_loglike_full */
 #define RBL_INPUT_ON_DEVICE  0x8u  /* data and psd are device pointers */
+#define RBL_CENTRE_NODES     0x10u /* Eq. (5) with r0 = r(f_m), the ratio at each bin centre, and
+                                      r1 from the edges: 2 n_bins + 1 waveform evaluations per
+                                      chain instead of n_bins + 1 (same summary data); not with
+                                      RBL_KEEP_B2 (RBL_EUNSUPPORTED) */
 
 typedef struct rbl_event rbl_event;
 
@@ -85,7 +89,9 @@ typedef struct {
     const double *det_vertex; /* host [n_det][3], Earth-fixed vertex position [m] */
     const double *theta_ref;  /* host [13], the fiducial (reference) parameters theta0 */
     const int64_t *edges;     /* host [n_bins + 1] grid indices of the bin edges: strictly
-                                 increasing, first 0, last n_freq - 1 (Sec. II C) */
+                                 increasing, first 0, last n_freq - 1 (Sec. II C); or NULL to
+                                 place them on the device by the post-Newtonian phase-bound
+                                 ansatz of rbl_bin_edges (rbl_event_get_edges returns them) */
 } rbl_event_desc;
 
 /* Build the event (the summary-data step of Sec. II C): reference waveform on the
@@ -97,7 +103,8 @@ typedef struct {
 int rbl_event_create(const rbl_event_desc *desc, void *hip_stream, rbl_event **out);
 void rbl_event_free(rbl_event *ev);
 
-/* Bytes of device workspace that rbl_loglike / rbl_loglike_grad need for B chains. */
+/* Bytes of device workspace that rbl_loglike / rbl_loglike_grad need for B chains; for an
+ * event created with RBL_KEEP_GRID the size also covers rbl_loglike_full for B chains. */
 int64_t rbl_workspace_bytes(const rbl_event *ev, int64_t B, int32_t with_grad);
 
 /* Relative-binned lnL (Eq. (2) with Eqs. (4)-(5)) for B chains.
@@ -132,10 +139,30 @@ int rbl_loglike_grad(const rbl_event *ev, const double *theta_dev, int64_t B, in
 int rbl_loglike_grad_noalloc(const rbl_event *ev, const double *theta_dev, int64_t B, int32_t precision,
                              double *lnl_dev, double *grad_dev, void *hip_stream);
 
-/* Full-grid lnL (Eqs. (2)-(3) without binning), FP64; needs RBL_KEEP_GRID.
- * Workspace as for rbl_loglike.  Used for validation and to report the binning error. */
+/* Full-grid lnL (Eqs. (2)-(3) without binning), FP64; needs RBL_KEEP_GRID.  Workspace: at
+ * least rbl_workspace_bytes(ev, B, 0) bytes of that event, 256-byte aligned.  Used for
+ * validation, to report the binning error, and as the likelihood of the reference-parameter
+ * search (no reference is needed for it beyond the event's own data). */
 int rbl_loglike_full(const rbl_event *ev, const double *theta_dev, int64_t B, double *lnl_dev,
                      void *workspace, void *hip_stream);
+
+/* Reference-parameter search (Sec. II C: the maximum-likelihood estimate that relative
+ * binning needs as theta_ref for real data): CMA-ES (Hansen's (mu/mu_w, lambda)-CMA-ES with
+ * cumulative step-size adaptation and its default constants) maximising the full-band lnL of
+ * Eqs. (2)-(3), taper included, over the box [lo, hi] (host [13] each); the event must have
+ * RBL_KEEP_GRID (its own theta_ref does not enter).  The search runs in box-normalised
+ * coordinates from `start` (host [13], inside the box) with initial step sigma0 (> 0, in box
+ * units); candidates outside the box rank last.  lambda (4 .. 2^20) candidates per generation
+ * are evaluated together on the device; normals: host [generations][lambda][13] standard
+ * normals, the caller's random numbers.  The search ends early, after *generations_run
+ * generations, when the covariance can no longer be factored, its Cholesky diagonal spans
+ * more than 1e7 (conditioning above 1e14), or the largest step exceeds the box width.
+ * Outputs (host): best_theta [13] and best_lnl, the best candidate seen; trace (may be NULL)
+ * [generations][15] = (best lnL so far, sigma, mean theta [13]) after each generation run.
+ * Synchronous on hip_stream; allocates its device buffers for the duration of the call. */
+int rbl_ref_search(const rbl_event *ev, const double *lo, const double *hi, const double *start, double sigma0,
+                   int32_t lambda, int32_t generations, const double *normals, double *best_theta,
+                   double *best_lnl, double *trace, int32_t *generations_run, void *hip_stream);
 
 /* Projected strain h_d(f_k; theta) on a grid for one parameter vector (host theta[13]);
  * out_dev [n_det][n_freq][2] complex float64, device.  `taper` selects the Planck taper
@@ -146,6 +173,9 @@ int rbl_strain(int32_t waveform, int32_t n_det, const double *det_tensor, const 
 
 /* Copy the summary data to host: [n_det][n_bins][7] = (Re A0, Im A0, Re A1, Im A1, B0, B1, B2). */
 int rbl_event_get_summary(const rbl_event *ev, double *host_out);
+
+/* Copy the event's bin edges to host: [n_bins + 1] grid indices. */
+int rbl_event_get_edges(const rbl_event *ev, int64_t *host_out);
 
 /* Event shape and resident device footprint in bytes. */
 int rbl_event_info(const rbl_event *ev, int32_t *n_det, int32_t *n_bins, int32_t *waveform,

@@ -13,7 +13,9 @@ maximisation:
   cov. path  p_c <- (1 - c_c) p_c + h_s sqrt(c_c (2 - c_c) mu_eff) <y>_w,
   covariance C <- (1 - c_1 - c_mu) C + c_1 (p_c p_c^T + (1 - h_s) c_c (2 - c_c) C)
                   + c_mu sum_i w_i y_{i:lambda} y_{i:lambda}^T,
-with the tutorial's default constants.  One reading: the tutorial's C^{-1/2} in the step-size
+with the tutorial's default constants.  The search stops (the tutorial's ConditionCov and
+TolUpSigma criteria, on the Cholesky factor) once C can no longer be factored, (max_i A_ii /
+min_i A_ii)^2 exceeds 1e14, or the largest step sigma max_i A_ii exceeds the box width.  One reading: the tutorial's C^{-1/2} in the step-size
 path is taken as A^{-1}, the inverse of the lower Cholesky factor, so that sampling needs no
 eigendecomposition (A^{-1} y_k = z_k has the same N(0, I) law under random selection).  The
 search runs in box-normalised coordinates u = (theta - lo) / (hi - lo); a candidate outside
@@ -43,6 +45,16 @@ class CMAES:
         self.pc = np.zeros(n)
         self.gen = 0
         self._y = None
+
+    def factor(self):
+        """Cholesky factor A of C; False when the search must stop (C not positive definite
+        in floating point, or its conditioning beyond 1e14)."""
+        try:
+            self.A = np.linalg.cholesky(self.C)
+        except np.linalg.LinAlgError:
+            return False
+        d = np.diag(self.A)
+        return bool((d.max() / d.min()) ** 2 <= 1e14 and self.sigma * d.max() <= 1.0)
 
     def ask(self, z):
         """Candidates x_k = m + sigma A z_k for the given standard normals z [lambda, n]."""
@@ -74,13 +86,16 @@ class CMAES:
 def search(fitness_fn, lo, hi, start, sigma0, lam, normals):
     """Maximise fitness_fn(theta [lambda, 13]) -> [lambda] over the box [lo, hi] from `start`,
     with the standard normals [generations, lambda, 13].  Returns (best theta, its fitness,
-    trace [generations, 2 + 13] of (best fitness so far, sigma, mean theta))."""
+    trace [generations run, 2 + 13] of (best fitness so far, sigma, mean theta)); the run
+    ends early when the covariance's conditioning stops it (CMAES.factor)."""
     lo, hi = np.asarray(lo, float), np.asarray(hi, float)
     width = hi - lo
     es = CMAES((np.asarray(start, float) - lo) / width, sigma0, lam)
     best_f, best_x = -np.inf, np.asarray(start, float).copy()
     trace = []
     for z in normals:
+        if not es.factor():
+            break
         u = es.ask(z)
         inside = np.all((u >= 0.0) & (u <= 1.0), axis=1)
         theta = lo + u * width

@@ -22,6 +22,10 @@ Relative binning (Sec. II C, Eqs. 4-5), step by step:
   6. substitute into the full-grid expression:
        lnL = sum_d sum_b [ Re(A0 r0* + A1 r1*) - B0 |r0|^2 / 2
                            - B1 Re(r0 r1*) - B2 |r1|^2 / 2 ].
+Centre-node variant (Event.centre): Eq. (5) expands the ratio about the bin centre, so
+r0 is taken as the ratio evaluated at f_m(b) itself, r0 = r(f_m), and r1 from the
+edges as above: 2 Nb + 1 waveform evaluations per chain instead of Nb + 1.  The summary
+data are the same; the B2 term is not offered with this variant.
 """
 from dataclasses import dataclass, field
 
@@ -44,6 +48,7 @@ class Event:
     theta_ref: np.ndarray = None  # [13]
     keep_b2: bool = False
     ref_taper: bool = False       # taper the reference (the paper's runs do not)
+    centre: bool = False          # r0 from the ratio at the bin centre (2 Nb + 1 evaluations)
     summary: dict = field(default=None, repr=False)
 
 
@@ -119,9 +124,16 @@ def prepare(ev):
     return ev
 
 
-def node_ratios(ev, theta):
-    """Step 4: r_d(f_j) = h_d(f_j; theta) / h0_d(f_j) -> list over d of [B, Nb+1]."""
-    fn = ev.f[np.asarray(ev.edges)]
+def bin_centres(ev):
+    """f_m(b) = (f_{e_b} + f_{e_{b+1}}) / 2."""
+    fe = ev.f[np.asarray(ev.edges)]
+    return 0.5 * (fe[:-1] + fe[1:])
+
+
+def node_ratios(ev, theta, freqs=None):
+    """Step 4: r_d(f_j) = h_d(f_j; theta) / h0_d(f_j) at the bin edges (or at `freqs`)
+    -> list over d of [B, len]."""
+    fn = ev.f[np.asarray(ev.edges)] if freqs is None else freqs
     h = waveform.strain(fn, theta, ev.tensors, ev.vertices, ev.gmst, ev.approximant, True)
     h0 = waveform.strain(fn, ev.theta_ref, ev.tensors, ev.vertices, ev.gmst, ev.approximant,
                          ev.ref_taper)
@@ -136,14 +148,17 @@ def loglike_rb(ev, theta):
     fn = ev.f[np.asarray(ev.edges)]
     width = fn[1:] - fn[:-1]
     total = 0.0
+    centre = node_ratios(ev, theta, bin_centres(ev)) if ev.centre else None
     for d, r in enumerate(node_ratios(ev, theta)):
         rl, rr = r[..., :-1], r[..., 1:]
-        r0 = 0.5 * (rl + rr)
+        r0 = centre[d] if ev.centre else 0.5 * (rl + rr)
         r1 = (rr - rl) / width
         r0c, r1c = r0.conj(), r1.conj()
         t = (s["A0"][d] * r0c + s["A1"][d] * r1c).real \
             - 0.5 * s["B0"][d] * (r0 * r0c).real - s["B1"][d] * (r0 * r1c).real
         if ev.keep_b2:
+            if ev.centre:
+                raise ValueError("the B2 term is not offered with the centre-node variant")
             t = t - 0.5 * s["B2"][d] * (r1 * r1c).real
         total = total + t.sum(axis=-1)
     return total

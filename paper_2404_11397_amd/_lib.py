@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(HERE, "librbl.so")
 RBL_OK = 0
 RBL_TAYLORF2, RBL_PHENOMD_NRTV2 = 0, 1
 RBL_FP64, RBL_MIXED = 0, 1
-RBL_KEEP_B2, RBL_REF_TAPER, RBL_KEEP_GRID, RBL_INPUT_ON_DEVICE = 0x1, 0x2, 0x4, 0x8
+RBL_KEEP_B2, RBL_REF_TAPER, RBL_KEEP_GRID, RBL_INPUT_ON_DEVICE, RBL_CENTRE_NODES = 0x1, 0x2, 0x4, 0x8, 0x10
 ERROR_NAMES = {-1: "RBL_EINVAL", -2: "RBL_EEDGES", -3: "RBL_EPSD", -4: "RBL_ENOMEM",
                -5: "RBL_EDEVICE", -6: "RBL_EREF", -7: "RBL_EUNSUPPORTED"}
 
@@ -22,7 +22,7 @@ EXPORTS = ("rbl_event_create", "rbl_event_free", "rbl_workspace_bytes", "rbl_log
            "rbl_last_error", "rbl_server_create", "rbl_server_add_event", "rbl_server_remove_event",
            "rbl_server_submit", "rbl_server_wait", "rbl_server_get_stats", "rbl_server_destroy", "rbl_clock_ns",
            "rbl_event_footprint_bytes", "rbl_debug_inject_fault", "rbl_mala_workspace_bytes", "rbl_mala_init",
-           "rbl_mala_step", "rbl_loglike_grad_noalloc")
+           "rbl_mala_step", "rbl_loglike_grad_noalloc", "rbl_ref_search", "rbl_event_get_edges")
 RBL_FAULT_ALLOC, RBL_FAULT_LAUNCH = 0, 1
 RBL_NOALLOC_MAX_CHAINS = 16384
 RBL_SERVE_NO_GRAPHS, RBL_SERVE_SPIN = 0x1, 0x2
@@ -81,10 +81,14 @@ def lib():
     L.rbl_loglike_grad_noalloc.restype = ctypes.c_int
     L.rbl_loglike_full.argtypes = [vp, vp, i64, vp, vp, vp]
     L.rbl_loglike_full.restype = ctypes.c_int
+    L.rbl_ref_search.argtypes = [vp, vp, vp, vp, dbl, i32, i32, vp, vp, vp, vp, vp, vp]
+    L.rbl_ref_search.restype = ctypes.c_int
     L.rbl_strain.argtypes = [i32, i32, vp, vp, dbl, dbl, dbl, i64, vp, i32, vp, vp]
     L.rbl_strain.restype = ctypes.c_int
     L.rbl_event_get_summary.argtypes = [vp, vp]
     L.rbl_event_get_summary.restype = ctypes.c_int
+    L.rbl_event_get_edges.argtypes = [vp, vp]
+    L.rbl_event_get_edges.restype = ctypes.c_int
     L.rbl_event_info.argtypes = [vp, vp, vp, vp, vp]
     L.rbl_event_info.restype = ctypes.c_int
     L.rbl_bin_edges.argtypes = [dbl, dbl, i64, i32, vp]

@@ -16,7 +16,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librbl.so")
-SOURCES = ["kernels.hip", "likelihood.hip", "api.hip", "serve.hip", "mala.hip", "noalloc.hip"]
+SOURCES = ["kernels.hip", "likelihood.hip", "api.hip", "serve.hip", "mala.hip", "noalloc.hip", "fullband.hip", "refsearch.hip"]
 
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-pthread"]
 DEVICE_ONLY = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

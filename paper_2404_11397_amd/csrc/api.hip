@@ -46,7 +46,6 @@ extern "C" int rbl_debug_inject_fault(int32_t kind, int32_t count) {
 
 namespace {
 
-constexpr int64_t kChunk = 256;     // grid points per summary work item (one workgroup)
 
 bool theta_in_domain(const double* t) {
     for (int i = 0; i < 13; ++i)
@@ -175,19 +174,24 @@ static int validate_desc(const rbl_event_desc* d) {
     if (!(d->f_low > 0.0) || !std::isfinite(d->f_low)) return fail(RBL_EINVAL, "rbl_event_create: f_low must be > 0");
     if (!(d->delta_f > 0.0) || !std::isfinite(d->delta_f)) return fail(RBL_EINVAL, "rbl_event_create: delta_f must be > 0");
     if (!std::isfinite(d->gmst)) return fail(RBL_EINVAL, "rbl_event_create: gmst not finite");
-    if (!d->data || !d->psd || !d->det_tensor || !d->det_vertex || !d->theta_ref || !d->edges)
+    if (!d->data || !d->psd || !d->det_tensor || !d->det_vertex || !d->theta_ref)
         return fail(RBL_EINVAL, "rbl_event_create: null pointer in descriptor");
     if (d->n_bins < 1 || (int64_t)d->n_bins > d->n_freq - 1)
         return fail(RBL_EEDGES, "rbl_event_create: need 1 <= n_bins <= n_freq - 1");
-    if (d->edges[0] != 0 || d->edges[d->n_bins] != d->n_freq - 1)
-        return fail(RBL_EEDGES, "rbl_event_create: first edge must be 0 and last n_freq - 1");
-    for (int32_t i = 0; i < d->n_bins; ++i)
-        if (!(d->edges[i + 1] > d->edges[i])) return fail(RBL_EEDGES, "rbl_event_create: edges not strictly increasing");
+    if (d->edges) {  // NULL: placed on the device
+        if (d->edges[0] != 0 || d->edges[d->n_bins] != d->n_freq - 1)
+            return fail(RBL_EEDGES, "rbl_event_create: first edge must be 0 and last n_freq - 1");
+        for (int32_t i = 0; i < d->n_bins; ++i)
+            if (!(d->edges[i + 1] > d->edges[i]))
+                return fail(RBL_EEDGES, "rbl_event_create: edges not strictly increasing");
+    }
     for (int i = 0; i < 9 * d->n_det; ++i)
         if (!std::isfinite(d->det_tensor[i])) return fail(RBL_EINVAL, "rbl_event_create: detector tensor not finite");
     for (int i = 0; i < 3 * d->n_det; ++i)
         if (!std::isfinite(d->det_vertex[i])) return fail(RBL_EINVAL, "rbl_event_create: detector vertex not finite");
     if (!theta_in_domain(d->theta_ref)) return fail(RBL_EINVAL, "rbl_event_create: theta_ref outside the physical domain");
+    if ((d->flags & RBL_CENTRE_NODES) && (d->flags & RBL_KEEP_B2))
+        return fail(RBL_EUNSUPPORTED, "rbl_event_create: RBL_KEEP_B2 is not offered with RBL_CENTRE_NODES");
     return RBL_OK;
 }
 
@@ -219,7 +223,8 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     rbl_event* ev = new rbl_event();
     ev->n_det = nd;
     ev->n_bins = nb;
-    ev->n_nodes = nb + 1;
+    const bool centre = (desc->flags & RBL_CENTRE_NODES) != 0;
+    ev->n_nodes = centre ? 2 * nb + 1 : nb + 1;  // bin edges, or edges and bin centres interleaved
     ev->n_nodes_pad = (int32_t)((ev->n_nodes + kNodeTile - 1) / kNodeTile * kNodeTile);  // 64 L
     ev->waveform = desc->waveform;
     ev->flags = desc->flags;
@@ -275,31 +280,29 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
             return cleanup(fail(RBL_EREF, "rbl_event_create: reference strain vanishes in detector " + std::to_string(d)));
     }
 
-    // Work items of the summary pass: runs of <= kChunk points inside one bin; the bin centre
-    // f_m = (f_{e_b} + f_{e_{b+1}}) / 2 of the linear model is attached to each item.
-    std::vector<SumItem> items;
-    std::vector<int64_t> bin_first((size_t)nb + 1);
-    for (int32_t b = 0; b < nb; ++b) {
-        bin_first[(size_t)b] = (int64_t)items.size();
-        const int64_t lo = desc->edges[b];
-        const int64_t hi = (b == nb - 1) ? n : desc->edges[b + 1];
-        const double fm = ev->f_low + 0.5 * (double)(desc->edges[b] + desc->edges[b + 1]) * ev->delta_f;
-        for (int64_t k = lo; k < hi; k += kChunk) items.push_back(SumItem{k, (int32_t)std::min(kChunk, hi - k), b, fm});
+    // Bin edges: given, or placed on the device by the post-Newtonian phase-bound ansatz.
+    if (desc->edges) {
+        ev->edges.assign(desc->edges, desc->edges + nb + 1);
+    } else {
+        double* d_phi = nullptr;
+        int64_t* d_pe = nullptr;
+        if (tmp.alloc((void**)&d_phi, sizeof(double) * n) != hipSuccess ||
+            tmp.alloc((void**)&d_pe, sizeof(int64_t) * (nb + 1)) != hipSuccess)
+            return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (bin placement)"));
+        ev->edges.resize((size_t)nb + 1);
+        if ((e = launch_bin_edges(ev->f_low, ev->delta_f, n, nb, d_phi, d_pe, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(ev->edges.data(), d_pe, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost, s)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return cleanup(hip_fail(e, "rbl_event_create: bin placement"));
     }
-    bin_first[(size_t)nb] = (int64_t)items.size();
-    const int64_t n_items = (int64_t)items.size();
-    SumItem* d_items = nullptr;
-    int64_t *d_bin_first = nullptr, *d_edges = nullptr;
-    double* d_partials = nullptr;
-    if (tmp.alloc((void**)&d_items, sizeof(SumItem) * n_items) != hipSuccess ||
-        tmp.alloc((void**)&d_bin_first, sizeof(int64_t) * (nb + 1)) != hipSuccess ||
-        tmp.alloc((void**)&d_edges, sizeof(int64_t) * (nb + 1)) != hipSuccess ||
-        tmp.alloc((void**)&d_partials, sizeof(double) * n_items * nd * 7) != hipSuccess)
-        return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (work items)"));
-    if ((e = hipMemcpyAsync(d_items, items.data(), sizeof(SumItem) * n_items, hipMemcpyHostToDevice, s)) ||
-        (e = hipMemcpyAsync(d_bin_first, bin_first.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, s)) ||
-        (e = hipMemcpyAsync(d_edges, desc->edges, sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, s)))
-        return cleanup(hip_fail(e, "rbl_event_create: copy work items"));
+    const int64_t* edges = ev->edges.data();
+
+    int64_t* d_edges = nullptr;
+    if (tmp.alloc((void**)&d_edges, sizeof(int64_t) * (nb + 1)) != hipSuccess)
+        return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (edges)"));
+    if ((e = hipMemcpyAsync(d_edges, edges, sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, s)) != hipSuccess)
+        return cleanup(hip_fail(e, "rbl_event_create: copy edges"));
 
     // Resident tables.
     const int64_t np = ev->n_nodes_pad;
@@ -329,8 +332,7 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
         return cleanup(hip_fail(e, "rbl_event_create: copy phasor table"));
 
     SummaryArgs sa{};
-    sa.n_items = n_items;
-    sa.items = d_items;
+    sa.edges = d_edges;
     sa.f_low = ev->f_low;
     sa.delta_f = ev->delta_f;
     sa.n_freq = n;
@@ -338,22 +340,21 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     sa.n_bins = nb;
     sa.data = d_data;
     sa.psd = d_psd;
-    sa.partials = d_partials;
+    sa.summary = ev->d_summary;
     sa.phasor = d_phasor;
     sa.ref = ev->ref;
     sa.ref_taper = (desc->flags & RBL_REF_TAPER) ? 1 : 0;
-    // benchmark timing: the two kernels' own durations, summed
-    std::array<hipEvent_t, 4> te{{nullptr, nullptr, nullptr, nullptr}};
+    // benchmark timing: the summary kernel's own duration
+    std::array<hipEvent_t, 2> te{{nullptr, nullptr}};
     if (g_prof.on)
         for (auto& t : te) t = g_prof.get();
-    const bool timed = te[0] && te[1] && te[2] && te[3];
-    if ((e = launch_summary(sa, d_bin_first, ev->d_summary, s, timed ? KTime{te[0], te[1]} : KTime{},
-                            timed ? KTime{te[2], te[3]} : KTime{})) != hipSuccess)
+    const bool timed = te[0] && te[1];
+    if ((e = launch_summary(sa, s, timed ? KTime{te[0], te[1]} : KTime{})) != hipSuccess)
         return cleanup(hip_fail(e, "rbl_event_create: summary pass"));
-    if (timed && hipEventSynchronize(te[3]) == hipSuccess) {
-        float m1 = 0.f, m2 = 0.f;
-        if (hipEventElapsedTime(&m1, te[0], te[1]) == hipSuccess && hipEventElapsedTime(&m2, te[2], te[3]) == hipSuccess) {
-            g_prof.summary_ms += m1 + m2;
+    if (timed && hipEventSynchronize(te[1]) == hipSuccess) {
+        float m1 = 0.f;
+        if (hipEventElapsedTime(&m1, te[0], te[1]) == hipSuccess) {
+            g_prof.summary_ms += m1;
             g_prof.summary_n += 1;
         }
     }
@@ -366,6 +367,7 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
     na.L = (int32_t)(np / kNodeTile);
     na.n_det = nd;
     na.keep_b2 = (desc->flags & RBL_KEEP_B2) ? 1 : 0;
+    na.centre = centre ? 1 : 0;
     na.edges = d_edges;
     na.f_low = ev->f_low;
     na.delta_f = ev->delta_f;
@@ -444,7 +446,10 @@ extern "C" void rbl_event_free(rbl_event* ev) {
 
 extern "C" int64_t rbl_workspace_bytes(const rbl_event* ev, int64_t B, int32_t with_grad) {
     if (!ev || B < 0) return 0;
-    return workspace_bytes(B, with_grad != 0);
+    const int64_t w = workspace_bytes(B, with_grad != 0);
+    if (!(ev->flags & RBL_KEEP_GRID)) return w;
+    const int64_t wf = full_workspace_bytes(ev->n_freq, B, ev->waveform);
+    return wf > w ? wf : w;
 }
 
 extern "C" int64_t rbl_event_footprint_bytes(const rbl_event* ev) { return ev ? ev->footprint : 0; }
@@ -515,8 +520,11 @@ extern "C" int rbl_loglike_full(const rbl_event* ev, const double* theta_dev, in
     a.delta_f = ev->delta_f;
     a.data = ev->d_data;
     a.psd = ev->d_psd;
+    a.phasor = ev->dev.phasor;
     a.lnl = lnl_dev;
-    e = launch_loglike_full(a, B, s, tm.main());
+    double* consts = (double*)((char*)workspace + align_up(B * kRecStride * (int64_t)sizeof(double)));
+    double* partials = (double*)((char*)consts + align_up(B * kFullStride * (int64_t)sizeof(double)));
+    e = launch_loglike_full(a, B, consts, partials, s, tm.main());
     if (e != hipSuccess) return hip_fail(e, "rbl_loglike_full: launch");
     tm.done();
     return RBL_OK;
@@ -553,6 +561,12 @@ extern "C" int rbl_event_get_summary(const rbl_event* ev, double* host_out) {
     if (!ev || !host_out) return fail(RBL_EINVAL, "rbl_event_get_summary: null pointer");
     hipError_t e = hipMemcpy(host_out, ev->d_summary, sizeof(double) * ev->n_det * ev->n_bins * 7, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "rbl_event_get_summary");
+    return RBL_OK;
+}
+
+extern "C" int rbl_event_get_edges(const rbl_event* ev, int64_t* host_out) {
+    if (!ev || !host_out) return fail(RBL_EINVAL, "rbl_event_get_edges: null pointer");
+    std::copy(ev->edges.begin(), ev->edges.end(), host_out);
     return RBL_OK;
 }
 

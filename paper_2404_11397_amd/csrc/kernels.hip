@@ -3,11 +3,10 @@
 //  k_ref_setup      reference (fiducial) constants for theta0            [1 thread]
 //  k_chain_setup    per-chain record                                     [1 thread / (chain, half)]
 //  k_chain_setup_grad  record and partial derivatives (dual numbers)    [1 lane / (chain, tangent)]
-//  k_summary_items  summary-data partial sums over (bin, chunk) items    [1 workgroup / item]
-//  k_summary_reduce ordered sum of the partials of each bin              [1 thread / (det, bin, field)]
+//  k_summary_bins   summary data of one bin                              [1 workgroup / bin]
 //  k_node_tables    per-edge coefficient tables of the binned sum        [1 thread / node]
 //  (k_loglike_fwd and k_loglike_grad, the likelihood kernels, are in likelihood.hip)
-//  k_loglike_full   full-grid likelihood (validation)                    [1 workgroup / chain]
+//  (the full-band likelihood kernels are in fullband.hip)
 //  k_strain         projected strain on a grid (injections)              [1 thread / grid point]
 //
 // All reductions are in a fixed order, so results are bitwise reproducible.
@@ -160,9 +159,13 @@ __global__ __launch_bounds__(64) void k_chain_setup(const double* __restrict__ t
 constexpr int kIntLanes = 8;
 constexpr int kExtLanes = 4;
 
+// PROP: the chain's theta is the MALA proposal theta(z'), z' = z + (s/2) gz + sqrt(s) xi (a NaN
+// row outside the prior box); lane 0 of each intrinsic group writes z' and theta' for the
+// gradient kernel's accept epilogue.
+template <bool PROP>
 __global__ __launch_bounds__(64) void k_chain_setup_grad(const double* __restrict__ theta, int64_t B, Network net,
                                                           RefConsts ref, double* __restrict__ rec,
-                                                          double* __restrict__ jac, int64_t n_int_blocks) {
+                                                          double* __restrict__ jac, int64_t n_int_blocks, MalaProp mp) {
     const bool intrinsic = (int64_t)blockIdx.x < n_int_blocks;
     const int64_t gid = ((int64_t)blockIdx.x - (intrinsic ? 0 : n_int_blocks)) * blockDim.x + threadIdx.x;
     const int lanes = intrinsic ? kIntLanes : kExtLanes;
@@ -170,8 +173,31 @@ __global__ __launch_bounds__(64) void k_chain_setup_grad(const double* __restric
     const int tg = (int)(gid % lanes);
     if (b >= B) return;
     double t[13];
+    if constexpr (PROP) {
+        double q[13];
+        bool in = true;
 #pragma unroll
-    for (int i = 0; i < 13; ++i) t[i] = theta[b * 13 + i];
+        for (int i = 0; i < 13; ++i) {
+            q[i] = fma(mp.sq[i], mp.xi[b * 13 + i], fma(0.5 * mp.s[i], mp.gz[b * 13 + i], mp.z[b * 13 + i]));
+            in = in && q[i] >= mp.lo[i] && q[i] <= mp.hi[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 13; ++i) t[i] = in ? q[i] : __builtin_nan("");
+        if (in) {
+            t[9] = acos(fmin(fmax(q[9], -1.0), 1.0));
+            t[12] = asin(fmin(fmax(q[12], -1.0), 1.0));
+        }
+        if (intrinsic && tg == 0) {
+#pragma unroll
+            for (int i = 0; i < 13; ++i) {
+                mp.zp[b * 13 + i] = q[i];
+                mp.thp[b * 13 + i] = t[i];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 13; ++i) t[i] = theta[b * 13 + i];
+    }
     double* out = rec + b * kRecStride;
     double* J = jac + b * kJacStride;
     const int st = theta_status(t);
@@ -272,15 +298,15 @@ __global__ __launch_bounds__(64) void k_chain_setup_grad(const double* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Summary data: one workgroup per item (a run of <= 256 grid points inside one bin, one
-// point per thread); the reference waveform is generated inline, once per point, and
-// projected onto every detector, with the unit phasors from the LDS table.  The 7 ND partial
-// sums are reduced across each wavefront (wave_sum_n) and the four wavefront totals added
-// in wave order, so the partials are bitwise reproducible.  Partials: [item][det][7].
-// (A last-item-per-bin reduction inside this kernel needs device-scope fences, which cost
-// far more here than the second kernel.)
+// Summary data: one workgroup per bin, kSumThreads threads taking kSumPPT grid points each
+// per pass (all of a pass's data and PSD loads issued before its arithmetic), as many passes
+// as the bin needs; the reference waveform is generated inline, once per point, and
+// projected onto every detector, with the unit phasors from the LDS table.  Each thread adds
+// its points in order, the 7 ND sums are reduced across each wavefront (wave_sum_n) and the
+// wavefront totals added in wave order: the summary data are bitwise reproducible, and the
+// pass is one kernel with no partial sums in memory.
 // ---------------------------------------------------------------------------
-template <int ND>
+template <int ND, int WF>
 __device__ inline void summary_point(const SummaryArgs& a, const double2* tab, int64_t k, double fm, const double* dre,
                                      const double* dim, const double* ps, double (&acc)[ND][7]) {
     const RefConsts& ref = a.ref;
@@ -291,7 +317,7 @@ __device__ inline void summary_point(const SummaryArgs& a, const double2* tab, i
     const double lx = log(x);
     double phi = 0.0;
     double amp = ref.amp0 * (ix * ix * ix) * sqrt(ix);  // f^(-7/6)
-    if (ref.waveform == kWfNrtv2) {
+    if constexpr (WF == kWfNrtv2) {
         double a0;
         nrt_node(ref.nrt, f, x, ix, lx, exp(5.78 * lx), a.ref_taper != 0, phi, a0);
         amp *= a0;
@@ -323,33 +349,47 @@ __device__ inline void summary_point(const SummaryArgs& a, const double2* tab, i
     }
 }
 
-template <int ND>
-__global__ __launch_bounds__(256) void k_summary_items(SummaryArgs a) {
+template <int ND, int WF>
+__global__ __launch_bounds__(kSumThreads) void k_summary_bins(
+    SummaryArgs a) {
     constexpr int NV = (7 * ND + 3) / 4 * 4;
+    constexpr int NW = kSumThreads / 64;
     __shared__ double2 tab[kPhasorN];
-    __shared__ double red[4][NV];
+    __shared__ double red[NW][NV];
     load_phasor_table(a.phasor, tab);
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wid = wave_id();
-    const int64_t item = blockIdx.x;
-    const SumItem it = a.items[item];
+    const int b = blockIdx.x;
+    const int64_t lo = a.edges[b];
+    const int64_t hi = (b == a.n_bins - 1) ? a.n_freq : a.edges[b + 1];
+    const double fm = a.f_low + 0.5 * (double)(a.edges[b] + a.edges[b + 1]) * a.delta_f;
     double acc[ND][7];
 #pragma unroll
     for (int d = 0; d < ND; ++d)
 #pragma unroll
         for (int j = 0; j < 7; ++j) acc[d][j] = 0.0;
-    if (t < it.count) {
-        const int64_t k = it.start + t;
-        double re[ND], im[ND], ps[ND];
+    for (int64_t base = lo; base < hi; base += (int64_t)kSumThreads * kSumPPT) {
+        double re[kSumPPT][ND], im[kSumPPT][ND], ps[kSumPPT][ND];
 #pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            const int64_t o = (int64_t)d * a.n_freq + k;
-            re[d] = a.data[2 * o];
-            im[d] = a.data[2 * o + 1];
-            ps[d] = a.psd[o];
+        for (int p = 0; p < kSumPPT; ++p) {
+            const int64_t k = base + p * kSumThreads + t;
+            if (k < hi) {
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    const int64_t o = (int64_t)d * a.n_freq + k;
+                    const double2 v = reinterpret_cast<const double2*>(a.data)[o];
+                    re[p][d] = v.x;
+                    im[p][d] = v.y;
+                    ps[p][d] = a.psd[o];
+                }
+            }
         }
-        summary_point<ND>(a, tab, k, it.fm, re, im, ps, acc);
+#pragma unroll
+        for (int p = 0; p < kSumPPT; ++p) {
+            const int64_t k = base + p * kSumThreads + t;
+            if (k < hi) summary_point<ND, WF>(a, tab, k, fm, re[p], im[p], ps[p], acc);
+        }
     }
     double part[NV], tot[NV];
 #pragma unroll
@@ -364,21 +404,13 @@ __global__ __launch_bounds__(256) void k_summary_items(SummaryArgs a) {
         for (int i = 0; i < NV; ++i) red[wid][i] = tot[i];
     }
     __syncthreads();
-    if (t < 7 * ND) a.partials[item * (7 * ND) + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
-}
-
-
-__global__ void k_summary_reduce(const double* __restrict__ partials, const int64_t* __restrict__ bin_first_item,
-                                 int32_t n_bins, int32_t n_det, double* __restrict__ summary) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)n_det * n_bins * 7;
-    if (t >= total) return;
-    const int j = t % 7;
-    const int b = (t / 7) % n_bins;
-    const int d = t / (7 * n_bins);
-    double s = 0.0;
-    for (int64_t it = bin_first_item[b]; it < bin_first_item[b + 1]; ++it) s += partials[(it * n_det + d) * 7 + j];
-    summary[((int64_t)d * n_bins + b) * 7 + j] = s;
+    if (t < 7 * ND) {
+        double v = red[0][t];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) v += red[w][t];
+        const int d = t / 7, j = t % 7;
+        a.summary[((int64_t)d * a.n_bins + b) * 7 + j] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -390,17 +422,30 @@ __global__ void k_summary_reduce(const double* __restrict__ partials, const int6
 //   gamma_j = alpha_j + beta_{j-1},  mu_j = (left part of bin j) + (right part of bin j-1),
 //   nu_b = B0/2 - 2 B2 w^2 multiplies Re(r_b r_{b+1}*).  The tables hold the cross
 // weights of 2 lnL, xL_j = -nu_{j-1} and xR_j = -nu_j.
+//
+// Centre-node variant: the nodes are e_0, c_0, e_1, c_1, ..., e_Nb (edges and bin centres
+// f_m interleaved), r0 = r(c_b) and r1 = (r(e_{b+1}) - r(e_b)) w.  Bin b's term
+//   Re(A0 r0* + A1 r1*) - B0 |r0|^2 / 2 - B1 Re(r0 r1*)
+// then gives  gamma(c_b) = A0, mu(c_b) = B0, gamma(e_b) -= A1 w, gamma(e_{b+1}) += A1 w, and the
+// cross weights (2 lnL) 2 B1 w between e_b and c_b and -2 B1 w between c_b and e_{b+1}.
 // ---------------------------------------------------------------------------
+__device__ inline double node_frequency(const NodeArgs& a, int j) {
+    if (!a.centre) return a.f_low + (double)a.edges[j] * a.delta_f;
+    if ((j & 1) == 0) return a.f_low + (double)a.edges[j >> 1] * a.delta_f;
+    const int b = j >> 1;  // the same expression as the bin centre of the summary pass
+    return a.f_low + 0.5 * (double)(a.edges[b] + a.edges[b + 1]) * a.delta_f;
+}
+
 __global__ void k_node_tables(NodeArgs a) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;  // edge index
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;  // node index
     if (j >= a.n_nodes_pad) return;
     // lane-contiguous position (TaylorF2) or natural order (IMRPhenomD_NRTidalv2)
     const int pos = a.ref.waveform == kWfNrtv2 ? j : (j % a.L) * kNodeTile + j / a.L;
     const bool real_node = j < a.n_nodes;
-    const int nb = a.n_nodes - 1;
+    const int nb = a.centre ? (a.n_nodes - 1) / 2 : a.n_nodes - 1;
     double f = 0.0, x = 1.0, ix = 1.0, lx = 0.0;
     if (real_node) {
-        f = a.f_low + (double)a.edges[j] * a.delta_f;
+        f = node_frequency(a, j);
         x = cbrt(f);
         ix = 1.0 / x;
         lx = log(x);
@@ -422,7 +467,33 @@ __global__ void k_node_tables(NodeArgs a) {
     }
     for (int d = 0; d < a.n_det; ++d) {
         double gre = 0.0, gim = 0.0, mu = 0.0, xl = 0.0, xr = 0.0;
-        if (real_node) {
+        if (real_node && a.centre) {
+            const int b = j >> 1;
+            if (j & 1) {  // centre of bin b
+                const double* s = a.summary + ((int64_t)d * nb + b) * 7;
+                const double w = 1.0 / ((double)(a.edges[b + 1] - a.edges[b]) * a.delta_f);
+                gre = s[0];
+                gim = s[1];
+                mu = s[4];
+                xl = 2.0 * s[5] * w;
+                xr = -2.0 * s[5] * w;
+            } else {      // edge b
+                if (b < nb) {  // bin b to the right
+                    const double* s = a.summary + ((int64_t)d * nb + b) * 7;
+                    const double w = 1.0 / ((double)(a.edges[b + 1] - a.edges[b]) * a.delta_f);
+                    gre -= s[2] * w;
+                    gim -= s[3] * w;
+                    xr = 2.0 * s[5] * w;
+                }
+                if (b > 0) {   // bin b - 1 to the left
+                    const double* s = a.summary + ((int64_t)d * nb + (b - 1)) * 7;
+                    const double w = 1.0 / ((double)(a.edges[b] - a.edges[b - 1]) * a.delta_f);
+                    gre += s[2] * w;
+                    gim += s[3] * w;
+                    xl = -2.0 * s[5] * w;
+                }
+            }
+        } else if (real_node) {
             if (j < nb) {  // bin j lies to the right of edge j
                 const double* s = a.summary + ((int64_t)d * nb + j) * 7;
                 const double w = 1.0 / ((double)(a.edges[j + 1] - a.edges[j]) * a.delta_f);
@@ -479,77 +550,6 @@ __global__ __launch_bounds__(64) void k_event_scales(NodeArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Full-grid likelihood (no binning), FP64: one block of 256 per chain.
-// h_d(f) = h0fac_d K_d amp0 f^(-7/6) exp(-2 pi i (sum_b (c0_b + dc_b) B_b(x) + f (tau0_d + dtau_d)))
-// ---------------------------------------------------------------------------
-// One 512-thread workgroup per chain (8 wavefronts: two per SIMD, so a batch of a few hundred
-// chains keeps every SIMD busy; the node model needs more registers than four per SIMD allow);
-// the wavefront sums are added in a fixed order.
-constexpr int kFullThreads = 512;
-__global__ __launch_bounds__(kFullThreads) void k_loglike_full(FullArgs a) {
-    __shared__ double red[kFullThreads / 64];
-    const int64_t chain = blockIdx.x;
-    const double* rec = a.recs + chain * kRecStride;
-    const double status = rec[kRecStatus];
-    if (!(status == 1.0)) {
-        if (threadIdx.x == 0) a.lnl[chain] = (status == 0.0) ? -__builtin_inf() : __builtin_nan("");
-        return;
-    }
-    const RefConsts& ref = a.ref;
-    const bool nrt = ref.waveform == kWfNrtv2;
-    NrtParams<double> np;
-    if (nrt) {
-        double* dst = reinterpret_cast<double*>(&np);
-        for (int i = 0; i < kNrtParams; ++i) dst[i] = rec[kRecNrt + i];
-    }
-    double c[kTf2Basis];
-    for (int k = 0; k < kTf2Basis; ++k) c[k] = ref.c0[k] + rec[kRecDc + k] * (1.0 / kPhasorN);
-    double fre[kMaxDet], fim[kMaxDet], tau[kMaxDet];
-    const double g_re = rec[kRecG], g_im = rec[kRecG + 1];
-    for (int d = 0; d < a.n_det; ++d) {
-        const double pr = rec[kRecK + 2 * d], pi = rec[kRecK + 2 * d + 1];
-        const double kre = pr * g_re - pi * g_im, kim = pr * g_im + pi * g_re;  // K_d = P_d G
-        fre[d] = ref.amp0 * (ref.h0fac_re[d] * kre - ref.h0fac_im[d] * kim);
-        fim[d] = ref.amp0 * (ref.h0fac_re[d] * kim + ref.h0fac_im[d] * kre);
-        tau[d] = ref.tau0[d] + rec[kRecTau + d] * (1.0 / kPhasorN);
-    }
-    const double w = 4.0 * a.delta_f;
-    double acc = 0.0;
-    for (int64_t k = threadIdx.x; k < a.n_freq; k += blockDim.x) {
-        const double f = a.f_low + (double)k * a.delta_f;
-        const double x = cbrt(f), ix = 1.0 / x, lx = log(x);
-        double ph = 0.0;
-        double am = (ix * ix * ix) * sqrt(ix);
-        if (nrt) {
-            double af;
-            nrt_node(np, f, x, ix, lx, exp(5.78 * lx), true, ph, af);
-            am *= af;
-        } else {
-            double bas[kTf2Basis];
-            tf2_basis(x, ix, lx, bas);
-            for (int j = 0; j < kTf2Basis; ++j) ph = fma(c[j], bas[j], ph);
-        }
-        for (int d = 0; d < a.n_det; ++d) {
-            double cu, su;
-            expm2pi_rev(fma(f, tau[d], ph), cu, su);
-            const double hre = am * (fre[d] * cu - fim[d] * su);
-            const double him = am * (fre[d] * su + fim[d] * cu);
-            const int64_t o = (int64_t)d * a.n_freq + k;
-            const double wk = w / a.psd[o];
-            acc += ((a.data[2 * o] * hre + a.data[2 * o + 1] * him) - 0.5 * (hre * hre + him * him)) * wk;
-        }
-    }
-    acc = wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int i = 0; i < kFullThreads / 64; ++i) t += red[i];
-        a.lnl[chain] = t;
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Projected strain on a grid for one parameter vector (its constants come from
 // k_ref_setup run on that vector).
 // ---------------------------------------------------------------------------
@@ -582,6 +582,62 @@ __global__ __launch_bounds__(256) void k_strain(const RefConsts* __restrict__ cs
 }
 
 // ---------------------------------------------------------------------------
+// Bin placement on the device (Sec. II C): the post-Newtonian phase-bound ansatz
+//   Phi(f) = sum_g sgn(g) (f / f*_g)^g,  g in {-5/3, -2/3, 1, 5/3, 7/3},
+// f*_g = f_low for g < 0 and f_high for g > 0, on every grid point (Phi increases with f);
+// n_bins + 1 equally spaced targets between Phi(f_low) and Phi(f_high), each snapped to the
+// grid point with the nearer Phi (the lower one on a tie); then one pass each way makes the
+// indices strictly increasing with the ends at 0 and N - 1.
+// ---------------------------------------------------------------------------
+__global__ void k_pn_phase(double f_low, double delta_f, int64_t n, double* __restrict__ phi) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double f_high = f_low + (double)(n - 1) * delta_f;
+    const double f = f_low + (double)k * delta_f;
+    double s = 0.0;
+    s += -pow(f / f_low, -5.0 / 3.0);
+    s += -pow(f / f_low, -2.0 / 3.0);
+    s += pow(f / f_high, 1.0);
+    s += pow(f / f_high, 5.0 / 3.0);
+    s += pow(f / f_high, 7.0 / 3.0);
+    phi[k] = s;
+}
+
+__global__ void k_pn_snap(const double* __restrict__ phi, int64_t n, int32_t n_bins, int64_t* __restrict__ edges) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n_bins) return;
+    const double p0 = phi[0], p1 = phi[n - 1];
+    const double tgt = p0 + (p1 - p0) * (double)i / (double)n_bins;
+    int64_t lo = 0, hi = n;  // first index with phi >= tgt
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (phi[mid] < tgt)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    const int64_t pos = lo < 1 ? 1 : (lo > n - 1 ? n - 1 : lo);
+    edges[i] = (tgt - phi[pos - 1] <= phi[pos] - tgt) ? pos - 1 : pos;
+}
+
+__global__ void k_pn_order(int64_t n, int32_t n_bins, int64_t* __restrict__ edges) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    edges[0] = 0;
+    edges[n_bins] = n - 1;
+    for (int32_t i = 1; i <= n_bins; ++i) edges[i] = edges[i] > edges[i - 1] + 1 ? edges[i] : edges[i - 1] + 1;
+    edges[n_bins] = n - 1;
+    for (int32_t i = n_bins - 1; i >= 0; --i) edges[i] = edges[i] < edges[i + 1] - 1 ? edges[i] : edges[i + 1] - 1;
+}
+
+hipError_t launch_bin_edges(double f_low, double delta_f, int64_t n, int32_t n_bins, double* phi, int64_t* edges,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_pn_phase, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, f_low, delta_f, n, phi);
+    hipLaunchKernelGGL(k_pn_snap, dim3((unsigned)((n_bins + 1 + 255) / 256)), dim3(256), 0, s, phi, n, n_bins, edges);
+    hipLaunchKernelGGL(k_pn_order, dim3(1), dim3(64), 0, s, n, n_bins, edges);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------
 hipError_t launch_ref_setup(const double* theta, const Network& net, int32_t waveform, RefConsts* out_dev,
@@ -593,12 +649,16 @@ hipError_t launch_ref_setup(const double* theta, const Network& net, int32_t wav
 }
 
 hipError_t launch_chain_setup(const double* theta, int64_t B, const Network& net, const RefConsts& ref,
-                              double* rec, double* jac, hipStream_t s, KTime kt) {
+                              double* rec, double* jac, hipStream_t s, KTime kt, const MalaProp* prop) {
     if (jac) {
         const int64_t n_int = (B * kIntLanes + 63) / 64;
         const int64_t n_ext = (B * kExtLanes + 63) / 64;
-        launch_k(k_chain_setup_grad, dim3((unsigned)(n_int + n_ext)), dim3(64), s, kt, theta, B, net, ref,
-                           rec, jac, n_int);
+        if (prop)
+            launch_k(k_chain_setup_grad<true>, dim3((unsigned)(n_int + n_ext)), dim3(64), s, kt, theta, B, net, ref,
+                     rec, jac, n_int, *prop);
+        else
+            launch_k(k_chain_setup_grad<false>, dim3((unsigned)(n_int + n_ext)), dim3(64), s, kt, theta, B, net, ref,
+                     rec, jac, n_int, MalaProp{});
     } else {
         const int64_t n_half = (B + 63) / 64;
         launch_k(k_chain_setup, dim3((unsigned)(2 * n_half)), dim3(64), s, kt, theta, B, net, ref, rec, n_half);
@@ -606,28 +666,29 @@ hipError_t launch_chain_setup(const double* theta, int64_t B, const Network& net
     return hipGetLastError();
 }
 
-hipError_t launch_summary(const SummaryArgs& a, const int64_t* bin_first_item, double* summary, hipStream_t s,
-                          KTime kt_items, KTime kt_reduce) {
-    const unsigned g1 = (unsigned)a.n_items;  // one workgroup per item
+hipError_t launch_summary(const SummaryArgs& a, hipStream_t s, KTime kt) {
+    const unsigned g = (unsigned)a.n_bins;  // one workgroup per bin
+    const bool nrt = a.ref.waveform == kWfNrtv2;
     switch (a.n_det) {
-        case 1: launch_k(k_summary_items<1>, dim3(g1), dim3(256), s, kt_items, a); break;
-        case 2: launch_k(k_summary_items<2>, dim3(g1), dim3(256), s, kt_items, a); break;
-        default: launch_k(k_summary_items<3>, dim3(g1), dim3(256), s, kt_items, a); break;
+        case 1:
+            nrt ? launch_k(k_summary_bins<1, kWfNrtv2>, dim3(g), dim3(kSumThreads), s, kt, a)
+                : launch_k(k_summary_bins<1, kWfTaylorF2>, dim3(g), dim3(kSumThreads), s, kt, a);
+            break;
+        case 2:
+            nrt ? launch_k(k_summary_bins<2, kWfNrtv2>, dim3(g), dim3(kSumThreads), s, kt, a)
+                : launch_k(k_summary_bins<2, kWfTaylorF2>, dim3(g), dim3(kSumThreads), s, kt, a);
+            break;
+        default:
+            nrt ? launch_k(k_summary_bins<3, kWfNrtv2>, dim3(g), dim3(kSumThreads), s, kt, a)
+                : launch_k(k_summary_bins<3, kWfTaylorF2>, dim3(g), dim3(kSumThreads), s, kt, a);
+            break;
     }
-    const int64_t tot = (int64_t)a.n_det * a.n_bins * 7;
-    launch_k(k_summary_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), s, kt_reduce, a.partials,
-                       bin_first_item, a.n_bins, a.n_det, summary);
     return hipGetLastError();
 }
 
 hipError_t launch_node_tables(const NodeArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_node_tables, dim3((unsigned)((a.n_nodes_pad + 255) / 256)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_event_scales, dim3((unsigned)a.n_det), dim3(64), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_loglike_full(const FullArgs& a, int64_t B, hipStream_t s, KTime kt) {
-    launch_k(k_loglike_full, dim3((unsigned)B), dim3(kFullThreads), s, kt, a);
     return hipGetLastError();
 }
 

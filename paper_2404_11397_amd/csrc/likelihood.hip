@@ -594,10 +594,44 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
 // walk (which spills at 4); 2 for the TaylorF2 FP64 global-table walk (170 registers: faster
 // than 3 with spills or 4 with more) and for NRTidalv2, whose 26 adjoint accumulators and
 // per-edge model would otherwise spill.
-template <int ND, bool MIXED, int WF, bool LT = false>
+// The end of a fused MALA step for one chain (lanes 0..12 hold d lnL'/dtheta_i, all lanes
+// active): gz' = d lnL'/dz (d/dcos iota = -(d/diota)/sin iota, d/dsin dec = (d/ddec)/cos dec),
+// log alpha = lnL' - lnL + log q(z|z') - log q(z'|z) with log q(b|a) = -sum (b - a - s g(a)/2)^2
+// / (2 s), accepted when log u < log alpha; then (z, lnL, gz) <- (z', lnL', gz').
+__device__ inline void mala_accept(const MalaEpi& me, int64_t chain, int lane, double lnl_new, double g) {
+    const bool c = lane < 13;
+    const int64_t o = chain * 13 + (c ? lane : 0);
+    double si = me.s[0];
+#pragma unroll
+    for (int i = 1; i < 13; ++i) si = lane == i ? me.s[i] : si;
+    double gzp = g;
+    if (lane == 9) gzp = -g / sin(me.thp[o]);
+    if (lane == 12) gzp = g / cos(me.thp[o]);
+    double term = 0.0, zpi = 0.0;
+    if (c) {
+        const double zi = me.z[o];
+        zpi = me.zp[o];
+        const double rb = zi - zpi - 0.5 * si * gzp;      // z - z' - s g(z')/2
+        const double rf = zpi - zi - 0.5 * si * me.gz[o];  // z' - z - s g(z)/2
+        term = (rf * rf - rb * rb) / (2.0 * si);
+    }
+    term = wave_sum(term);
+    const double log_alpha = lnl_new - me.lnl[chain] + term;
+    const bool accept = isfinite(lnl_new) && me.logu[chain] < log_alpha;
+    if (accept && c) {
+        me.z[o] = zpi;
+        me.gz[o] = gzp;
+    }
+    if (lane == 0) {
+        if (accept) me.lnl[chain] = lnl_new;
+        me.accepted[chain] = accept ? 1 : 0;
+    }
+}
+
+template <int ND, bool MIXED, int WF, bool LT = false, bool MALA = false>
 __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu_waves_per_eu((WF == kWfNrtv2 || !(LT || MIXED)) ? 2 : 3))) void k_loglike_grad(
     EventDev ev, const double* __restrict__ recs, const double* __restrict__ jac, int64_t B,
-    double* __restrict__ lnl, double* __restrict__ grad) {
+    double* __restrict__ lnl, double* __restrict__ grad, MalaEpi me) {
     __shared__ double2 tab[kPhasorN];
     load_phasor_table(ev, tab);
     if constexpr (LT) {
@@ -615,8 +649,12 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
     const double* rec = recs + chain * kRecStride;
     const double status = rec[kRecStatus];
     if (!(status == 1.0)) {
-        if (lane == 0) lnl[chain] = (status == 0.0) ? -__builtin_inf() : __builtin_nan("");
-        if (lane < 13) grad[chain * 13 + lane] = (status == 0.0) ? 0.0 : __builtin_nan("");
+        if constexpr (MALA) {
+            if (lane == 0) me.accepted[chain] = 0;  // a proposal outside the prior box, or not physical
+        } else {
+            if (lane == 0) lnl[chain] = (status == 0.0) ? -__builtin_inf() : __builtin_nan("");
+            if (lane < 13) grad[chain * 13 + lane] = (status == 0.0) ? 0.0 : __builtin_nan("");
+        }
         return;
     }
     // IMRPhenomD_NRTidalv2: the chain's 29 node parameters are read by the walk from LDS
@@ -756,10 +794,9 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
     //   intrinsic i:  dK_d = K_d (d ln amp - 2 pi i d dc_const)
     //   dL: dK_d = -K_d / dL;  phic: dK_d = 2i K_d;  tc: d dtau_d = 1
     //   angles a:     dK_d = G dP_d,  d dtau_d = d dt_d
-    if (lane == 0) lnl[chain] = acc;
+    double g = 0.0;
     if (lane < 13) {
         const double* J = jac + chain * kJacStride;
-        double g = 0.0;
         if (lane < 6 && WF == kWfNrtv2) {
 #pragma unroll
             for (int b = 0; b < NA; ++b) g = fma(A[b], J[kJacInt + b * 6 + lane], g);
@@ -796,7 +833,12 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
                 g += ZR[d] * kr - ZI[d] * ki + Tt[d] * J[kJacExt + (d * 3 + 2) * 4 + a];
             }
         }
-        grad[chain * 13 + lane] = g;
+    }
+    if constexpr (MALA) {
+        mala_accept(me, chain, lane, acc, g);
+    } else {
+        if (lane == 0) lnl[chain] = acc;
+        if (lane < 13) grad[chain * 13 + lane] = g;
     }
 }
 
@@ -835,48 +877,56 @@ hipError_t launch_loglike(const EventDev& ev, const double* rec, int64_t B, int 
     return hipGetLastError();
 }
 
-template <int ND>
+template <int ND, bool MALA>
 static void grad_nd(const EventDev& ev, const double* rec, const double* jac, int64_t B, int mixed, double* lnl,
-                    double* grad, hipStream_t s, KTime kt) {
+                    double* grad, hipStream_t s, KTime kt, const MalaEpi& me) {
     const unsigned grid = (unsigned)((B + 3) / 4);
+    const unsigned grid_lt = (unsigned)((B + kStageChains - 1) / kStageChains);
+    const dim3 blk(256), blk_lt(64 * kStageChains);
     if (ev.waveform == kWfNrtv2) {
         const size_t lb = staged_nrt_table_bytes(ND, ev.n_nodes_pad);
         const size_t lb32 = staged_nrt_table32_bytes(ND, ev.n_nodes_pad);
         if (mixed && lb32 <= kNrtStageMaxBytes)
-            launch_k_lds(k_loglike_grad<ND, true, kWfNrtv2, true>,
-                         dim3((unsigned)((B + kStageChains - 1) / kStageChains)), dim3(64 * kStageChains), lb32,
-                         s, kt, ev, rec, jac, B, lnl, grad);
+            launch_k_lds(k_loglike_grad<ND, true, kWfNrtv2, true, MALA>, dim3(grid_lt), blk_lt, lb32, s, kt, ev, rec,
+                         jac, B, lnl, grad, me);
         else if (mixed)
-            launch_k(k_loglike_grad<ND, true, kWfNrtv2>, dim3(grid), dim3(256), s, kt, ev, rec, jac, B,
-                               lnl, grad);
+            launch_k(k_loglike_grad<ND, true, kWfNrtv2, false, MALA>, dim3(grid), blk, s, kt, ev, rec, jac, B, lnl,
+                     grad, me);
         else if (lb <= kNrtStageMaxBytes)
-            launch_k_lds(k_loglike_grad<ND, false, kWfNrtv2, true>,
-                         dim3((unsigned)((B + kStageChains - 1) / kStageChains)), dim3(64 * kStageChains), lb,
-                         s, kt, ev, rec, jac, B, lnl, grad);
+            launch_k_lds(k_loglike_grad<ND, false, kWfNrtv2, true, MALA>, dim3(grid_lt), blk_lt, lb, s, kt, ev, rec,
+                         jac, B, lnl, grad, me);
         else
-            launch_k(k_loglike_grad<ND, false, kWfNrtv2>, dim3(grid), dim3(256), s, kt, ev, rec, jac, B,
-                               lnl, grad);
+            launch_k(k_loglike_grad<ND, false, kWfNrtv2, false, MALA>, dim3(grid), blk, s, kt, ev, rec, jac, B, lnl,
+                     grad, me);
     } else {
         const size_t lb = staged_table_bytes(ND, ev.n_nodes_pad);
         if (mixed)
-            launch_k(k_loglike_grad<ND, true, kWfTaylorF2>, dim3(grid), dim3(256), s, kt, ev, rec, jac,
-                               B, lnl, grad);
+            launch_k(k_loglike_grad<ND, true, kWfTaylorF2, false, MALA>, dim3(grid), blk, s, kt, ev, rec, jac, B, lnl,
+                     grad, me);
         else if (lb <= kStageMaxBytes)
-            launch_k_lds(k_loglike_grad<ND, false, kWfTaylorF2, true>,
-                         dim3((unsigned)((B + kStageChains - 1) / kStageChains)), dim3(64 * kStageChains), lb,
-                         s, kt, ev, rec, jac, B, lnl, grad);
+            launch_k_lds(k_loglike_grad<ND, false, kWfTaylorF2, true, MALA>, dim3(grid_lt), blk_lt, lb, s, kt, ev,
+                         rec, jac, B, lnl, grad, me);
         else
-            launch_k(k_loglike_grad<ND, false, kWfTaylorF2>, dim3(grid), dim3(256), s, kt, ev, rec, jac,
-                               B, lnl, grad);
+            launch_k(k_loglike_grad<ND, false, kWfTaylorF2, false, MALA>, dim3(grid), blk, s, kt, ev, rec, jac, B,
+                     lnl, grad, me);
     }
 }
 
 hipError_t launch_loglike_grad(const EventDev& ev, const double* rec, const double* jac, int64_t B, int mixed,
-                               double* lnl, double* grad, hipStream_t s, KTime kt) {
-    switch (ev.n_det) {
-        case 1: grad_nd<1>(ev, rec, jac, B, mixed, lnl, grad, s, kt); break;
-        case 2: grad_nd<2>(ev, rec, jac, B, mixed, lnl, grad, s, kt); break;
-        default: grad_nd<3>(ev, rec, jac, B, mixed, lnl, grad, s, kt); break;
+                               double* lnl, double* grad, hipStream_t s, KTime kt, const MalaEpi* mala) {
+    const MalaEpi none{};
+    if (mala) {
+        switch (ev.n_det) {
+            case 1: grad_nd<1, true>(ev, rec, jac, B, mixed, lnl, grad, s, kt, *mala); break;
+            case 2: grad_nd<2, true>(ev, rec, jac, B, mixed, lnl, grad, s, kt, *mala); break;
+            default: grad_nd<3, true>(ev, rec, jac, B, mixed, lnl, grad, s, kt, *mala); break;
+        }
+    } else {
+        switch (ev.n_det) {
+            case 1: grad_nd<1, false>(ev, rec, jac, B, mixed, lnl, grad, s, kt, none); break;
+            case 2: grad_nd<2, false>(ev, rec, jac, B, mixed, lnl, grad, s, kt, none); break;
+            default: grad_nd<3, false>(ev, rec, jac, B, mixed, lnl, grad, s, kt, none); break;
+        }
     }
     return hipGetLastError();
 }

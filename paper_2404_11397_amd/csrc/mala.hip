@@ -3,11 +3,13 @@
 //
 // A chain's state is z (13): (Mc, q, chi1, chi2, Lambda1, Lambda2, dL, tc, phic, cos iota,
 // psi, ra, sin delta) -- the coordinates in which the priors are uniform -- with its lnL and
-// g = d lnL / dz.  One step: propose z' = z + (s/2) g + sqrt(s) xi (k_mala_propose), evaluate
-// lnL and its gradient at theta(z') with the likelihood kernels, then accept when
+// g = d lnL / dz.  One step is two launches of the gradient path: the gradient setup kernel
+// makes the proposal z' = z + (s/2) g + sqrt(s) xi and theta(z') (a NaN row outside the prior
+// box, which the likelihood kernel then skips), and the gradient kernel's epilogue accepts
+// when
 //   log u < lnL' - lnL + log q(z | z') - log q(z' | z),
 //   log q(b | a) = -sum_i (b_i - a_i - s_i g_i(a) / 2)^2 / (2 s_i),
-// and z' lies inside the prior box (k_mala_accept).  xi and log u are inputs.
+// updating (z, lnL, g) in place.  xi and log u are inputs.
 #include "rbl_host.h"
 
 using namespace rbl;
@@ -19,13 +21,6 @@ constexpr int kIota = 9, kDec = 12;
 struct MalaArgs {
     double s[13], sq[13], lo[13], hi[13];  // step (variance), its square root, prior box
 };
-
-__device__ inline bool inside_box(const double* z, const MalaArgs& m) {
-    bool in = true;
-#pragma unroll
-    for (int i = 0; i < 13; ++i) in = in && (z[i] >= m.lo[i]) && (z[i] <= m.hi[i]);
-    return in;
-}
 
 // theta(z): iota = arccos(cos iota), dec = arcsin(sin dec); the rest unchanged.
 __device__ inline void z_to_theta(const double* z, double* th) {
@@ -63,63 +58,6 @@ __global__ void k_mala_gradz(const double* __restrict__ theta, const double* __r
     }
     grad_to_z(th, gg, out);
     for (int i = 0; i < 13; ++i) gz[b * 13 + i] = out[i];
-}
-
-// z' = z + (s/2) g + sqrt(s) xi; theta(z'), or a NaN row when z' leaves the prior box
-// (the likelihood kernels then skip the chain).
-__global__ void k_mala_propose(const double* __restrict__ z, const double* __restrict__ gz,
-                               const double* __restrict__ xi, int64_t B, MalaArgs m, double* __restrict__ zp,
-                               double* __restrict__ thp) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    double q[13], th[13];
-    for (int i = 0; i < 13; ++i) q[i] = z[b * 13 + i] + 0.5 * m.s[i] * gz[b * 13 + i] + m.sq[i] * xi[b * 13 + i];
-    for (int i = 0; i < 13; ++i) zp[b * 13 + i] = q[i];
-    if (inside_box(q, m)) {
-        z_to_theta(q, th);
-    } else {
-        for (int i = 0; i < 13; ++i) th[i] = __builtin_nan("");
-    }
-    for (int i = 0; i < 13; ++i) thp[b * 13 + i] = th[i];
-}
-
-__global__ void k_mala_accept(double* __restrict__ z, double* __restrict__ lnl, double* __restrict__ gz,
-                              const double* __restrict__ zp, const double* __restrict__ thp,
-                              const double* __restrict__ lnlp, const double* __restrict__ gthp,
-                              const double* __restrict__ logu, int64_t B, MalaArgs m, int32_t* __restrict__ accepted) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    double a[13], q[13], ga[13], gq[13], th[13], gt[13];
-    for (int i = 0; i < 13; ++i) {
-        a[i] = z[b * 13 + i];
-        q[i] = zp[b * 13 + i];
-        ga[i] = gz[b * 13 + i];
-        th[i] = thp[b * 13 + i];
-        gt[i] = gthp[b * 13 + i];
-    }
-    const double lp = lnlp[b];
-    bool ok = inside_box(q, m) && isfinite(lp);
-    int32_t acc = 0;
-    if (ok) {
-        grad_to_z(th, gt, gq);
-        double lq_back = 0.0, lq_fwd = 0.0;  // log q(z | z'), log q(z' | z)
-        for (int i = 0; i < 13; ++i) {
-            const double rb = a[i] - q[i] - 0.5 * m.s[i] * gq[i];
-            const double rf = q[i] - a[i] - 0.5 * m.s[i] * ga[i];
-            lq_back -= rb * rb / (2.0 * m.s[i]);
-            lq_fwd -= rf * rf / (2.0 * m.s[i]);
-        }
-        const double log_alpha = lp - lnl[b] + lq_back - lq_fwd;
-        if (logu[b] < log_alpha) {
-            acc = 1;
-            for (int i = 0; i < 13; ++i) {
-                z[b * 13 + i] = q[i];
-                gz[b * 13 + i] = gq[i];
-            }
-            lnl[b] = lp;
-        }
-    }
-    accepted[b] = acc;
 }
 
 struct MalaWs {
@@ -193,14 +131,34 @@ extern "C" int rbl_mala_step(const rbl_event* ev, double* z_dev, double* lnl_dev
     if (!xi_dev || !logu_dev || !accepted_dev) return fail(RBL_EINVAL, "rbl_mala_step: null random numbers or output");
     hipStream_t s = (hipStream_t)hip_stream;
     MalaWs w = carve(workspace, B);
-    const unsigned grid = (unsigned)((B + 63) / 64);
-    hipLaunchKernelGGL(k_mala_propose, dim3(grid), dim3(64), 0, s, z_dev, gz_dev, xi_dev, B, m, w.zp, w.thp);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "rbl_mala_step: launch");
-    rc = rbl_loglike_grad(ev, w.thp, B, precision, w.lnlp, w.gthp, w.lws, hip_stream);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_mala_accept, dim3(grid), dim3(64), 0, s, z_dev, lnl_dev, gz_dev, w.zp, w.thp, w.lnlp, w.gthp,
-                       logu_dev, B, m, accepted_dev);
-    e = hipGetLastError();
+    if (fault_take(RBL_FAULT_LAUNCH)) return hip_fail(hipErrorLaunchFailure, "rbl_mala_step: injected");
+    // Two launches: the gradient setup kernel makes the proposal, the gradient kernel's
+    // epilogue takes the Metropolis decision and updates (z, lnL, gz) in place.
+    MalaProp mp{};
+    mp.z = z_dev;
+    mp.gz = gz_dev;
+    mp.xi = xi_dev;
+    mp.zp = w.zp;
+    mp.thp = w.thp;
+    MalaEpi me{};
+    me.zp = w.zp;
+    me.thp = w.thp;
+    me.logu = logu_dev;
+    me.z = z_dev;
+    me.gz = gz_dev;
+    me.lnl = lnl_dev;
+    me.accepted = accepted_dev;
+    for (int i = 0; i < 13; ++i) {
+        mp.s[i] = m.s[i];
+        mp.sq[i] = m.sq[i];
+        mp.lo[i] = m.lo[i];
+        mp.hi[i] = m.hi[i];
+        me.s[i] = m.s[i];
+    }
+    double* rec = (double*)w.lws;
+    double* jac = (double*)((char*)w.lws + align_up(B * kRecStride * (int64_t)sizeof(double)));
+    hipError_t e = launch_chain_setup(nullptr, B, ev->net, ev->ref, rec, jac, s, KTime{}, &mp);
+    if (e != hipSuccess) return hip_fail(e, "rbl_mala_step: setup launch");
+    e = launch_loglike_grad(ev->dev, rec, jac, B, precision == RBL_MIXED, nullptr, nullptr, s, KTime{}, &me);
     return e == hipSuccess ? RBL_OK : hip_fail(e, "rbl_mala_step: launch");
 }

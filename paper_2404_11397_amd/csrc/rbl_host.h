@@ -41,6 +41,12 @@ inline int64_t workspace_bytes(int64_t B, bool with_grad) {
     if (with_grad) bytes += align_up(B * kJacStride * (int64_t)sizeof(double));
     return bytes;
 }
+// Workspace bytes of the full-band likelihood: records, chain constants, tile partials.
+inline int64_t full_workspace_bytes(int64_t n_freq, int64_t B, int32_t waveform) {
+    const FullPlan p = full_plan(n_freq, B, waveform);
+    return align_up(B * kRecStride * (int64_t)sizeof(double)) + align_up(B * kFullStride * (int64_t)sizeof(double)) +
+           align_up(p.n_tiles * B * (int64_t)sizeof(double));
+}
 
 }  // namespace rbl
 
@@ -58,5 +64,6 @@ struct rbl_event {
     double* d_data = nullptr;  // only with RBL_KEEP_GRID
     double* d_psd = nullptr;
     int64_t footprint = 0;
+    std::vector<int64_t> edges;  // the bin edges (grid indices), given or placed on the device
     rbl::DevList mem;
 };

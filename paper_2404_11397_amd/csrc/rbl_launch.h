@@ -9,23 +9,18 @@ struct Theta13 {
     double v[13];
 };
 
-// One work item of the summary pass: a run of grid points inside one bin, with the bin
-// centre precomputed (one load gives a wavefront everything it needs before its data).
-struct SumItem {
-    int64_t start;
-    int32_t count, bin;
-    double fm;
-};
+// The summary pass: one workgroup of kSumThreads per bin, kSumPPT points per thread and pass.
+constexpr int kSumThreads = 1024;
+constexpr int kSumPPT = 1;
 
 struct SummaryArgs {
-    int64_t n_items;
-    const SumItem* items;
+    const int64_t* edges;  // [n_bins + 1] grid indices of the bin edges
     double f_low, delta_f;
     int64_t n_freq;
     int32_t n_det, n_bins;
-    const double* data;  // [n_det][n_freq][2]
-    const double* psd;   // [n_det][n_freq]
-    double* partials;    // [n_items][n_det][7]
+    const double* data;    // [n_det][n_freq][2]
+    const double* psd;     // [n_det][n_freq]
+    double* summary;       // [n_det][n_bins][7]
     const double* phasor;  // [kPhasorN][2] unit-phasor table
     RefConsts ref;
     int32_t ref_taper;
@@ -33,6 +28,7 @@ struct SummaryArgs {
 
 struct NodeArgs {
     int32_t n_nodes, n_nodes_pad, L, n_det, keep_b2, ref_taper;
+    int32_t centre;  // nodes are the edges and the bin centres interleaved (RBL_CENTRE_NODES)
     RefConsts ref;
     double *phi0, *ia0;
     float* ia0_32;
@@ -56,7 +52,29 @@ struct FullArgs {
     double f_low, delta_f;
     const double* data;
     const double* psd;
+    const double* phasor;  // [kPhasorN][2] unit-phasor table
     double* lnl;
+};
+
+// Full-band likelihood: chains are taken in groups of kFullGroup* that share every grid
+// point's loads and chain-independent waveform work; the grid is cut into tiles whose
+// per-chain partial sums are added in tile order.
+constexpr int kFullStride = 56;     // doubles of per-chain constants
+constexpr int kFullGroupTf2 = 8;    // chains per group (TaylorF2)
+constexpr int kFullGroupNrt = 4;    // chains per group (IMRPhenomD_NRTidalv2)
+struct FullPlan {
+    int64_t chains_per_group, n_groups, tile_points, n_tiles;
+};
+FullPlan full_plan(int64_t n_freq, int64_t B, int32_t waveform);
+struct FullTileArgs {
+    const double* consts;  // [B][kFullStride]
+    double* partials;      // [n_tiles][B]
+    const double* phasor;
+    const double* data;    // [n_det][n_freq][2]
+    const double* psd;     // [n_det][n_freq]
+    int64_t B, n_freq;
+    double f_low, delta_f;
+    int64_t tile_points, n_tiles, n_groups;
 };
 
 // Optional start / stop events recorded by the runtime at the kernel's own start and end
@@ -80,19 +98,41 @@ inline void launch_k_lds(F kernel, dim3 grid, dim3 block, size_t lds_bytes, hipS
         hipLaunchKernelGGL(kernel, grid, block, lds_bytes, s, args...);
 }
 
+// MALA step fused into the gradient kernels (Sec. II D): the proposal
+//   z' = z + (s/2) gz + sqrt(s) xi,  theta' = theta(z') (iota = arccos z_9, dec = arcsin z_12),
+// a NaN row outside the prior box, made by the gradient setup kernel; the Metropolis
+// decision on log u < lnL' - lnL + log q(z|z') - log q(z'|z) and the in-place update of
+// (z, lnL, gz), made by the gradient kernel's epilogue.
+struct MalaProp {
+    const double *z, *gz, *xi;  // [B][13]
+    double *zp, *thp;           // [B][13] proposals written for the epilogue
+    double s[13], sq[13], lo[13], hi[13];
+};
+struct MalaEpi {
+    const double *zp, *thp, *logu;
+    double *z, *gz, *lnl;  // updated in place where accepted
+    int32_t* accepted;
+    double s[13];
+};
+
 hipError_t launch_ref_setup(const double* theta_host, const Network& net, int32_t waveform, RefConsts* out_dev,
                             hipStream_t s);
+// prop (gradient setup only): take theta from the MALA proposal instead of `theta`.
 hipError_t launch_chain_setup(const double* theta, int64_t B, const Network& net, const RefConsts& ref,
-                              double* rec, double* jac, hipStream_t s, KTime kt = {});
-// kt_items / kt_reduce: timing of the per-item kernel and of the reduction.
-hipError_t launch_summary(const SummaryArgs& a, const int64_t* bin_first_item, double* summary, hipStream_t s,
-                          KTime kt_items = {}, KTime kt_reduce = {});
+                              double* rec, double* jac, hipStream_t s, KTime kt = {}, const MalaProp* prop = nullptr);
+hipError_t launch_summary(const SummaryArgs& a, hipStream_t s, KTime kt = {});
 hipError_t launch_node_tables(const NodeArgs& a, hipStream_t s);
 hipError_t launch_loglike(const EventDev& ev, const double* rec, int64_t B, int mixed, double* lnl, hipStream_t s,
                           KTime kt = {});
+// mala: finish a MALA step in the epilogue instead of writing lnl and grad.
 hipError_t launch_loglike_grad(const EventDev& ev, const double* rec, const double* jac, int64_t B, int mixed,
-                               double* lnl, double* grad, hipStream_t s, KTime kt = {});
-hipError_t launch_loglike_full(const FullArgs& a, int64_t B, hipStream_t s, KTime kt = {});
+                               double* lnl, double* grad, hipStream_t s, KTime kt = {}, const MalaEpi* mala = nullptr);
+// consts: B * kFullStride doubles; partials: n_tiles * B doubles (full_plan).
+hipError_t launch_loglike_full(const FullArgs& a, int64_t B, double* consts, double* partials, hipStream_t s,
+                               KTime kt = {});
+// Bin edges on the device by the post-Newtonian phase-bound ansatz; phi: n doubles of scratch.
+hipError_t launch_bin_edges(double f_low, double delta_f, int64_t n, int32_t n_bins, double* phi, int64_t* edges,
+                            hipStream_t s);
 hipError_t launch_strain(const RefConsts* cst_dev, int32_t waveform, int32_t taper, int32_t n_det, double f_low,
                          double delta_f, int64_t n_freq, double* out, hipStream_t s);
 

@@ -106,13 +106,13 @@ class Event:
 
     def __init__(self, data, psd, det_tensor, det_vertex, gmst, f_low, delta_f, theta_ref, edges,
                  waveform="taylorf2", keep_b2=False, ref_taper=False, keep_grid=False,
-                 device="cuda"):
+                 centre_nodes=False, device="cuda"):
         self.device = torch.device(device)
         tens = _host_f64(det_tensor).reshape(-1, 9)
         vert = _host_f64(det_vertex).reshape(-1, 3)
         nd = tens.shape[0]
         flags = (_lib.RBL_KEEP_B2 if keep_b2 else 0) | (_lib.RBL_REF_TAPER if ref_taper else 0) \
-            | (_lib.RBL_KEEP_GRID if keep_grid else 0)
+            | (_lib.RBL_KEEP_GRID if keep_grid else 0) | (_lib.RBL_CENTRE_NODES if centre_nodes else 0)
         if isinstance(data, torch.Tensor):
             d = torch.view_as_real(data.to(self.device, torch.complex128).contiguous()).contiguous()
             p = psd.to(self.device, torch.float64).contiguous()
@@ -127,22 +127,25 @@ class Event:
             dptr = d.ctypes.data_as(ctypes.c_void_p)
             pptr = p.ctypes.data_as(ctypes.c_void_p)
             self._keep = (d, p)
-        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64))
+        if isinstance(edges, (int, np.integer)):   # a bin count: edges placed on the device
+            n_bins, e, eptr = int(edges), None, None
+        else:
+            e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64))
+            n_bins, eptr = len(e) - 1, e.ctypes.data_as(ctypes.c_void_p)
         th = _host_f64(theta_ref).reshape(13)
-        desc = _lib.EventDesc(n_det=nd, waveform=WAVEFORMS[waveform], n_bins=len(e) - 1, flags=flags,
+        desc = _lib.EventDesc(n_det=nd, waveform=WAVEFORMS[waveform], n_bins=n_bins, flags=flags,
                               n_freq=n_freq, f_low=float(f_low), delta_f=float(delta_f),
                               gmst=float(gmst), data=dptr, psd=pptr,
                               det_tensor=tens.ctypes.data_as(ctypes.c_void_p),
                               det_vertex=vert.ctypes.data_as(ctypes.c_void_p),
-                              theta_ref=th.ctypes.data_as(ctypes.c_void_p),
-                              edges=e.ctypes.data_as(ctypes.c_void_p))
+                              theta_ref=th.ctypes.data_as(ctypes.c_void_p), edges=eptr)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             check(_lib.lib().rbl_event_create(ctypes.byref(desc), _stream_handle(self.device),
                                               ctypes.byref(handle)))
         self._h = handle
         self._keep = None
-        self.n_det, self.n_bins, self.n_freq = nd, len(e) - 1, n_freq
+        self.n_det, self.n_bins, self.n_freq = nd, n_bins, n_freq
         self.waveform = waveform
 
     def __del__(self):
@@ -159,6 +162,12 @@ class Event:
         """Summary data [n_det, n_bins, 7] = (ReA0, ImA0, ReA1, ImA1, B0, B1, B2)."""
         out = np.empty((self.n_det, self.n_bins, 7), dtype=np.float64)
         check(_lib.lib().rbl_event_get_summary(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def edges(self):
+        """The bin edges (grid indices) [n_bins + 1], given or placed on the device."""
+        out = np.empty(self.n_bins + 1, dtype=np.int64)
+        check(_lib.lib().rbl_event_get_edges(self._h, out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
     def footprint_bytes(self):
@@ -213,6 +222,27 @@ class Event:
         check(_lib.lib().rbl_loglike_full(self._h, _ptr(theta), B, _ptr(lnl), _ptr(ws),
                                           _stream_handle(theta.device)))
         return lnl
+
+
+def ref_search(event, lo, hi, start, sigma0, normals):
+    """CMA-ES reference-parameter search over the full-band lnL (rbl_ref_search).  normals:
+    [generations, lambda, 13] standard normals (the caller's random numbers).  Returns
+    (best theta [13], best lnL, trace [generations run, 15])."""
+    z = _host_f64(normals)
+    if z.ndim != 3 or z.shape[2] != 13:
+        raise ValueError("normals must have shape [generations, lambda, 13]")
+    gens, lam = z.shape[0], z.shape[1]
+    lo_, hi_, st = (_host_f64(v).reshape(13) for v in (lo, hi, start))
+    best = np.empty(13)
+    best_l = ctypes.c_double()
+    ran = ctypes.c_int32()
+    trace = np.empty((gens, 15))
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    with torch.cuda.device(event.device):
+        check(_lib.lib().rbl_ref_search(event._h, vp(lo_), vp(hi_), vp(st), float(sigma0), int(lam), int(gens),
+                                        vp(z), vp(best), ctypes.byref(best_l), vp(trace), ctypes.byref(ran),
+                                        _stream_handle(event.device)))
+    return best, best_l.value, trace[:ran.value]
 
 
 class LogLikeFn(torch.autograd.Function):

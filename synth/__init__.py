@@ -14,6 +14,7 @@ from .inputs import (  # noqa: F401
     detector_geometry,
     gaussian_noise,
     draw_theta,
+    mismatch_draws,
     PRIORS,
 )
 from .configs import (  # noqa: F401

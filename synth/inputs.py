@@ -119,6 +119,32 @@ def draw_theta(seed, n, prior, mc_window=None):
     return th
 
 
+def mismatch_draws(seed, n):
+    """n parameter vectors of the waveform-accuracy study (the paper's Tab. I): component
+    masses uniform in [0.5, 3] Msun (either may be the heavier: q = m2/m1 may exceed 1),
+    aligned spins uniform in [-0.05, 0.05], tidal deformabilities uniform in [0, 5000],
+    inclination uniform in [0, pi]; distance 100 Mpc and the remaining angles fixed
+    (the mismatch does not depend on them)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m1 = rng.uniform(0.5, 3.0, n)
+    m2 = rng.uniform(0.5, 3.0, n)
+    mc, q = component_to_chirp(m1, m2)
+    th = np.empty((n, N_PARAMS), dtype=np.float64)
+    th[:, 0], th[:, 1] = mc, q
+    th[:, 2] = rng.uniform(-0.05, 0.05, n)
+    th[:, 3] = rng.uniform(-0.05, 0.05, n)
+    th[:, 4] = rng.uniform(0.0, 5000.0, n)
+    th[:, 5] = rng.uniform(0.0, 5000.0, n)
+    th[:, 6] = 100.0
+    th[:, 7] = 0.0
+    th[:, 8] = 0.0
+    th[:, 9] = rng.uniform(0.0, np.pi, n)
+    th[:, 10] = 0.3
+    th[:, 11] = 1.1
+    th[:, 12] = 0.4
+    return th
+
+
 def component_to_chirp(m1, m2):
     """(m1, m2) -> (Mc, q) with q = m2/m1.  Pure unit bookkeeping used to state
     the injections of the workloads in the parameterisation above."""

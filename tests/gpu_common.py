@@ -41,7 +41,7 @@ def gpu_event(ev, keep_grid=False, device="cuda"):
     from paper_2404_11397_amd import Event
     return Event(ev.data, ev.psd, ev.tensors, ev.vertices, ev.gmst, ev.f[0], ev.delta_f, ev.theta_ref,
                  ev.edges, waveform=ev.approximant, keep_b2=ev.keep_b2, ref_taper=ev.ref_taper,
-                 keep_grid=keep_grid, device=device)
+                 keep_grid=keep_grid, centre_nodes=ev.centre, device=device)
 
 
 def rb_condition_scale(ev, theta):
@@ -50,8 +50,9 @@ def rb_condition_scale(ev, theta):
     s = ev.summary
     fn = ev.f[ev.edges]
     tot = 0.0
+    rc = L.node_ratios(ev, theta, L.bin_centres(ev)) if ev.centre else None
     for d, r in enumerate(L.node_ratios(ev, theta)):
-        r0 = 0.5 * (r[:, 1:] + r[:, :-1])
+        r0 = rc[d] if ev.centre else 0.5 * (r[:, 1:] + r[:, :-1])
         r1 = (r[:, 1:] - r[:, :-1]) / (fn[1:] - fn[:-1])
         tot = tot + (np.abs(s["A0"][d]) * np.abs(r0) + np.abs(s["A1"][d]) * np.abs(r1)
                      + 0.5 * s["B0"][d] * np.abs(r0) ** 2 + np.abs(s["B1"][d]) * np.abs(r0) * np.abs(r1)).sum(-1)

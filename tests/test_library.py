@@ -58,7 +58,8 @@ def _desc(L, **over):
     edges = over.get("edges", edges)
     th = over.get("theta", th)
     keep = (data, psd, tens, vert, th, edges)
-    d = L.EventDesc(n_det=nd, waveform=over.get("waveform", 0), n_bins=len(edges) - 1, flags=0, n_freq=n,
+    d = L.EventDesc(n_det=nd, waveform=over.get("waveform", 0), n_bins=len(edges) - 1, flags=over.get("flags", 0),
+                    n_freq=n,
                     f_low=20.0, delta_f=1.0, gmst=0.0,
                     data=data.ctypes.data_as(ctypes.c_void_p), psd=psd.ctypes.data_as(ctypes.c_void_p),
                     det_tensor=tens.ctypes.data_as(ctypes.c_void_p),
@@ -76,6 +77,7 @@ def _desc(L, **over):
     ({"psd": np.concatenate([np.ones(63), [np.nan]])[None, :]}, -3),
     ({"theta": np.array([1.2, 0.8, 0, 0, 0, 0, -40, 0, 0, 0.3, 0, 0, 0], float)}, -1),
     ({"waveform": 7}, -1),
+    ({"flags": 0x10 | 0x1}, -7),
 ])
 def test_event_create_rejects_bad_input_before_device_work(case, code):
     L = _lib()

@@ -229,3 +229,74 @@ def test_dual_numbers_against_closed_forms():
             - 0.5 / np.sqrt(1.9) * np.log(0.7))
     assert z.d[0] == pytest.approx(dzdx, rel=1e-14)
     assert z.d[1] == pytest.approx(dzdy, rel=1e-14)
+
+
+# ---- centre-node variant of Eq. (5) -----------------------------------------------------------
+
+def _brute_piecewise_linear(ev, th, centre):
+    """Full-grid likelihood of the piecewise-linear model h = h0 (r0 + r1 (f - f_m)) per bin,
+    written directly on the grid (no summary data), minus nothing: returns (lnL_model, S2)
+    with S2 = sum_b B2 |r1|^2 / 2 computed on the grid, so that the binned formula without
+    the B2 term equals lnL_model + S2."""
+    edges = np.asarray(ev.edges)
+    f = ev.f
+    fe = f[edges]
+    fm = 0.5 * (fe[:-1] + fe[1:])
+    b_of_k = L.bin_index(len(f), edges)
+    h0 = W.strain(f, ev.theta_ref, ev.tensors, ev.vertices, ev.gmst, ev.approximant, ev.ref_taper)
+    r_e = L.node_ratios(ev, th)
+    r_c = L.node_ratios(ev, th, fm) if centre else None
+    out, s2 = 0.0, 0.0
+    for d in range(len(h0)):
+        rl, rr = r_e[d][:, :-1], r_e[d][:, 1:]
+        r0 = r_c[d] if centre else 0.5 * (rl + rr)
+        r1 = (rr - rl) / (fe[1:] - fe[:-1])
+        model = h0[d][0] * (r0[:, b_of_k] + r1[:, b_of_k] * (f - fm[b_of_k]))
+        w = 4.0 * ev.delta_f / ev.psd[d]
+        out = out + (np.conj(model) * ev.data[d] * w).sum(-1).real - 0.5 * (np.abs(model) ** 2 * w).sum(-1)
+        q = np.abs(h0[d][0]) ** 2 * w * (f - fm[b_of_k]) ** 2
+        b2 = np.array([q[b_of_k == b].sum() for b in range(len(fm))])
+        s2 = s2 + 0.5 * (b2 * np.abs(r1) ** 2).sum(-1)
+    return out, s2
+
+
+@pytest.mark.parametrize("approximant", ["taylorf2", "phenomd_nrtv2"])
+def test_centre_variant_equals_its_piecewise_linear_model(approximant):
+    """The binned sum with r0 = r(f_m) is the full-grid likelihood of the piecewise-linear
+    ratio through r(f_m) with the edge slope, up to its dropped B2 term (brute force)."""
+    ev = small_event(approximant=approximant, duration=2.0, f_high=400.0, n_bins=30)
+    ev.centre = True
+    L.prepare(ev)
+    th = near_draws(ev.theta_ref, 4, 31, scale=5.0)
+    model, s2 = _brute_piecewise_linear(ev, th, centre=True)
+    np.testing.assert_allclose(L.loglike_rb(ev, th), model + s2, rtol=1e-11)
+    # and the edge variant matches its own model the same way (the two differ)
+    ev.centre = False
+    model_e, s2_e = _brute_piecewise_linear(ev, th, centre=False)
+    np.testing.assert_allclose(L.loglike_rb(ev, th), model_e + s2_e, rtol=1e-11)
+    assert np.abs(model - model_e).max() > 1e-6 * np.abs(model).max()
+
+
+def test_centre_variant_exact_at_reference_and_converges():
+    ev = small_event(duration=8.0, f_high=1024.0)
+    ev.centre = True
+    th0 = ev.theta_ref[None, :]
+    th = near_draws(ev.theta_ref, 8, 5)
+    full, full0 = L.loglike_full(ev, th), L.loglike_full(ev, th0)[0]
+    errs = []
+    for nb in (25, 50, 100, 200, 400):
+        ev.edges = binning.pn_bin_edges(ev.f[0], ev.delta_f, len(ev.f), nb)
+        L.prepare(ev)
+        assert L.loglike_rb(ev, th0)[0] == pytest.approx(full0, rel=1e-12)
+        errs.append(np.abs(L.loglike_rb(ev, th) - full).max())
+    errs = np.array(errs)
+    assert np.all(np.diff(errs) < 0), errs
+    slope = np.polyfit(np.log([25, 50, 100, 200, 400]), np.log(errs), 1)[0]
+    assert slope < -1.5, slope
+
+
+def test_centre_variant_refuses_b2():
+    ev = small_event(keep_b2=True)
+    ev.centre = True
+    with pytest.raises(ValueError):
+        L.loglike_rb(ev, ev.theta_ref[None, :])

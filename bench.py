@@ -228,6 +228,22 @@ def full_flops(n_freq, chains, n_det, waveform="taylorf2"):
     return n_freq * shared + n_freq * chains * per_chain
 
 
+def diag_information_sigma(grad_fn, x0, widths, cap):
+    """sigma_i = 1 / sqrt(I_ii) with I_ii = -d^2 lnL / dx_i^2 at x0, the diagonal of the
+    observed information, by central differences of the library gradient with steps
+    h_i = 1e-6 of the prior widths; components with I_ii <= 0 or a sigma above `cap` take
+    `cap`.  grad_fn: [n, 13] -> [n, 13] (numpy)."""
+    h = 1e-6 * widths
+    probes = np.repeat(x0[None, :], 26, axis=0)
+    for i in range(13):
+        probes[2 * i, i] += h[i]
+        probes[2 * i + 1, i] -= h[i]
+    g = grad_fn(probes)
+    info = np.array([-(g[2 * i, i] - g[2 * i + 1, i]) / (2 * h[i]) for i in range(13)])
+    sigma = np.where(info > 0, 1.0 / np.sqrt(np.maximum(info, 1e-300)), np.inf)
+    return np.minimum(sigma, cap)
+
+
 def _near_draws(ev, w, B, rng):
     """B draws around the injection with spreads 1/sqrt(-d2 lnL/dtheta_i2) there (the diagonal
     of the observed information, from the library gradient)."""

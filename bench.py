@@ -316,11 +316,12 @@ def full_band(torch, steps):
     return out
 
 
-def reference_search(torch, lam=2048, generations=250):
+def reference_search(torch, n_starts=16, lam=128, generations=400):
     """The CMA-ES reference-parameter search (rbl_ref_search) on a noise-free injection into the
-    3-detector 128 s TaylorF2 workload, over the GW170817 prior box from its centre: wall time,
-    candidate evaluations per second, and how far below the peak (<h, h>/2 at the injection)
-    the best candidate ends."""
+    3-detector 128 s TaylorF2 workload, over the GW170817 prior box: n_starts runs from points
+    drawn uniformly over the box, advanced together.  Wall time, candidate evaluations per
+    second, how far below the peak (<h, h>/2 at the injection) the best candidate ends, and how
+    many runs end within 13/2 of it."""
     from paper_2404_11397_amd import Event, bin_edges, ref_search, strain
     w = synth.workload("tf2_3det_128s", batch=1)
     dev = torch.device("cuda:0")
@@ -335,19 +336,26 @@ def reference_search(torch, lam=2048, generations=250):
                    0.0, 0.0, 0.0, 0.0, -np.pi / 2])
     hi = np.array([b["Mc"][1], b["q"][1], b["chi"][1], b["chi"][1], b["L"][1], b["L"][1], b["dL"][1], b["tc"][1],
                    2 * np.pi, np.pi, np.pi, 2 * np.pi, np.pi / 2])
-    normals = np.random.default_rng(9).standard_normal((generations, lam, 13))
+    rng = np.random.default_rng(21)
+    starts = lo + rng.random((n_starts, 13)) * (hi - lo)
+    normals = rng.standard_normal((n_starts, generations, lam, 13))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    best, best_l, trace = ref_search(ev, lo, hi, 0.5 * (lo + hi), 0.3, normals)
+    best, best_l, traces = ref_search(ev, lo, hi, starts, 0.3, normals)
     dt = time.perf_counter() - t0
     peak = float(ev.loglike_full(torch.as_tensor(th0[None, :], device=dev))[0])
+    finals = np.array([t[-1, 0] for t in traces])
+    evals = lam * sum(len(t) for t in traces)
     return {"workload": "noise-free TaylorF2 injection, 3 det, 128 s, 259585 points per detector; GW170817 prior box, "
-                        "start at its centre",
-            "lambda": lam, "generations": generations, "seconds": dt, "candidate_evals_per_s": lam * generations / dt,
+                        f"{n_starts} starts drawn uniformly over it",
+            "n_starts": n_starts, "lambda": lam, "generations": generations,
+            "generations_run": [len(t) for t in traces], "seconds": dt, "candidate_evals_per_s": evals / dt,
             "lnl_peak": peak, "lnl_found": best_l, "delta_lnl": peak - best_l,
-            "generation_of_best": int(np.argmax(trace[:, 0] >= best_l)),
+            "runs_within_6.5_of_peak": int(np.sum(peak - finals <= 6.5)),
+            "delta_lnl_per_run": (peak - finals).tolist(),
             "found_minus_injection": (best - th0).tolist(),
-            "what": "rbl_ref_search: CMA-ES over the full-band lnL on the device, update on the host"}
+            "what": "rbl_ref_search: CMA-ES runs over the full-band lnL, the populations of all runs evaluated "
+                    "together on the device each generation, updates on the host"}
 
 
 def summary_pass(torch, w, edges, data, psd, repeats=3):

@@ -150,18 +150,22 @@ int rbl_loglike_full(const rbl_event *ev, const double *theta_dev, int64_t B, do
  * binning needs as theta_ref for real data): CMA-ES (Hansen's (mu/mu_w, lambda)-CMA-ES with
  * cumulative step-size adaptation and its default constants) maximising the full-band lnL of
  * Eqs. (2)-(3), taper included, over the box [lo, hi] (host [13] each); the event must have
- * RBL_KEEP_GRID (its own theta_ref does not enter).  The search runs in box-normalised
- * coordinates from `start` (host [13], inside the box) with initial step sigma0 (> 0, in box
- * units); candidates outside the box rank last.  lambda (4 .. 2^20) candidates per generation
- * are evaluated together on the device; normals: host [generations][lambda][13] standard
- * normals, the caller's random numbers.  The search ends early, after *generations_run
- * generations, when the covariance can no longer be factored, its Cholesky diagonal spans
- * more than 1e7 (conditioning above 1e14), or the largest step exceeds the box width.
- * Outputs (host): best_theta [13] and best_lnl, the best candidate seen; trace (may be NULL)
- * [generations][15] = (best lnL so far, sigma, mean theta [13]) after each generation run.
- * Synchronous on hip_stream; allocates its device buffers for the duration of the call. */
-int rbl_ref_search(const rbl_event *ev, const double *lo, const double *hi, const double *start, double sigma0,
-                   int32_t lambda, int32_t generations, const double *normals, double *best_theta,
+ * RBL_KEEP_GRID (its own theta_ref does not enter).  n_starts (>= 1) independent runs, run r
+ * from starts[r] (host [n_starts][13], inside the box), each with initial step sigma0 (> 0,
+ * in box-normalised coordinates) and lambda (>= 4) candidates per generation; candidates
+ * outside the box rank last.  The runs advance together: one device evaluation per
+ * generation covers the populations of every run still going (lambda n_starts <= 2^20).
+ * normals: host [n_starts][generations][lambda][13] standard normals, the caller's random
+ * numbers.  Run r ends early, after generations_run[r] generations, when its covariance can
+ * no longer be factored, its Cholesky diagonal spans more than 1e7 (conditioning above
+ * 1e14), or its largest step exceeds the box width.  Outputs (host): best_theta [13] and
+ * best_lnl, the best candidate over all runs (the first one seen on a tie, runs in order);
+ * generations_run [n_starts]; trace (may be NULL) [n_starts][generations][15] = (the run's
+ * best lnL so far, sigma, mean theta [13]) after each of its generations (rows past
+ * generations_run[r] are left untouched).  Synchronous on hip_stream; allocates its device
+ * buffers for the duration of the call. */
+int rbl_ref_search(const rbl_event *ev, const double *lo, const double *hi, int32_t n_starts, const double *starts,
+                   double sigma0, int32_t lambda, int32_t generations, const double *normals, double *best_theta,
                    double *best_lnl, double *trace, int32_t *generations_run, void *hip_stream);
 
 /* Projected strain h_d(f_k; theta) on a grid for one parameter vector (host theta[13]);

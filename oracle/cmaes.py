@@ -20,6 +20,11 @@ path is taken as A^{-1}, the inverse of the lower Cholesky factor, so that sampl
 eigendecomposition (A^{-1} y_k = z_k has the same N(0, I) law under random selection).  The
 search runs in box-normalised coordinates u = (theta - lo) / (hi - lo); a candidate outside
 the box ranks below every candidate inside it.  Ties keep the candidates' order.
+
+The search is a multistart: independent runs from given starting points, the best candidate
+over all of them kept (a long inspiral's likelihood has many separated local maxima along the
+chirp-mass / coalescence-time ridge and over the sky; one run ends in whichever it meets
+first).
 """
 import numpy as np
 
@@ -83,28 +88,42 @@ class CMAES:
         self.sigma *= np.exp((self.cs / self.ds) * (norm_ps / self.chi_n - 1.0))
 
 
-def search(fitness_fn, lo, hi, start, sigma0, lam, normals):
-    """Maximise fitness_fn(theta [lambda, 13]) -> [lambda] over the box [lo, hi] from `start`,
-    with the standard normals [generations, lambda, 13].  Returns (best theta, its fitness,
-    trace [generations run, 2 + 13] of (best fitness so far, sigma, mean theta)); the run
-    ends early when the covariance's conditioning stops it (CMAES.factor)."""
+def search(fitness_fn, lo, hi, starts, sigma0, lam, normals):
+    """Maximise fitness_fn(theta [k, 13]) -> [k] over the box [lo, hi] by independent runs,
+    run r from starts[r] ([n_starts, 13]) with the standard normals normals[r]
+    ([n_starts, generations, lambda, 13]).  The runs advance together (one fitness call per
+    generation for the candidates of every run still going); run r ends early when its
+    covariance's conditioning stops it (CMAES.factor).  Returns (best theta over all runs, its
+    fitness, traces: one array [generations run, 2 + 13] per run of (the run's best fitness so
+    far, sigma, mean theta)).  On a tie the first candidate seen is kept, runs in order."""
     lo, hi = np.asarray(lo, float), np.asarray(hi, float)
+    starts = np.atleast_2d(np.asarray(starts, float))
     width = hi - lo
-    es = CMAES((np.asarray(start, float) - lo) / width, sigma0, lam)
-    best_f, best_x = -np.inf, np.asarray(start, float).copy()
-    trace = []
-    for z in normals:
-        if not es.factor():
+    runs = [CMAES((st - lo) / width, sigma0, lam) for st in starts]
+    going = [True] * len(runs)
+    run_best = [-np.inf] * len(runs)
+    best_f, best_x = -np.inf, starts[0].copy()
+    traces = [[] for _ in runs]
+    for g in range(normals.shape[1]):
+        for r, es in enumerate(runs):
+            if going[r] and not es.factor():
+                going[r] = False
+        active = [r for r in range(len(runs)) if going[r]]
+        if not active:
             break
-        u = es.ask(z)
+        u = np.concatenate([runs[r].ask(normals[r, g]) for r in active])
         inside = np.all((u >= 0.0) & (u <= 1.0), axis=1)
         theta = lo + u * width
-        f = np.full(lam, -np.inf)
+        f = np.full(len(u), -np.inf)
         if inside.any():
             f[inside] = fitness_fn(theta[inside])
-        k = int(np.argmax(np.where(np.isnan(f), -np.inf, f)))
-        if f[k] > best_f:
-            best_f, best_x = float(f[k]), theta[k].copy()
-        es.tell(np.where(np.isnan(f), -np.inf, f))
-        trace.append(np.concatenate([[best_f, es.sigma], lo + es.m * width]))
-    return best_x, best_f, np.array(trace)
+        f = np.where(np.isnan(f), -np.inf, f)
+        for j, r in enumerate(active):
+            fr = f[j * lam:(j + 1) * lam]
+            k = int(np.argmax(fr))
+            run_best[r] = max(run_best[r], fr[k])
+            if fr[k] > best_f:
+                best_f, best_x = float(fr[k]), theta[j * lam + k].copy()
+            runs[r].tell(fr)
+            traces[r].append(np.concatenate([[run_best[r], runs[r].sigma], lo + runs[r].m * width]))
+    return best_x, best_f, [np.array(t).reshape(-1, 2 + len(lo)) for t in traces]

@@ -81,7 +81,7 @@ def lib():
     L.rbl_loglike_grad_noalloc.restype = ctypes.c_int
     L.rbl_loglike_full.argtypes = [vp, vp, i64, vp, vp, vp]
     L.rbl_loglike_full.restype = ctypes.c_int
-    L.rbl_ref_search.argtypes = [vp, vp, vp, vp, dbl, i32, i32, vp, vp, vp, vp, vp, vp]
+    L.rbl_ref_search.argtypes = [vp, vp, vp, i32, vp, dbl, i32, i32, vp, vp, vp, vp, vp, vp]
     L.rbl_ref_search.restype = ctypes.c_int
     L.rbl_strain.argtypes = [i32, i32, vp, vp, dbl, dbl, dbl, i64, vp, i32, vp, vp]
     L.rbl_strain.restype = ctypes.c_int

@@ -298,13 +298,15 @@ __global__ __launch_bounds__(64) void k_chain_setup_grad(const double* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Summary data: one workgroup per bin, kSumThreads threads taking kSumPPT grid points each
-// per pass (all of a pass's data and PSD loads issued before its arithmetic), as many passes
-// as the bin needs; the reference waveform is generated inline, once per point, and
-// projected onto every detector, with the unit phasors from the LDS table.  Each thread adds
-// its points in order, the 7 ND sums are reduced across each wavefront (wave_sum_n) and the
-// wavefront totals added in wave order: the summary data are bitwise reproducible, and the
-// pass is one kernel with no partial sums in memory.
+// Summary data: one workgroup per bin, T threads taking up to PPT grid points each per pass
+// (point base + p T + t for thread t), as many passes as the bin needs.  A pass issues all of
+// its data and PSD loads before its arithmetic, and the first pass's loads go out before the
+// unit-phasor table is copied into LDS, so that the two memory round trips overlap.  The
+// reference waveform is generated inline, once per point, and projected onto every detector
+// with the unit phasors from the LDS table.  Each thread adds its points in order, the 7 ND
+// sums are reduced across each wavefront (wave_sum_n) and the wavefront totals added in wave
+// order: the summary data are bitwise reproducible, and the pass is one kernel with no
+// partial sums in memory.
 // ---------------------------------------------------------------------------
 template <int ND, int WF>
 __device__ inline void summary_point(const SummaryArgs& a, const double2* tab, int64_t k, double fm, const double* dre,
@@ -349,14 +351,31 @@ __device__ inline void summary_point(const SummaryArgs& a, const double2* tab, i
     }
 }
 
-template <int ND, int WF>
-__global__ __launch_bounds__(kSumThreads) void k_summary_bins(
-    SummaryArgs a) {
+template <int ND, int PPT>
+__device__ inline void summary_loads(const SummaryArgs& a, int64_t base, int64_t hi, int t, int T,
+                                     double (&re)[PPT][ND], double (&im)[PPT][ND], double (&ps)[PPT][ND]) {
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int64_t k = base + (int64_t)p * T + t;
+        if (k < hi) {
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                const int64_t o = (int64_t)d * a.n_freq + k;
+                const double2 v = reinterpret_cast<const double2*>(a.data)[o];
+                re[p][d] = v.x;
+                im[p][d] = v.y;
+                ps[p][d] = a.psd[o];
+            }
+        }
+    }
+}
+
+template <int ND, int WF, int T, int PPT>
+__global__ __launch_bounds__(T) void k_summary_bins(SummaryArgs a) {
     constexpr int NV = (7 * ND + 3) / 4 * 4;
-    constexpr int NW = kSumThreads / 64;
+    constexpr int NW = T / 64;
     __shared__ double2 tab[kPhasorN];
     __shared__ double red[NW][NV];
-    load_phasor_table(a.phasor, tab);
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wid = wave_id();
@@ -364,32 +383,23 @@ __global__ __launch_bounds__(kSumThreads) void k_summary_bins(
     const int64_t lo = a.edges[b];
     const int64_t hi = (b == a.n_bins - 1) ? a.n_freq : a.edges[b + 1];
     const double fm = a.f_low + 0.5 * (double)(a.edges[b] + a.edges[b + 1]) * a.delta_f;
+    double re[PPT][ND], im[PPT][ND], ps[PPT][ND];
+    summary_loads<ND, PPT>(a, lo, hi, t, T, re, im, ps);
+    load_phasor_table(a.phasor, tab);
     double acc[ND][7];
 #pragma unroll
     for (int d = 0; d < ND; ++d)
 #pragma unroll
         for (int j = 0; j < 7; ++j) acc[d][j] = 0.0;
-    for (int64_t base = lo; base < hi; base += (int64_t)kSumThreads * kSumPPT) {
-        double re[kSumPPT][ND], im[kSumPPT][ND], ps[kSumPPT][ND];
+    for (int64_t base = lo;;) {
 #pragma unroll
-        for (int p = 0; p < kSumPPT; ++p) {
-            const int64_t k = base + p * kSumThreads + t;
-            if (k < hi) {
-#pragma unroll
-                for (int d = 0; d < ND; ++d) {
-                    const int64_t o = (int64_t)d * a.n_freq + k;
-                    const double2 v = reinterpret_cast<const double2*>(a.data)[o];
-                    re[p][d] = v.x;
-                    im[p][d] = v.y;
-                    ps[p][d] = a.psd[o];
-                }
-            }
-        }
-#pragma unroll
-        for (int p = 0; p < kSumPPT; ++p) {
-            const int64_t k = base + p * kSumThreads + t;
+        for (int p = 0; p < PPT; ++p) {
+            const int64_t k = base + (int64_t)p * T + t;
             if (k < hi) summary_point<ND, WF>(a, tab, k, fm, re[p], im[p], ps[p], acc);
         }
+        base += (int64_t)T * PPT;
+        if (base >= hi) break;
+        summary_loads<ND, PPT>(a, base, hi, t, T, re, im, ps);
     }
     double part[NV], tot[NV];
 #pragma unroll
@@ -666,22 +676,20 @@ hipError_t launch_chain_setup(const double* theta, int64_t B, const Network& net
     return hipGetLastError();
 }
 
+template <int ND>
+void launch_summary_nd(const SummaryArgs& a, hipStream_t s, KTime kt) {
+    const dim3 g((unsigned)a.n_bins);  // one workgroup per bin
+    if (a.ref.waveform == kWfNrtv2)
+        launch_k(k_summary_bins<ND, kWfNrtv2, kSumThreadsNrt, kSumPptNrt>, g, dim3(kSumThreadsNrt), s, kt, a);
+    else
+        launch_k(k_summary_bins<ND, kWfTaylorF2, kSumThreadsTf2, kSumPptTf2>, g, dim3(kSumThreadsTf2), s, kt, a);
+}
+
 hipError_t launch_summary(const SummaryArgs& a, hipStream_t s, KTime kt) {
-    const unsigned g = (unsigned)a.n_bins;  // one workgroup per bin
-    const bool nrt = a.ref.waveform == kWfNrtv2;
     switch (a.n_det) {
-        case 1:
-            nrt ? launch_k(k_summary_bins<1, kWfNrtv2>, dim3(g), dim3(kSumThreads), s, kt, a)
-                : launch_k(k_summary_bins<1, kWfTaylorF2>, dim3(g), dim3(kSumThreads), s, kt, a);
-            break;
-        case 2:
-            nrt ? launch_k(k_summary_bins<2, kWfNrtv2>, dim3(g), dim3(kSumThreads), s, kt, a)
-                : launch_k(k_summary_bins<2, kWfTaylorF2>, dim3(g), dim3(kSumThreads), s, kt, a);
-            break;
-        default:
-            nrt ? launch_k(k_summary_bins<3, kWfNrtv2>, dim3(g), dim3(kSumThreads), s, kt, a)
-                : launch_k(k_summary_bins<3, kWfTaylorF2>, dim3(g), dim3(kSumThreads), s, kt, a);
-            break;
+        case 1: launch_summary_nd<1>(a, s, kt); break;
+        case 2: launch_summary_nd<2>(a, s, kt); break;
+        default: launch_summary_nd<3>(a, s, kt); break;
     }
     return hipGetLastError();
 }

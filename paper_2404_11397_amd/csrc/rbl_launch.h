@@ -9,9 +9,12 @@ struct Theta13 {
     double v[13];
 };
 
-// The summary pass: one workgroup of kSumThreads per bin, kSumPPT points per thread and pass.
-constexpr int kSumThreads = 1024;
-constexpr int kSumPPT = 1;
+// The summary pass: one workgroup per bin of kSumThreads* threads, each taking kSumPpt* grid
+// points per pass (TaylorF2 / IMRPhenomD_NRTidalv2).
+constexpr int kSumThreadsTf2 = 256;
+constexpr int kSumPptTf2 = 4;
+constexpr int kSumThreadsNrt = 256;
+constexpr int kSumPptNrt = 2;
 
 struct SummaryArgs {
     const int64_t* edges;  // [n_bins + 1] grid indices of the bin edges

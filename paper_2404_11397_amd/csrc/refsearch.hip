@@ -7,8 +7,14 @@
 // step-size adaptation and the default constants, maximising, in box-normalised coordinates
 // u = (theta - lo) / (hi - lo); candidates are x = m + sigma A z with A the lower Cholesky
 // factor of C, and the step-size path uses A^{-1} <y>_w.  A candidate outside the box ranks
-// below every candidate inside it; equal fitness keeps the candidates' order.  The search
-// ends early once the covariance is too ill-conditioned to factor reliably.
+// below every candidate inside it; equal fitness keeps the candidates' order.  A run ends
+// early once its covariance is too ill-conditioned to factor reliably.
+//
+// Several independent runs from the caller's starting points (a multistart: the likelihood
+// surface of a long inspiral has many separated local maxima along the chirp-mass / time
+// ridge and over the sky, and one run ends in whichever it meets first) advance together:
+// each generation evaluates the populations of all running runs in one batch on the device,
+// and the best candidate over all runs is returned.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -89,10 +95,10 @@ struct Cmaes {
     }
 
     // Update from the candidates' steps y [lam][kN] and fitness [lam] (larger is better).
-    void tell(const std::vector<double>& y, const std::vector<double>& fit) {
+    void tell(const double* y, const double* fit) {
         std::vector<int> order((size_t)lam);
         std::iota(order.begin(), order.end(), 0);
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return fit[(size_t)a] > fit[(size_t)b]; });
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return fit[a] > fit[b]; });
         double yw[kN] = {};
         for (int i = 0; i < mu; ++i)
             for (int k = 0; k < kN; ++k) yw[k] += w[(size_t)i] * y[(size_t)order[(size_t)i] * kN + k];
@@ -134,57 +140,85 @@ struct Cmaes {
 
 }  // namespace
 
-extern "C" int rbl_ref_search(const rbl_event* ev, const double* lo, const double* hi, const double* start,
-                              double sigma0, int32_t lambda, int32_t generations, const double* normals,
-                              double* best_theta, double* best_lnl, double* trace, int32_t* generations_run,
-                              void* hip_stream) {
-    if (!ev || !lo || !hi || !start || !normals || !best_theta || !best_lnl || !generations_run)
+extern "C" int rbl_ref_search(const rbl_event* ev, const double* lo, const double* hi, int32_t n_starts,
+                              const double* starts, double sigma0, int32_t lambda, int32_t generations,
+                              const double* normals, double* best_theta, double* best_lnl, double* trace,
+                              int32_t* generations_run, void* hip_stream) {
+    if (!ev || !lo || !hi || !starts || !normals || !best_theta || !best_lnl || !generations_run)
         return fail(RBL_EINVAL, "rbl_ref_search: null argument");
     if (!(ev->flags & RBL_KEEP_GRID) || !ev->d_data)
         return fail(RBL_EUNSUPPORTED, "rbl_ref_search: the event was built without RBL_KEEP_GRID");
-    if (lambda < 4 || lambda > (1 << 20) || generations < 1)
-        return fail(RBL_EINVAL, "rbl_ref_search: need 4 <= lambda <= 2^20 and generations >= 1");
+    if (lambda < 4 || n_starts < 1 || (int64_t)lambda * n_starts > (1 << 20) || generations < 1)
+        return fail(RBL_EINVAL, "rbl_ref_search: need lambda >= 4, n_starts >= 1, lambda n_starts <= 2^20 and "
+                                "generations >= 1");
     if (!(sigma0 > 0.0) || !std::isfinite(sigma0)) return fail(RBL_EINVAL, "rbl_ref_search: sigma0 must be > 0");
-    double width[kN], u0[kN];
+    double width[kN];
     for (int i = 0; i < kN; ++i) {
         if (!(hi[i] > lo[i]) || !std::isfinite(lo[i]) || !std::isfinite(hi[i]))
             return fail(RBL_EINVAL, "rbl_ref_search: the box needs lo < hi, finite");
         width[i] = hi[i] - lo[i];
-        u0[i] = (start[i] - lo[i]) / width[i];
-        if (!(u0[i] >= 0.0 && u0[i] <= 1.0)) return fail(RBL_EINVAL, "rbl_ref_search: start outside the box");
+    }
+    const int R = n_starts;
+    std::vector<Cmaes> es;
+    es.reserve((size_t)R);
+    for (int r = 0; r < R; ++r) {
+        double u0[kN];
+        for (int i = 0; i < kN; ++i) {
+            u0[i] = (starts[r * kN + i] - lo[i]) / width[i];
+            if (!(u0[i] >= 0.0 && u0[i] <= 1.0)) return fail(RBL_EINVAL, "rbl_ref_search: a start outside the box");
+        }
+        es.emplace_back(u0, sigma0, lambda);
     }
     hipStream_t s = (hipStream_t)hip_stream;
     const int64_t L = lambda;
-    const int64_t ws_bytes = full_workspace_bytes(ev->n_freq, L, ev->waveform);
+    const int64_t B_max = L * R;
+    const int64_t ws_bytes = full_workspace_bytes(ev->n_freq, B_max, ev->waveform);
     DevList mem;
     double *d_theta = nullptr, *d_lnl = nullptr;
     void* d_ws = nullptr;
-    if (mem.alloc((void**)&d_theta, sizeof(double) * L * kN) != hipSuccess ||
-        mem.alloc((void**)&d_lnl, sizeof(double) * L) != hipSuccess || mem.alloc(&d_ws, (size_t)ws_bytes) != hipSuccess) {
+    if (mem.alloc((void**)&d_theta, sizeof(double) * B_max * kN) != hipSuccess ||
+        mem.alloc((void**)&d_lnl, sizeof(double) * B_max) != hipSuccess ||
+        mem.alloc(&d_ws, (size_t)ws_bytes) != hipSuccess) {
         mem.release();
         return fail(RBL_ENOMEM, "rbl_ref_search: device allocation");
     }
-    Cmaes es(u0, sigma0, lambda);
-    std::vector<double> y((size_t)L * kN), theta((size_t)L * kN), lnl((size_t)L), fit((size_t)L);
-    std::vector<char> inside((size_t)L);
+    std::vector<double> y((size_t)(B_max * kN)), theta((size_t)(B_max * kN)), lnl((size_t)B_max), fit((size_t)L);
+    std::vector<char> inside((size_t)B_max), running((size_t)R, 1);
+    std::vector<double> run_best((size_t)R, -HUGE_VAL);
+    std::vector<int> active;
     double best_f = -HUGE_VAL;
-    for (int i = 0; i < kN; ++i) best_theta[i] = start[i];
+    for (int i = 0; i < kN; ++i) best_theta[i] = starts[i];
+    for (int r = 0; r < R; ++r) generations_run[r] = generations;
     int rc = RBL_OK;
-    int32_t g = 0;
-    for (; g < generations && rc == RBL_OK; ++g) {
-        if (!es.factor()) break;  // converged as far as the covariance allows
-        for (int64_t k = 0; k < L; ++k) {
-            es.sample(normals + ((int64_t)g * L + k) * kN, &y[(size_t)(k * kN)]);
-            bool in = true;
-            for (int i = 0; i < kN; ++i) {
-                const double u = es.m[i] + es.sigma * y[(size_t)(k * kN + i)];
-                in = in && u >= 0.0 && u <= 1.0;
-                theta[(size_t)(k * kN + i)] = lo[i] + u * width[i];
+    for (int32_t g = 0; g < generations && rc == RBL_OK; ++g) {
+        active.clear();
+        for (int r = 0; r < R; ++r) {
+            if (!running[(size_t)r]) continue;
+            if (!es[(size_t)r].factor()) {  // this run has converged as far as its covariance allows
+                running[(size_t)r] = 0;
+                generations_run[r] = g;
+                continue;
             }
-            inside[(size_t)k] = in;
+            active.push_back(r);
         }
-        hipError_t e = hipMemcpyAsync(d_theta, theta.data(), sizeof(double) * L * kN, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = launch_chain_setup(d_theta, L, ev->net, ev->ref, (double*)d_ws, nullptr, s);
+        if (active.empty()) break;
+        const int64_t B = L * (int64_t)active.size();
+        for (size_t j = 0; j < active.size(); ++j) {
+            const Cmaes& e = es[(size_t)active[j]];
+            for (int64_t k = 0; k < L; ++k) {
+                const int64_t c = (int64_t)j * L + k;
+                e.sample(normals + (((int64_t)active[j] * generations + g) * L + k) * kN, &y[(size_t)(c * kN)]);
+                bool in = true;
+                for (int i = 0; i < kN; ++i) {
+                    const double u = e.m[i] + e.sigma * y[(size_t)(c * kN + i)];
+                    in = in && u >= 0.0 && u <= 1.0;
+                    theta[(size_t)(c * kN + i)] = lo[i] + u * width[i];
+                }
+                inside[(size_t)c] = in;
+            }
+        }
+        hipError_t e = hipMemcpyAsync(d_theta, theta.data(), sizeof(double) * B * kN, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = launch_chain_setup(d_theta, B, ev->net, ev->ref, (double*)d_ws, nullptr, s);
         if (e == hipSuccess) {
             FullArgs a{};
             a.recs = (const double*)d_ws;
@@ -197,36 +231,40 @@ extern "C" int rbl_ref_search(const rbl_event* ev, const double* lo, const doubl
             a.psd = ev->d_psd;
             a.phasor = ev->dev.phasor;
             a.lnl = d_lnl;
-            double* consts = (double*)((char*)d_ws + align_up(L * kRecStride * (int64_t)sizeof(double)));
-            double* partials = (double*)((char*)consts + align_up(L * kFullStride * (int64_t)sizeof(double)));
-            e = launch_loglike_full(a, L, consts, partials, s);
+            double* consts = (double*)((char*)d_ws + align_up(B * kRecStride * (int64_t)sizeof(double)));
+            double* partials = (double*)((char*)consts + align_up(B * kFullStride * (int64_t)sizeof(double)));
+            e = launch_loglike_full(a, B, consts, partials, s);
         }
-        if (e == hipSuccess) e = hipMemcpyAsync(lnl.data(), d_lnl, sizeof(double) * L, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(lnl.data(), d_lnl, sizeof(double) * B, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
             rc = hip_fail(e, "rbl_ref_search: fitness evaluation");
             break;
         }
-        int64_t kb = -1;
-        for (int64_t k = 0; k < L; ++k) {
-            const double f = lnl[(size_t)k];
-            fit[(size_t)k] = (inside[(size_t)k] && !std::isnan(f)) ? f : -HUGE_VAL;
-            if (kb < 0 || fit[(size_t)k] > fit[(size_t)kb]) kb = k;
-        }
-        if (fit[(size_t)kb] > best_f) {
-            best_f = fit[(size_t)kb];
-            for (int i = 0; i < kN; ++i) best_theta[i] = theta[(size_t)(kb * kN + i)];
-        }
-        es.tell(y, fit);
-        if (trace) {
-            double* t = trace + (int64_t)g * (kN + 2);
-            t[0] = best_f;
-            t[1] = es.sigma;
-            for (int i = 0; i < kN; ++i) t[2 + i] = lo[i] + es.m[i] * width[i];
+        for (size_t j = 0; j < active.size(); ++j) {
+            const int r = active[j];
+            int64_t kb = -1;
+            for (int64_t k = 0; k < L; ++k) {
+                const int64_t c = (int64_t)j * L + k;
+                const double f = lnl[(size_t)c];
+                fit[(size_t)k] = (inside[(size_t)c] && !std::isnan(f)) ? f : -HUGE_VAL;
+                if (kb < 0 || fit[(size_t)k] > fit[(size_t)kb]) kb = k;
+            }
+            run_best[(size_t)r] = std::max(run_best[(size_t)r], fit[(size_t)kb]);
+            if (fit[(size_t)kb] > best_f) {
+                best_f = fit[(size_t)kb];
+                for (int i = 0; i < kN; ++i) best_theta[i] = theta[(size_t)(((int64_t)j * L + kb) * kN + i)];
+            }
+            es[(size_t)r].tell(&y[(size_t)((int64_t)j * L * kN)], fit.data());
+            if (trace) {
+                double* t = trace + ((int64_t)r * generations + g) * (kN + 2);
+                t[0] = run_best[(size_t)r];
+                t[1] = es[(size_t)r].sigma;
+                for (int i = 0; i < kN; ++i) t[2 + i] = lo[i] + es[(size_t)r].m[i] * width[i];
+            }
         }
     }
     mem.release();
     *best_lnl = best_f;
-    *generations_run = g;
     return rc;
 }

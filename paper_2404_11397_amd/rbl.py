@@ -224,25 +224,34 @@ class Event:
         return lnl
 
 
-def ref_search(event, lo, hi, start, sigma0, normals):
-    """CMA-ES reference-parameter search over the full-band lnL (rbl_ref_search).  normals:
-    [generations, lambda, 13] standard normals (the caller's random numbers).  Returns
-    (best theta [13], best lnL, trace [generations run, 15])."""
+def ref_search(event, lo, hi, starts, sigma0, normals):
+    """CMA-ES reference-parameter search over the full-band lnL (rbl_ref_search): independent
+    runs from starts [n_starts, 13] (or one start [13]) advanced together.  normals:
+    [n_starts, generations, lambda, 13] (or [generations, lambda, 13] for one start) standard
+    normals, the caller's random numbers.  Returns (best theta [13], best lnL, traces): traces
+    is a list with one array [generations run, 15] per start."""
+    st = np.atleast_2d(_host_f64(starts))
     z = _host_f64(normals)
-    if z.ndim != 3 or z.shape[2] != 13:
-        raise ValueError("normals must have shape [generations, lambda, 13]")
-    gens, lam = z.shape[0], z.shape[1]
-    lo_, hi_, st = (_host_f64(v).reshape(13) for v in (lo, hi, start))
+    if z.ndim == 3:
+        z = z[None]
+    if st.ndim != 2 or st.shape[1] != 13:
+        raise ValueError("starts must have shape [n_starts, 13] or [13]")
+    if z.ndim != 4 or z.shape[0] != st.shape[0] or z.shape[3] != 13:
+        raise ValueError("normals must have shape [n_starts, generations, lambda, 13]")
+    n_starts, gens, lam = z.shape[0], z.shape[1], z.shape[2]
+    z = np.ascontiguousarray(z)
+    st = np.ascontiguousarray(st)
+    lo_, hi_ = (_host_f64(v).reshape(13) for v in (lo, hi))
     best = np.empty(13)
     best_l = ctypes.c_double()
-    ran = ctypes.c_int32()
-    trace = np.empty((gens, 15))
+    ran = np.zeros(n_starts, dtype=np.int32)
+    trace = np.empty((n_starts, gens, 15))
     vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
     with torch.cuda.device(event.device):
-        check(_lib.lib().rbl_ref_search(event._h, vp(lo_), vp(hi_), vp(st), float(sigma0), int(lam), int(gens),
-                                        vp(z), vp(best), ctypes.byref(best_l), vp(trace), ctypes.byref(ran),
+        check(_lib.lib().rbl_ref_search(event._h, vp(lo_), vp(hi_), int(n_starts), vp(st), float(sigma0), int(lam),
+                                        int(gens), vp(z), vp(best), ctypes.byref(best_l), vp(trace), vp(ran),
                                         _stream_handle(event.device)))
-    return best, best_l.value, trace[:ran.value]
+    return best, best_l.value, [trace[r, :ran[r]] for r in range(n_starts)]
 
 
 class LogLikeFn(torch.autograd.Function):

@@ -64,8 +64,9 @@ def test_box_search_stays_inside_and_reaches_the_bound():
     n = 13
     lo, hi = np.zeros(n), np.ones(n)
     z = _normals(6, 150, 12, n)
-    best_x, best_f, trace = cmaes.search(lambda th: th[:, 0] - np.sum((th[:, 1:] - 0.5) ** 2, axis=1), lo, hi,
-                                         np.full(n, 0.5), 0.2, 12, z)
+    best_x, best_f, traces = cmaes.search(lambda th: th[:, 0] - np.sum((th[:, 1:] - 0.5) ** 2, axis=1), lo, hi,
+                                          np.full(n, 0.5), 0.2, 12, z[None])
+    trace = traces[0]
     assert np.all((best_x >= 0) & (best_x <= 1))
     assert best_x[0] > 0.99 and best_f > 0.98
     assert np.all(np.diff(trace[:, 0]) >= 0)          # the best-so-far never decreases
@@ -109,3 +110,24 @@ def test_recombination_weights_give_mu_eff_near_a_quarter_of_lambda():
     for lam in (8, 16, 32, 64, 128, 1024):
         es = cmaes.CMAES(np.zeros(13), 1.0, lam)
         assert 0.2 < es.mueff / lam < 0.35
+
+
+def test_multistart_keeps_the_best_mode_and_its_runs_do_not_interact():
+    """Two separated maxima, the higher at b: a run started at each converges to its own, the
+    multistart returns b's (found by the first run, so keeping the last run's best fails), and
+    each run's trace is the one it has when run alone."""
+    n = 4
+    lo, hi = np.zeros(n), np.ones(n)
+    a, b = np.full(n, 0.25), np.full(n, 0.75)
+
+    def f(th):
+        return np.exp(-np.sum((th - a) ** 2, axis=1) / 0.005) + 2.0 * np.exp(-np.sum((th - b) ** 2, axis=1) / 0.005)
+
+    starts = np.array([b - 0.02, a + 0.02])
+    z = np.stack([_normals(11, 120, 10, n), _normals(12, 120, 10, n)])
+    best_x, best_f, traces = cmaes.search(f, lo, hi, starts, 0.05, 10, z)
+    assert abs(best_f - 2.0) < 1e-9 and np.max(np.abs(best_x - b)) < 1e-4
+    assert abs(traces[1][-1, 0] - 1.0) < 1e-9 and np.max(np.abs(traces[1][-1, 2:] - a)) < 1e-4
+    for r in range(2):
+        _, _, alone = cmaes.search(f, lo, hi, starts[r], 0.05, 10, z[r:r + 1])
+        np.testing.assert_array_equal(traces[r], alone[0])

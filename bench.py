@@ -358,9 +358,12 @@ def reference_search(torch, n_starts=16, lam=128, generations=400):
                     "together on the device each generation, updates on the host"}
 
 
-def summary_pass(torch, w, edges, data, psd, repeats=3):
-    """Average duration of the summary-data kernels of rbl_event_create (HIP events)."""
+def summary_pass(torch, w, edges, data, psd, repeats=5):
+    """Average duration of the summary-data kernel of rbl_event_create (HIP events), over
+    `repeats` event builds after one untimed build."""
     from paper_2404_11397_amd import Event, profile_enable, profile_read_summary
+    Event(data, psd, w["tensors"], w["vertices"], w["gmst"], w["f_low"], w["delta_f"], w["theta_inj"], edges,
+          waveform=w["waveform"], device=data.device)
     profile_enable(True)
     profile_read_summary()
     for _ in range(repeats):
@@ -654,20 +657,26 @@ def mala_rate(torch, ev, w, steps):
         a = float(ch.step((f * sigma) ** 2, lo, hi, xi, logu).double().mean())
         f *= 1.3 if a > 0.6 else 0.7
     step = (f * sigma) ** 2
-    xi = torch.randn((steps, B, 13), dtype=torch.float64, device="cuda:0", generator=gen)
-    logu = torch.log(torch.rand((steps, B), dtype=torch.float64, device="cuda:0", generator=gen))
-    acc = torch.zeros(B, dtype=torch.int64, device="cuda:0")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(steps):
-        acc += ch.step(step, lo, hi, xi[k], logu[k])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    return {"chain_steps_per_s": B * steps / dt, "us_per_step": dt / steps * 1e6, "chains": B, "steps": steps,
-            "acceptance": float(acc.sum()) / (B * steps), "step_factor": f, "precision": "fp64",
-            "what": "rbl_mala_step on the headline event (proposal, setup + lnL+grad kernels, accept), chains "
-                    "around the injection, preconditioned by the diagonal observed information, step adapted in "
-                    "warm-up"}
+    n_rand = 8
+    xi = torch.randn((n_rand, B, 13), dtype=torch.float64, device="cuda:0", generator=gen)
+    logu = torch.log(torch.rand((n_rand, B), dtype=torch.float64, device="cuda:0", generator=gen))
+    k = [0]
+
+    def one():
+        ch.step(step, lo, hi, xi[k[0] % n_rand], logu[k[0] % n_rand])
+        k[0] += 1
+
+    el, ku, su = time_calls(torch, one, steps, 2)
+    acc = torch.zeros(B, dtype=torch.int64, device="cuda:0")  # acceptance, outside the timed region
+    for j in range(steps):
+        acc += ch.step(step, lo, hi, xi[j % n_rand], logu[j % n_rand])
+    return {"chain_steps_per_s": B * steps / el, "us_per_step": el / steps * 1e6, "kernel_us": ku, "setup_us": su,
+            "chains": B, "steps": steps, "acceptance": float(acc.sum()) / (B * steps), "step_factor": f,
+            "precision": "fp64",
+            "what": "rbl_mala_step on the headline event: two kernels, the gradient setup with the Langevin "
+                    "proposal in its prologue and the lnL+grad kernel with the Metropolis decision in its "
+                    "epilogue; chains around the injection, preconditioned by the diagonal observed information, "
+                    "step adapted in warm-up; random numbers cycled from 8 pre-drawn sets"}
 
 
 def progress(msg):

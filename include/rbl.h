@@ -193,8 +193,8 @@ int rbl_event_info(const rbl_event *ev, int32_t *n_det, int32_t *n_bins, int32_t
 int rbl_bin_edges(double f_low, double delta_f, int64_t n_freq, int32_t n_bins, int64_t *edges_out);
 
 /* Kernel timing for benchmarks.  With every = n > 0, the first and then every n-th
- * rbl_loglike / rbl_loglike_grad / rbl_loglike_full call records HIP events on its own
- * stream at the start and end of its setup kernel and of its main kernel (the runtime
+ * rbl_loglike / rbl_loglike_grad / rbl_loglike_full / rbl_mala_step call records HIP events
+ * on its own stream at the start and end of its setup kernel and of its main kernel (the runtime
  * stamps the kernels themselves); every = 0 turns timing off.  Each timed call costs a
  * few microseconds of device time, so a sampled rate disturbs a throughput run less.
  * rbl_profile_read waits for the recorded events, returns the summed milliseconds of the

@@ -1,5 +1,6 @@
 // Host side of the C-ABI: validation, resident event state, kernel launches.
 #include <algorithm>
+#include <numeric>
 #include <array>
 #include <atomic>
 #include <cmath>
@@ -77,22 +78,17 @@ struct ProfState {
 };
 ProfState g_prof;
 
-struct CallTimer {
-    std::array<hipEvent_t, 4> ev{{nullptr, nullptr, nullptr, nullptr}};
-    bool active = false;
-    CallTimer() {
-        if (!g_prof.on || (g_prof.calls++ % g_prof.every) != 0) return;
-        for (auto& e : ev) e = g_prof.get();
-        active = ev[0] && ev[1] && ev[2] && ev[3];
-    }
-    KTime setup() const { return active ? KTime{ev[0], ev[1]} : KTime{}; }
-    KTime main() const { return active ? KTime{ev[2], ev[3]} : KTime{}; }
-    void done() {
-        if (active) g_prof.pending.push_back(ev);
-    }
-};
-
 }  // namespace
+
+CallTimer::CallTimer() {
+    if (!g_prof.on || (g_prof.calls++ % g_prof.every) != 0) return;
+    for (auto& e : ev) e = g_prof.get();
+    active = ev[0] && ev[1] && ev[2] && ev[3];
+}
+
+void CallTimer::done() {
+    if (active) g_prof.pending.push_back(ev);
+}
 
 extern "C" int rbl_profile_enable(int32_t every) {
     if (every < 0) return fail(RBL_EINVAL, "rbl_profile_enable: every must be >= 0");
@@ -331,8 +327,32 @@ extern "C" int rbl_event_create(const rbl_event_desc* desc, void* hip_stream, rb
         hipSuccess)
         return cleanup(hip_fail(e, "rbl_event_create: copy phasor table"));
 
+    // Workgroup order of the summary pass: bins by decreasing size, every other group of
+    // n_cu workgroups reversed (breadth-first dispatch puts workgroups w and w + n_cu on one
+    // CU, so a large bin shares its CU with a small one).
+    int n_cu = 256;
+    {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            n_cu = v;
+    }
+    std::vector<int32_t> order((size_t)nb);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return edges[x + 1] - edges[x] > edges[y + 1] - edges[y];
+    });
+    for (int64_t g0 = n_cu; g0 < nb; g0 += 2 * (int64_t)n_cu)
+        std::reverse(order.begin() + g0, order.begin() + std::min<int64_t>(g0 + n_cu, nb));
+    int32_t* d_order = nullptr;
+    if (tmp.alloc((void**)&d_order, sizeof(int32_t) * nb) != hipSuccess)
+        return cleanup(fail(RBL_ENOMEM, "rbl_event_create: device allocation (bin order)"));
+    if ((e = hipMemcpyAsync(d_order, order.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return cleanup(hip_fail(e, "rbl_event_create: copy bin order"));
+
     SummaryArgs sa{};
     sa.edges = d_edges;
+    sa.order = d_order;
     sa.f_low = ev->f_low;
     sa.delta_f = ev->delta_f;
     sa.n_freq = n;

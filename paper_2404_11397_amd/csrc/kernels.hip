@@ -160,8 +160,8 @@ constexpr int kIntLanes = 8;
 constexpr int kExtLanes = 4;
 
 // PROP: the chain's theta is the MALA proposal theta(z'), z' = z + (s/2) gz + sqrt(s) xi (a NaN
-// row outside the prior box); lane 0 of each intrinsic group writes z' and theta' for the
-// gradient kernel's accept epilogue.
+// row outside the prior box); lane 0 of each intrinsic group writes z' for the gradient
+// kernel's accept epilogue.
 template <bool PROP>
 __global__ __launch_bounds__(64) void k_chain_setup_grad(const double* __restrict__ theta, int64_t B, Network net,
                                                           RefConsts ref, double* __restrict__ rec,
@@ -189,10 +189,7 @@ __global__ __launch_bounds__(64) void k_chain_setup_grad(const double* __restric
         }
         if (intrinsic && tg == 0) {
 #pragma unroll
-            for (int i = 0; i < 13; ++i) {
-                mp.zp[b * 13 + i] = q[i];
-                mp.thp[b * 13 + i] = t[i];
-            }
+            for (int i = 0; i < 13; ++i) mp.zp[b * 13 + i] = q[i];
         }
     } else {
 #pragma unroll
@@ -306,7 +303,10 @@ __global__ __launch_bounds__(64) void k_chain_setup_grad(const double* __restric
 // with the unit phasors from the LDS table.  Each thread adds its points in order, the 7 ND
 // sums are reduced across each wavefront (wave_sum_n) and the wavefront totals added in wave
 // order: the summary data are bitwise reproducible, and the pass is one kernel with no
-// partial sums in memory.
+// partial sums in memory.  Workgroup w takes bin order[w]: bins sorted by size, the largest
+// first, the order reversed for every next group of as many workgroups as the device has
+// CUs, so that the workgroups that share a CU pair large bins with small ones (the largest
+// bins, up to a few thousand points, bound the pass).
 // ---------------------------------------------------------------------------
 template <int ND, int WF>
 __device__ inline void summary_point(const SummaryArgs& a, const double2* tab, int64_t k, double fm, const double* dre,
@@ -314,9 +314,9 @@ __device__ inline void summary_point(const SummaryArgs& a, const double2* tab, i
     const RefConsts& ref = a.ref;
     const double w = 4.0 * a.delta_f;
     const double f = a.f_low + (double)k * a.delta_f;
-    const double x = cbrt(f);
-    const double ix = 1.0 / x;
-    const double lx = log(x);
+    const double ix = inv_cbrt_nr(f);  // f^(-1/3)
+    const double x = f * ix * ix;
+    const double lx = log(f) * (1.0 / 3.0);
     double phi = 0.0;
     double amp = ref.amp0 * (ix * ix * ix) * sqrt(ix);  // f^(-7/6)
     if constexpr (WF == kWfNrtv2) {
@@ -336,7 +336,7 @@ __device__ inline void summary_point(const SummaryArgs& a, const double2* tab, i
         unit_phasor(fma(f, ref.tau0[d], phi) * (double)kPhasorN, tab, cu, su);
         const double hre = amp * (ref.h0fac_re[d] * cu - ref.h0fac_im[d] * su);
         const double him = amp * (ref.h0fac_re[d] * su + ref.h0fac_im[d] * cu);
-        const double wk = w / ps[d];
+        const double wk = w * rcp_nr(ps[d]);
         // d conj(h0) w and |h0|^2 w
         const double are = (dre[d] * hre + dim[d] * him) * wk;
         const double aim = (dim[d] * hre - dre[d] * him) * wk;
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(T) void k_summary_bins(SummaryArgs a) {
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wid = wave_id();
-    const int b = blockIdx.x;
+    const int b = a.order[blockIdx.x];
     const int64_t lo = a.edges[b];
     const int64_t hi = (b == a.n_bins - 1) ? a.n_freq : a.edges[b + 1];
     const double fm = a.f_low + 0.5 * (double)(a.edges[b] + a.edges[b + 1]) * a.delta_f;

@@ -595,31 +595,48 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
 // than 3 with spills or 4 with more) and for NRTidalv2, whose 26 adjoint accumulators and
 // per-edge model would otherwise spill.
 // The end of a fused MALA step for one chain (lanes 0..12 hold d lnL'/dtheta_i, all lanes
-// active): gz' = d lnL'/dz (d/dcos iota = -(d/diota)/sin iota, d/dsin dec = (d/ddec)/cos dec),
+// active): gz' = d lnL'/dz (d/dcos iota = -(d/diota)/sin iota and d/dsin dec = (d/ddec)/cos dec,
+// with sin iota = cos dec = sqrt(1 - z'^2) on [0, pi] and [-pi/2, pi/2]),
 // log alpha = lnL' - lnL + log q(z|z') - log q(z'|z) with log q(b|a) = -sum (b - a - s g(a)/2)^2
-// / (2 s), accepted when log u < log alpha; then (z, lnL, gz) <- (z', lnL', gz').
-__device__ inline void mala_accept(const MalaEpi& me, int64_t chain, int lane, double lnl_new, double g) {
+// / (2 s), accepted when log u < log alpha; then (z, lnL, gz) <- (z', lnL', gz').  The chain's
+// state (z, z', gz on lanes 0..12; lnL and log u) was loaded by the caller before the walk.
+struct MalaState {
+    double z = 0.0, zp = 0.0, gz = 0.0, lnl = 0.0, logu = 0.0;
+};
+
+__device__ inline MalaState mala_load(const MalaEpi& me, int64_t chain, int lane) {
+    MalaState m;
+    if (lane < 13) {
+        const int64_t o = chain * 13 + lane;
+        m.z = me.z[o];
+        m.zp = me.zp[o];
+        m.gz = me.gz[o];
+    }
+    m.lnl = me.lnl[chain];
+    m.logu = me.logu[chain];
+    return m;
+}
+
+__device__ inline void mala_accept(const MalaEpi& me, const MalaState& m, int64_t chain, int lane, double lnl_new,
+                                   double g) {
     const bool c = lane < 13;
     const int64_t o = chain * 13 + (c ? lane : 0);
     double si = me.s[0];
 #pragma unroll
     for (int i = 1; i < 13; ++i) si = lane == i ? me.s[i] : si;
     double gzp = g;
-    if (lane == 9) gzp = -g / sin(me.thp[o]);
-    if (lane == 12) gzp = g / cos(me.thp[o]);
-    double term = 0.0, zpi = 0.0;
+    if (lane == 9 || lane == 12) gzp = (lane == 9 ? -g : g) / sqrt(fma(-m.zp, m.zp, 1.0));
+    double term = 0.0;
     if (c) {
-        const double zi = me.z[o];
-        zpi = me.zp[o];
-        const double rb = zi - zpi - 0.5 * si * gzp;      // z - z' - s g(z')/2
-        const double rf = zpi - zi - 0.5 * si * me.gz[o];  // z' - z - s g(z)/2
+        const double rb = m.z - m.zp - 0.5 * si * gzp;   // z - z' - s g(z')/2
+        const double rf = m.zp - m.z - 0.5 * si * m.gz;  // z' - z - s g(z)/2
         term = (rf * rf - rb * rb) / (2.0 * si);
     }
     term = wave_sum(term);
-    const double log_alpha = lnl_new - me.lnl[chain] + term;
-    const bool accept = isfinite(lnl_new) && me.logu[chain] < log_alpha;
+    const double log_alpha = lnl_new - m.lnl + term;
+    const bool accept = isfinite(lnl_new) && m.logu < log_alpha;
     if (accept && c) {
-        me.z[o] = zpi;
+        me.z[o] = m.zp;
         me.gz[o] = gzp;
     }
     if (lane == 0) {
@@ -646,6 +663,8 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
     const int lane = threadIdx.x & 63;
     const int64_t chain = (int64_t)blockIdx.x * (LT ? kStageChains : 4) + wave_id();
     if (chain >= B) return;
+    MalaState ms;
+    if constexpr (MALA) ms = mala_load(me, chain, lane);  // in flight during the walk
     const double* rec = recs + chain * kRecStride;
     const double status = rec[kRecStatus];
     if (!(status == 1.0)) {
@@ -835,7 +854,7 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
         }
     }
     if constexpr (MALA) {
-        mala_accept(me, chain, lane, acc, g);
+        mala_accept(me, ms, chain, lane, acc, g);
     } else {
         if (lane == 0) lnl[chain] = acc;
         if (lane < 13) grad[chain * 13 + lane] = g;

@@ -139,10 +139,8 @@ extern "C" int rbl_mala_step(const rbl_event* ev, double* z_dev, double* lnl_dev
     mp.gz = gz_dev;
     mp.xi = xi_dev;
     mp.zp = w.zp;
-    mp.thp = w.thp;
     MalaEpi me{};
     me.zp = w.zp;
-    me.thp = w.thp;
     me.logu = logu_dev;
     me.z = z_dev;
     me.gz = gz_dev;
@@ -157,8 +155,10 @@ extern "C" int rbl_mala_step(const rbl_event* ev, double* z_dev, double* lnl_dev
     }
     double* rec = (double*)w.lws;
     double* jac = (double*)((char*)w.lws + align_up(B * kRecStride * (int64_t)sizeof(double)));
-    hipError_t e = launch_chain_setup(nullptr, B, ev->net, ev->ref, rec, jac, s, KTime{}, &mp);
+    CallTimer tm;
+    hipError_t e = launch_chain_setup(nullptr, B, ev->net, ev->ref, rec, jac, s, tm.setup(), &mp);
     if (e != hipSuccess) return hip_fail(e, "rbl_mala_step: setup launch");
-    e = launch_loglike_grad(ev->dev, rec, jac, B, precision == RBL_MIXED, nullptr, nullptr, s, KTime{}, &me);
+    e = launch_loglike_grad(ev->dev, rec, jac, B, precision == RBL_MIXED, nullptr, nullptr, s, tm.main(), &me);
+    tm.done();
     return e == hipSuccess ? RBL_OK : hip_fail(e, "rbl_mala_step: launch");
 }

@@ -1,5 +1,6 @@
 // Host-side state shared by the C-ABI translation units (events, errors, helpers).
 #pragma once
+#include <array>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -16,6 +17,17 @@ int hip_fail(hipError_t e, const char* what);
 
 // Failure injection (rbl_debug_inject_fault): true when this allocation / launch must fail.
 bool fault_take(int kind);
+
+// Kernel timing of a call while rbl_profile_enable is on (every n-th call): runtime start/stop
+// events around its setup and main kernels, collected by rbl_profile_read.
+struct CallTimer {
+    std::array<hipEvent_t, 4> ev{{nullptr, nullptr, nullptr, nullptr}};
+    bool active = false;
+    CallTimer();
+    KTime setup() const { return active ? KTime{ev[0], ev[1]} : KTime{}; }
+    KTime main() const { return active ? KTime{ev[2], ev[3]} : KTime{}; }
+    void done();
+};
 
 constexpr int64_t kAlign = 256;
 inline int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }

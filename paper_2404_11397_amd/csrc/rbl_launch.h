@@ -18,6 +18,7 @@ constexpr int kSumPptNrt = 2;
 
 struct SummaryArgs {
     const int64_t* edges;  // [n_bins + 1] grid indices of the bin edges
+    const int32_t* order;  // [n_bins] bin of each workgroup
     double f_low, delta_f;
     int64_t n_freq;
     int32_t n_det, n_bins;
@@ -108,11 +109,11 @@ inline void launch_k_lds(F kernel, dim3 grid, dim3 block, size_t lds_bytes, hipS
 // (z, lnL, gz), made by the gradient kernel's epilogue.
 struct MalaProp {
     const double *z, *gz, *xi;  // [B][13]
-    double *zp, *thp;           // [B][13] proposals written for the epilogue
+    double* zp;                 // [B][13] proposals written for the epilogue
     double s[13], sq[13], lo[13], hi[13];
 };
 struct MalaEpi {
-    const double *zp, *thp, *logu;
+    const double *zp, *logu;
     double *z, *gz, *lnl;  // updated in place where accepted
     int32_t* accepted;
     double s[13];

@@ -98,6 +98,17 @@ __device__ inline double rcp_nr(double b) {
     e = fma(-b, r, 1.0);
     return fma(r, e, r);
 }
+// f^(-1/3) for a positive, normal f below 2^100, to about one ulp: a single-precision
+// estimate from the hardware log2 and exp2 (relative error near 1e-6) refined by two Newton
+// steps for y^-3 = f, y <- y + (y / 3)(1 - f y^3), which square the relative error each time.
+__device__ inline double inv_cbrt_nr(double f) {
+    const float l = __builtin_amdgcn_logf((float)f);
+    double y = (double)__builtin_amdgcn_exp2f(l * (-1.0f / 3.0f));
+    double e = fma(-f, y * y * y, 1.0);
+    y = fma(y * (1.0 / 3.0), e, y);
+    e = fma(-f, y * y * y, 1.0);
+    return fma(y * (1.0 / 3.0), e, y);
+}
 template <int N> __host__ __device__ inline double val(const Dual<N>& x) { return x.v; }
 
 __host__ __device__ inline double dsin(double x) { return sin(x); }

@@ -15,7 +15,7 @@ from .rbl import PRECISIONS, _ptr, _stream_handle, check_buffers
 
 def _host13(x):
     a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(13))
-    return a, a.ctypes.data_as(ctypes.c_void_p)
+    return a, a.ctypes.data
 
 
 class Mala:

@@ -549,12 +549,12 @@ def build_serving_events(torch):
     return events, pools, specs, cuts
 
 
-def run_stream(srv, ids, pools, n, rate, precision):
+def run_stream(srv, ids, pools, n, rate, precision, seed=5999):
     """Submit n requests at Poisson arrival times; latency = done - arrival (host clock)."""
     import queue
     import threading
     from paper_2404_11397_amd import clock_ns
-    offs, evs, pidx = synth.serving_stream(n, rate)
+    offs, evs, pidx = synth.serving_stream(n, rate, seed=seed)
     q = queue.Queue()
     lat = np.empty(n)
     wait_adm = np.empty(n)
@@ -585,7 +585,9 @@ def run_stream(srv, ids, pools, n, rate, precision):
     return {"rate_hz": rate, "requests": n, "precision": precision,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "admit_wait_p50_ms": float(np.percentile(wait_adm, 50)),
-            "service_p50_ms": float(np.percentile(lat - wait_adm, 50)), "evals_per_s": float(chains.sum() / span),
+            "admit_wait_p99_ms": float(np.percentile(wait_adm, 99)),
+            "service_p50_ms": float(np.percentile(lat - wait_adm, 50)),
+            "service_p99_ms": float(np.percentile(lat - wait_adm, 99)), "evals_per_s": float(chains.sum() / span),
             "offered_evals_per_s": float(chains.sum() / (offs[-1] + 1e-9))}
 
 
@@ -612,11 +614,14 @@ def serving(torch, n_requests):
                                              ("baseline_fifo_fp64_plain", 1, False, False, "fp64")):
         with Server(budget, n_streams=streams, graphs=graphs, spin=spin) as srv:
             ids = [srv.add_event(e) for e in events]
-            # warm-up: every (event, pool) once, one at a time (the buffers a light load
-            # uses), then a pause in which the idle worker captures their graphs
+            # warm-up to the steady state: every (event, pool) once, one at a time, then a
+            # short Poisson stream (the buffers a light load rotates through), each followed
+            # by a pause in which the idle worker captures the graphs of the new keys
             for e in range(len(events)):
                 for k in range(len(pools[e])):
                     srv.wait(srv.submit(ids[e], pools[e][k], precision=prec))
+            time.sleep(1.0)
+            run_stream(srv, ids, pools, n_requests // 2, 2 * synth.SERVE_RATE_HZ, prec, seed=77)
             time.sleep(1.0)
             r = run_stream(srv, ids, pools, n_requests, synth.SERVE_RATE_HZ, prec)
             r["saturation"] = [run_stream(srv, ids, pools, n_requests, rate, prec) for rate in (2000.0, 20000.0)]

@@ -3,7 +3,8 @@
 //  k_full_consts  per-chain constants of the strain, from the setup record   [1 thread / chain]
 //  k_full_tiles   partial lnL of a group of C chains over a tile of grid points
 //                 [1 workgroup / (tile, chain group), one grid point per thread at a time]
-//  k_full_reduce  lnL of each chain: its tile partials summed in tile order  [1 thread / chain]
+//  k_full_reduce  lnL of each chain: its tile partials, lane j summing tiles j, j + 64, ... in
+//                 order, then the wavefront's fixed reduction tree         [1 wavefront / chain]
 //
 // A workgroup loads each grid point's data and PSD, and evaluates the chain-independent part
 // of the waveform there (x = f^(1/3), 1/x, ln x, f^(-7/6), the TaylorF2 basis or x^5.78),
@@ -131,22 +132,26 @@ __global__ __launch_bounds__(kFullTileThreads) void k_full_tiles(FullTileArgs a)
     }
     __syncthreads();
     if ((int)threadIdx.x < nc)
-        a.partials[t * a.B + c0 + threadIdx.x] =
+        a.partials[(c0 + threadIdx.x) * a.n_tiles + t] =
             ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
 }
 
-__global__ void k_full_reduce(const double* __restrict__ partials, const double* __restrict__ consts, int64_t B,
-                              int64_t n_tiles, double* __restrict__ lnl) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+__global__ __launch_bounds__(256) void k_full_reduce(const double* __restrict__ partials,
+                                                     const double* __restrict__ consts, int64_t B, int64_t n_tiles,
+                                                     double* __restrict__ lnl) {
+    const int64_t b = (int64_t)blockIdx.x * 4 + wave_id();
+    if (b >= B) return;  // wave-uniform
+    const int lane = threadIdx.x & 63;
     const double status = consts[b * kFullStride + kFcStatus];
     if (!(status == 1.0)) {
-        lnl[b] = (status == 0.0) ? -__builtin_inf() : __builtin_nan("");
+        if (lane == 0) lnl[b] = (status == 0.0) ? -__builtin_inf() : __builtin_nan("");
         return;
     }
+    const double* p = partials + b * n_tiles;
     double s = 0.0;
-    for (int64_t t = 0; t < n_tiles; ++t) s += partials[t * B + b];
-    lnl[b] = s;
+    for (int64_t t = lane; t < n_tiles; t += 64) s += p[t];
+    s = wave_sum(s);
+    if (lane == 0) lnl[b] = s;
 }
 
 template <int ND, int WF, int C>
@@ -194,8 +199,8 @@ hipError_t launch_loglike_full(const FullArgs& f, int64_t B, double* consts, dou
         case 2: nrt ? launch_tiles<2, kWfNrtv2, kFullGroupNrt>(a, s, kt) : launch_tiles<2, kWfTaylorF2, kFullGroupTf2>(a, s, kt); break;
         default: nrt ? launch_tiles<3, kWfNrtv2, kFullGroupNrt>(a, s, kt) : launch_tiles<3, kWfTaylorF2, kFullGroupTf2>(a, s, kt); break;
     }
-    hipLaunchKernelGGL(k_full_reduce, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, partials, consts, B,
-                       p.n_tiles, f.lnl);
+    hipLaunchKernelGGL(k_full_reduce, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, s, partials, consts, B, p.n_tiles,
+                       f.lnl);
     return hipGetLastError();
 }
 

@@ -183,7 +183,7 @@ __global__ __launch_bounds__(64) void k_chain_setup_grad(const double* __restric
         }
 #pragma unroll
         for (int i = 0; i < 13; ++i) t[i] = in ? q[i] : __builtin_nan("");
-        if (in) {
+        if (in && !intrinsic) {  // the intrinsic lanes use neither angle (only its finiteness)
             t[9] = acos(fmin(fmax(q[9], -1.0), 1.0));
             t[12] = asin(fmin(fmax(q[12], -1.0), 1.0));
         }

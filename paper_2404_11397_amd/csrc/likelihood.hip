@@ -589,11 +589,6 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
     }
 }
 
-// Occupancy target (waves per SIMD): 3 for the TaylorF2 LDS-table walk (unrolled by two, one
-// 8-wave workgroup per CU; two workgroups at 128 registers measured slower) and the mixed
-// walk (which spills at 4); 2 for the TaylorF2 FP64 global-table walk (170 registers: faster
-// than 3 with spills or 4 with more) and for NRTidalv2, whose 26 adjoint accumulators and
-// per-edge model would otherwise spill.
 // The end of a fused MALA step for one chain (lanes 0..12 hold d lnL'/dtheta_i, all lanes
 // active): gz' = d lnL'/dz (d/dcos iota = -(d/diota)/sin iota and d/dsin dec = (d/ddec)/cos dec,
 // with sin iota = cos dec = sqrt(1 - z'^2) on [0, pi] and [-pi/2, pi/2]),
@@ -645,6 +640,11 @@ __device__ inline void mala_accept(const MalaEpi& me, const MalaState& m, int64_
     }
 }
 
+// Occupancy target (waves per SIMD): 3 for the TaylorF2 LDS-table walk (unrolled by two, one
+// 8-wave workgroup per CU; two workgroups at 128 registers measured slower) and the mixed
+// walk (which spills at 4); 2 for the TaylorF2 FP64 global-table walk (170 registers: faster
+// than 3 with spills or 4 with more) and for NRTidalv2, whose 26 adjoint accumulators and
+// per-edge model would otherwise spill.
 template <int ND, bool MIXED, int WF, bool LT = false, bool MALA = false>
 __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu_waves_per_eu((WF == kWfNrtv2 || !(LT || MIXED)) ? 2 : 3))) void k_loglike_grad(
     EventDev ev, const double* __restrict__ recs, const double* __restrict__ jac, int64_t B,

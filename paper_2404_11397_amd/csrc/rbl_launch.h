@@ -72,7 +72,7 @@ struct FullPlan {
 FullPlan full_plan(int64_t n_freq, int64_t B, int32_t waveform);
 struct FullTileArgs {
     const double* consts;  // [B][kFullStride]
-    double* partials;      // [n_tiles][B]
+    double* partials;      // [B][n_tiles]
     const double* phasor;
     const double* data;    // [n_det][n_freq][2]
     const double* psd;     // [n_det][n_freq]
@@ -131,7 +131,7 @@ hipError_t launch_loglike(const EventDev& ev, const double* rec, int64_t B, int 
 // mala: finish a MALA step in the epilogue instead of writing lnl and grad.
 hipError_t launch_loglike_grad(const EventDev& ev, const double* rec, const double* jac, int64_t B, int mixed,
                                double* lnl, double* grad, hipStream_t s, KTime kt = {}, const MalaEpi* mala = nullptr);
-// consts: B * kFullStride doubles; partials: n_tiles * B doubles (full_plan).
+// consts: B * kFullStride doubles; partials: B * n_tiles doubles (full_plan).
 hipError_t launch_loglike_full(const FullArgs& a, int64_t B, double* consts, double* partials, hipStream_t s,
                                KTime kt = {});
 // Bin edges on the device by the post-Newtonian phase-bound ansatz; phi: n doubles of scratch.

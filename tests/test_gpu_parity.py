@@ -5,6 +5,8 @@ max |g - g_ref| <= 1e-5 max |g_ref|."""
 import numpy as np
 import pytest
 
+import synth
+
 from oracle import likelihood as L
 from oracle import waveform as W
 
@@ -203,6 +205,26 @@ def test_loglike_and_grad_parity_tf2_3det_128s_sampled(tf2_3det_128s):
     gs, ws = g[idx[:32]] * WIDTHS, wg * WIDTHS
     rel = np.abs(gs - ws).max(axis=1) / np.abs(ws).max(axis=1)
     say("tf2_3det_128s grad max rel err", rel.max())
+    assert np.all(rel <= 1e-5)
+
+
+def test_headline_batch_parity_tf2_3det_128s_grad8192(tf2_3det_128s):
+    """The benchmark's headline batch (the same event data, 8192 prior draws of seed 3004) in
+    one rbl_loglike_grad call, the launch the benchmark times; the oracle checks a seeded sample
+    of 64 chains, lnL and gradient."""
+    ev, _, gev = tf2_3det_128s
+    th = synth.workload("tf2_3det_128s_grad8192")["theta"]
+    assert th.shape == (8192, 13)
+    lg, g = gev.loglike_grad(_cuda(th))
+    lg, g = lg.cpu().numpy(), g.cpu().numpy()
+    idx = np.sort(np.random.default_rng(43).choice(len(th), 64, replace=False))
+    wl, wg = L.loglike_rb_grad(ev, th[idx])
+    scale = np.maximum(np.abs(wl), rb_condition_scale(ev, th[idx]))
+    err = np.abs(lg[idx] - wl) / scale
+    gs, ws = g[idx] * WIDTHS, wg * WIDTHS
+    rel = np.abs(gs - ws).max(axis=1) / np.abs(ws).max(axis=1)
+    say(f"headline batch: lnL max scaled err {err.max():.2e}, grad max rel err {rel.max():.2e}")
+    assert np.all(err <= 1e-8)
     assert np.all(rel <= 1e-5)
 
 

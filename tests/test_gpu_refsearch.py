@@ -75,3 +75,30 @@ def test_ref_search_finds_a_noise_free_injection():
         f"runs within 13/2 of the peak: {int(np.sum(peak - finals <= 6.5))} of 16")
     assert abs(best_l - want) <= 1e-8 * max(abs(want), peak)
     assert peak - best_l <= 6.5
+
+
+def test_ref_search_argument_checks():
+    """Refused before any device work: a population below 4, no start, a start outside the
+    box, an empty box, a non-positive step, and an event built without the full grid."""
+    from paper_2404_11397_amd import RblError, ref_search
+    ev = small_event(approximant="taylorf2", n_det=1, duration=4.0, f_high=256.0, n_bins=20)
+    L.prepare(ev)
+    gev = gpu_event(ev, keep_grid=True)
+    lo, hi = ev.theta_ref - 0.1 * np.abs(ev.theta_ref) - 1e-3, ev.theta_ref + 0.1 * np.abs(ev.theta_ref) + 1e-3
+    z = np.zeros((1, 2, 8, 13))
+    cases = [
+        (lo, hi, ev.theta_ref, 0.2, np.zeros((1, 2, 3, 13))),   # lambda < 4
+        (lo, hi, hi + 1.0, 0.2, z),                               # start outside the box
+        (hi, lo, ev.theta_ref, 0.2, z),                           # lo > hi
+        (lo, hi, ev.theta_ref, 0.0, z),                           # sigma0 = 0
+    ]
+    for a, b, st, sig, nz in cases:
+        with pytest.raises(RblError) as ei:
+            ref_search(gev, a, b, st, sig, nz)
+        assert ei.value.code == -1
+    with pytest.raises(ValueError):
+        ref_search(gev, lo, hi, ev.theta_ref, 0.2, np.zeros((2, 2, 8, 13)))  # one start, two sets of normals
+    nogrid = gpu_event(ev, keep_grid=False)
+    with pytest.raises(RblError) as ei:
+        ref_search(nogrid, lo, hi, ev.theta_ref, 0.2, z)
+    assert ei.value.code == -7

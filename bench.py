@@ -188,17 +188,45 @@ def cpu_baseline(workload, seconds):
 
 
 KERNEL_PASS_CALLS = 50  # calls of the separate pass that takes the kernel times
+# The GPU raises its clocks over the first ~30 ms of back-to-back work and lowers them again
+# when idle (measured on the headline step: 78, 46, 44, 43, 42, 41 us per step over the first
+# six chunks of 100 calls, 41 us from there on, and 47 us again after two idle seconds).  Every
+# timed region is therefore preceded by untimed calls until this much time has passed, so that
+# it measures the steady state of a sampler that keeps the device busy.
+CLOCK_RAMP_S = 0.3
 
 
-def time_calls(torch, fn, steps, warmup):
-    """Wall time of `steps` calls (no kernel timing inside the timed region), then the
-    average kernel durations (main, setup) [us] from a separate pass of
-    min(steps, KERNEL_PASS_CALLS) calls, each stamped with HIP start/stop events that the
-    runtime records at the kernels' own start and end on the launch stream."""
-    from paper_2404_11397_amd import profile_enable, profile_read
+def ramp(torch, fn, warmup, ramp_fn=None, seconds=CLOCK_RAMP_S):
+    """The untimed calls before a timed region: calls of ramp_fn (default: fn) until `seconds`
+    of back-to-back work have passed (the host waits for the device every 16 calls, so that it
+    never runs far ahead), then `warmup` calls of fn, with no pause in between.  Returns
+    (calls, seconds)."""
+    rf = ramp_fn or fn
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds:
+        rf()
+        n += 1
+        if n % 16 == 0:
+            torch.cuda.synchronize()
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    return n + warmup, time.perf_counter() - t0
+
+
+LAST_RAMP = {}
+
+
+def time_calls(torch, fn, steps, warmup, ramp_fn=None):
+    """Wall time of `steps` calls (no kernel timing inside the timed region) after the
+    untimed ramp, then the average kernel durations (main, setup) [us] from a separate pass
+    of min(steps, KERNEL_PASS_CALLS) calls, each stamped with HIP start/stop events that the
+    runtime records at the kernels' own start and end on the launch stream.  A call that
+    changes state (a sampler step) passes a ramp_fn that does not."""
+    from paper_2404_11397_amd import profile_enable, profile_read
+    n, dt = ramp(torch, fn, warmup, ramp_fn)
+    LAST_RAMP.update(calls=n, seconds=dt)
     t0 = time.perf_counter()
     for _ in range(steps):
         fn()
@@ -358,15 +386,21 @@ def reference_search(torch, n_starts=16, lam=128, generations=400):
                     "together on the device each generation, updates on the host"}
 
 
-def summary_pass(torch, w, edges, data, psd, repeats=5):
+def summary_pass(torch, w, edges, data, psd, repeats=5, ramp_fn=None):
     """Average duration of the summary-data kernel of rbl_event_create (HIP events), over
-    `repeats` event builds after one untimed build."""
+    `repeats` event builds after one untimed build.  With ramp_fn (device work), the builds run
+    at the clocks of sustained work: the clock ramp first, and 30 ms of ramp_fn calls before
+    each build."""
     from paper_2404_11397_amd import Event, profile_enable, profile_read_summary
+    if ramp_fn is not None:
+        ramp(torch, ramp_fn, 0)
     Event(data, psd, w["tensors"], w["vertices"], w["gmst"], w["f_low"], w["delta_f"], w["theta_inj"], edges,
           waveform=w["waveform"], device=data.device)
     profile_enable(True)
     profile_read_summary()
     for _ in range(repeats):
+        if ramp_fn is not None:
+            ramp(torch, ramp_fn, 0, seconds=0.03)
         Event(data, psd, w["tensors"], w["vertices"], w["gmst"], w["f_low"], w["delta_f"], w["theta_inj"], edges,
               waveform=w["waveform"], device=data.device)
     ms, n = profile_read_summary()
@@ -502,7 +536,7 @@ def nrtv2_forms(torch, steps):
         v["est_tflops"] = per * nb / (v["kernel_us"] * 1e-6) / 1e12
         v["est_frac_fp64_peak"] = v["est_tflops"] / PEAK_FP64_TFLOPS
     psd = torch.as_tensor(w["psd"], device="cuda:0")
-    su = summary_pass(torch, w, edges, data, psd)
+    su = summary_pass(torch, w, edges, data, psd, ramp_fn=lambda: ev.loglike(th, out=lnl[:B], workspace=ws))
     nbytes = w["n_freq"] * nd * 24
     res["forms"] = f
     res["summary_pass"] = {"us": su, "bytes": nbytes, "GB_per_s": nbytes / (su * 1e-6) / 1e9,
@@ -665,13 +699,21 @@ def mala_rate(torch, ev, w, steps):
     n_rand = 8
     xi = torch.randn((n_rand, B, 13), dtype=torch.float64, device="cuda:0", generator=gen)
     logu = torch.log(torch.rand((n_rand, B), dtype=torch.float64, device="cuda:0", generator=gen))
+    xis, logus = list(xi), list(logu)
     k = [0]
 
     def one():
-        ch.step(step, lo, hi, xi[k[0] % n_rand], logu[k[0] % n_rand])
+        ch.step(step, lo, hi, xis[k[0] % n_rand], logus[k[0] % n_rand])
         k[0] += 1
 
-    el, ku, su = time_calls(torch, one, steps, 2)
+    # the clock ramp runs lnL+grad calls on the same event and batch size: the chains advance
+    # only by the warm-up, timed and acceptance steps
+    th_r = torch.as_tensor(w["theta"], device="cuda:0")
+    out_r = (torch.empty(B, dtype=torch.float64, device="cuda:0"),
+             torch.empty((B, 13), dtype=torch.float64, device="cuda:0"))
+    ws_r = ev.workspace(B, with_grad=True)
+    el, ku, su = time_calls(torch, one, steps, 2,
+                            ramp_fn=lambda: ev.loglike_grad(th_r, out=out_r, workspace=ws_r))
     acc = torch.zeros(B, dtype=torch.int64, device="cuda:0")  # acceptance, outside the timed region
     for j in range(steps):
         acc += ch.step(step, lo, hi, xi[j % n_rand], logu[j % n_rand])
@@ -713,6 +755,7 @@ def main():
         ev.loglike_grad(theta, args.precision, out=(lnl, grad), workspace=ws)
 
     elapsed, kern_us, setup_us = time_calls(torch, step, args.steps, args.warmup)
+    ramp_calls, ramp_s = LAST_RAMP["calls"], LAST_RAMP["seconds"]
     progress(f"headline done: {B * args.steps / elapsed:.4g} evals/s")
 
     # per-call latency of a synchronised batch call
@@ -729,7 +772,7 @@ def main():
 
     nd = len(w["tensors"])
     psd = torch.as_tensor(w["psd"], device="cuda:0")
-    summ_us = summary_pass(torch, w, edges, data, psd)
+    summ_us = summary_pass(torch, w, edges, data, psd, ramp_fn=step)
     summ_bytes = w["n_freq"] * nd * 24  # data (complex128) + PSD (float64) per grid point and detector
 
     n_nodes = w["n_bins"] + 1
@@ -742,6 +785,10 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "clock_ramp": {"untimed_calls": ramp_calls, "seconds": ramp_s,
+                       "what": f"untimed calls before the timed region: steps until {CLOCK_RAMP_S} s of "
+                               f"back-to-back work had passed (the GPU raises its clocks over the first ~30 ms "
+                               f"of sustained work), then the {args.warmup} warm-up steps"},
         "ms_per_step": elapsed / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",

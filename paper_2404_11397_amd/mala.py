@@ -18,6 +18,10 @@ def _host13(x):
     return a, a.ctypes.data
 
 
+def _is_host13(x):
+    return (isinstance(x, np.ndarray) and x.dtype == np.float64 and x.size == 13 and x.flags.c_contiguous)
+
+
 class Mala:
     """B chains of the MALA local sampler on one event; state lives on the device."""
 
@@ -34,6 +38,9 @@ class Mala:
         self.accepted = torch.zeros(B, dtype=torch.int32, device=z.device)
         n = _lib.lib().rbl_mala_workspace_bytes(event._h, B)
         self._ws = torch.empty(max(n, 256), dtype=torch.uint8, device=z.device)
+        # the chain-state buffers never move: their pointers are taken once
+        self._p = [_ptr(t) for t in (self.z, self.lnl, self.gz, self.accepted, self._ws)]
+        self._box = (None, None, None, None)  # the last (step, lo, hi) arrays passed as they are
         check(_lib.lib().rbl_mala_init(event._h, _ptr(self.z), B, PRECISIONS[precision], _ptr(self.lnl),
                                        _ptr(self.gz), _ptr(self._ws), _stream_handle(z.device)))
 
@@ -43,10 +50,16 @@ class Mala:
         xi = xi.contiguous()
         logu = logu.contiguous()
         check_buffers(self.z, ((xi, (B, 13)), (logu, (B,))), None, 0)
-        s, sp = _host13(step)
-        l, lp = _host13(lo)
-        h, hp = _host13(hi)
-        check(_lib.lib().rbl_mala_step(self.event._h, _ptr(self.z), _ptr(self.lnl), _ptr(self.gz), B,
-                                       PRECISIONS[self.precision], sp, lp, hp, _ptr(xi), _ptr(logu),
-                                       _ptr(self.accepted), _ptr(self._ws), _stream_handle(self.z.device)))
+        last = self._box
+        if step is last[0] and lo is last[1] and hi is last[2]:
+            sp, lp, hp = last[3]  # the same float64 arrays as the last call (read at the call)
+        else:
+            s, sp = _host13(step)
+            l, lp = _host13(lo)
+            h, hp = _host13(hi)
+            if _is_host13(step) and _is_host13(lo) and _is_host13(hi):
+                self._box = (step, lo, hi, (sp, lp, hp))
+        pz, pl, pg, pa, pw = self._p
+        check(_lib.lib().rbl_mala_step(self.event._h, pz, pl, pg, B, PRECISIONS[self.precision], sp, lp, hp,
+                                       _ptr(xi), _ptr(logu), pa, pw, _stream_handle(self.z.device)))
         return self.accepted

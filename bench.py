@@ -625,10 +625,30 @@ def run_stream(srv, ids, pools, n, rate, precision, seed=5999):
             "offered_evals_per_s": float(chains.sum() / (offs[-1] + 1e-9))}
 
 
+def run_burst(srv, ids, pools, n, precision, seed=6001):
+    """Submit n requests at once (the serving stream's events and batches, all arriving
+    together) and wait for all: the server's capacity when it has a backlog."""
+    from paper_2404_11397_amd import clock_ns
+    _, evs, pidx = synth.serving_stream(n, synth.SERVE_RATE_HZ, seed=seed)
+    before = srv.stats()
+    t0 = clock_ns()
+    tickets = [srv.submit(ids[e], pools[e][k], precision=precision, grad=True, t_arrival_ns=t0)
+               for e, k in zip(evs, pidx)]
+    done = max(srv.wait(t)[2]["t_done_ns"] for t in tickets)
+    after = srv.stats()
+    chains = sum(pools[e][k].shape[0] for e, k in zip(evs, pidx))
+    return {"requests": n, "chains": int(chains), "seconds": (done - t0) * 1e-9,
+            "evals_per_s": chains / ((done - t0) * 1e-9),
+            "merged_launches": after["merged_launches"] - before["merged_launches"],
+            "merged_requests": after["merged_requests"] - before["merged_requests"]}
+
+
 def serving(torch, n_requests):
     """The multi-event request stream: 64 resident events, Poisson arrivals, lnL+grad
     per request.  Served by the library's request server (mixed precision, 4 streams,
-    graph replays) and, for comparison, one FIFO with FP64 plain launches."""
+    graph replays, merged launches of queued requests of one event) and, for comparison, one
+    FIFO with FP64 plain launches, one request per launch.  Beside the Poisson streams, a
+    burst of all requests at once measures each server's capacity with a backlog."""
     from paper_2404_11397_amd import Server
     t_build = time.perf_counter()
     events, pools, specs, cuts = build_serving_events(torch)
@@ -644,9 +664,9 @@ def serving(torch, n_requests):
                              "point of the tapered injection (below 1.2 f_merger); band ends [Hz]: "
                              + ", ".join(f"{k}: {v:.0f}" for k, v in sorted(cuts.items())),
            "nrtv2_parity_vs_published_model": NRTV2_NOTE}
-    for tag, streams, graphs, spin, prec in (("server", 4, True, True, "mixed"),
-                                             ("baseline_fifo_fp64_plain", 1, False, False, "fp64")):
-        with Server(budget, n_streams=streams, graphs=graphs, spin=spin) as srv:
+    for tag, streams, graphs, spin, merge, prec in (("server", 4, True, True, True, "mixed"),
+                                                    ("baseline_fifo_fp64_plain", 1, False, False, False, "fp64")):
+        with Server(budget, n_streams=streams, graphs=graphs, spin=spin, merge=merge) as srv:
             ids = [srv.add_event(e) for e in events]
             # warm-up to the steady state: every (event, pool) once, one at a time, then a
             # short Poisson stream (the buffers a light load rotates through), each followed
@@ -659,6 +679,7 @@ def serving(torch, n_requests):
             time.sleep(1.0)
             r = run_stream(srv, ids, pools, n_requests, synth.SERVE_RATE_HZ, prec)
             r["saturation"] = [run_stream(srv, ids, pools, n_requests, rate, prec) for rate in (2000.0, 20000.0)]
+            r["burst"] = run_burst(srv, ids, pools, n_requests, prec)
             r["stats"] = srv.stats()
             r["streams"], r["graphs"], r["spin"] = streams, graphs, spin
             res[tag] = r

@@ -253,11 +253,14 @@ int rbl_mala_step(const rbl_event *ev, double *z_dev, double *lnl_dev, double *g
  * arrival order (FIFO) as soon as a stream is free and a buffer of their class is free
  * or can be allocated within the budget (idle buffers of other classes are released to
  * make room); otherwise they wait (back-pressure).  Admitted requests run concurrently,
- * one per stream.  Each runs as one persistent hipGraph replay (copy in, per-chain setup,
- * likelihood kernel, copy out) kept per (buffer, event, B, precision, gradient); a request
- * with no graph yet runs as plain launches, and its graph is captured the next time the
- * worker is idle, so that no capture delays a request; RBL_SERVE_NO_GRAPHS makes plain
- * launches always.  While requests are in flight the worker polls their completion
+ * one launch per stream.  A launch takes along the requests queued behind the head for
+ * the same event, precision and gradient flag, up to 8192 chains in all, as one batch
+ * (RBL_SERVE_NO_MERGE: one request per launch).  A launch of one request runs as one
+ * persistent hipGraph replay (copy in, per-chain setup, likelihood kernel, copy out) kept
+ * per (buffer, event, B, precision, gradient); a request with no graph yet, and every
+ * merged launch, runs as plain launches, and the request's graph is captured the next
+ * time the worker is idle, so that no capture delays a request; RBL_SERVE_NO_GRAPHS
+ * makes plain launches always.  While requests are in flight the worker polls their completion
  * events (yielding the core between polls).  Results are bitwise identical to rbl_loglike / rbl_loglike_grad on the same
  * theta: no value is reduced across chains or requests.
  *
@@ -267,6 +270,8 @@ typedef struct rbl_server rbl_server;
 #define RBL_SERVE_NO_GRAPHS 0x1u  /* plain launches instead of graph replays */
 #define RBL_SERVE_SPIN      0x2u  /* the worker polls for new requests instead of sleeping
                                      while idle: lowest admission latency, one busy host core */
+#define RBL_SERVE_NO_MERGE  0x4u  /* one launch per request: queued requests of the head's
+                                     event are not taken into its launch */
 
 typedef struct {
     int64_t t_arrival_ns;  /* as given to rbl_server_submit (or the submit time) */
@@ -281,6 +286,7 @@ typedef struct {
     int64_t submitted, completed, queued, in_flight, max_in_flight;
     int64_t graphs, graph_launches, plain_launches;
     int64_t buffer_allocs, buffer_releases, admission_waits;
+    int64_t merged_launches, merged_requests;  /* launches of several requests, and their requests */
 } rbl_server_stats;
 
 /* Create a server.  hbm_budget_bytes > 0; n_streams in 1..16.  RBL_ENOMEM if resources

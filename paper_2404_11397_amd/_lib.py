@@ -25,7 +25,7 @@ EXPORTS = ("rbl_event_create", "rbl_event_free", "rbl_workspace_bytes", "rbl_log
            "rbl_mala_step", "rbl_loglike_grad_noalloc", "rbl_ref_search", "rbl_event_get_edges")
 RBL_FAULT_ALLOC, RBL_FAULT_LAUNCH = 0, 1
 RBL_NOALLOC_MAX_CHAINS = 16384
-RBL_SERVE_NO_GRAPHS, RBL_SERVE_SPIN = 0x1, 0x2
+RBL_SERVE_NO_GRAPHS, RBL_SERVE_SPIN, RBL_SERVE_NO_MERGE = 0x1, 0x2, 0x4
 
 
 class RblError(RuntimeError):
@@ -52,7 +52,7 @@ class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "budget_bytes", "resident_bytes", "buffer_bytes", "submitted", "completed", "queued", "in_flight",
         "max_in_flight", "graphs", "graph_launches", "plain_launches", "buffer_allocs", "buffer_releases",
-        "admission_waits")]
+        "admission_waits", "merged_launches", "merged_requests")]
 
 
 _lib = None

@@ -2,19 +2,25 @@
 //
 // One worker thread owns the streams, the request-buffer pool and the graph cache.
 // Callers queue requests (rbl_server_submit) and block on tickets (rbl_server_wait).
-// The worker loop: (1) reap finished requests (event query per stream), copying the
-// results from pinned staging to the caller's buffers; (2) admit queued requests in
-// FIFO order while a stream is free and a buffer fits the HBM budget; (3) while requests
-// are in flight, poll their completion events, yielding the core between polls; when
-// nothing is queued or running, capture one pending graph if any, else sleep on a
-// condition variable (or keep polling with RBL_SERVE_SPIN).
+// The worker loop:
+//   (1) reap finished launches (event query per stream), copying the results from pinned
+//       staging to the callers' buffers;
+//   (2) admit queued requests in FIFO order while a stream is free and a buffer fits the
+//       HBM budget; each launch takes along the requests further back in the queue for the
+//       same event, precision and gradient flag (up to kMergeMaxChains chains in all);
+//   (3) while launches are in flight, poll their completion events with the mutex
+//       released, yielding the core between polls, until one finishes or a request
+//       arrives; when nothing is queued or running, capture one pending graph if any, else
+//       sleep on a condition variable (or, with RBL_SERVE_SPIN, poll for arrivals with the
+//       mutex released).
 // Every launch is either one graph replay or the same operations issued one by one.  A
-// request whose (buffer, event, batch, precision, gradient) has no graph yet runs as plain
-// launches, and its graph is captured later, when the worker is idle: a capture never
-// delays a request in flight.
+// single request whose (buffer, event, batch, precision, gradient) has no graph yet runs
+// as plain launches, and its graph is captured later, when the worker is idle: a capture
+// never delays a request in flight.  Merged launches are always plain launches.
 #include <time.h>
 
 #include <algorithm>
+#include <atomic>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -40,6 +46,7 @@ int64_t now_ns() {
 
 constexpr int64_t kMinClass = 256;  // smallest buffer class [chains]
 constexpr int kMaxStreams = 16;
+constexpr int64_t kMergeMaxChains = 8192;  // chains of one merged launch, at most
 
 int64_t class_of(int64_t B) {
     int64_t c = kMinClass;
@@ -84,12 +91,13 @@ struct Request {
     int state = 0;  // 0 queued, 1 running, 2 done
     bool counted_wait = false;
     Buffer* buf = nullptr;
+    int64_t off = 0;  // first chain of this request in its launch
 };
 
 struct Slot {
     hipStream_t s = nullptr;
     hipEvent_t done = nullptr;
-    Request* cur = nullptr;
+    std::vector<Request*> cur;  // the requests of the launch in flight (empty: free)
 };
 
 using GraphKey = std::tuple<uint64_t, int32_t, int64_t, int32_t, int32_t>;  // buffer, event, B, precision, grad
@@ -124,6 +132,11 @@ struct rbl_server {
     std::vector<PendingCapture> pending;  // graphs to capture when idle
     rbl_server_stats st{};
     bool stop = false;
+    // Submissions and shutdown, readable by the worker without the mutex: it polls its
+    // launches and waits for work with the mutex released, so that submitters are never
+    // held off by its polling.
+    std::atomic<uint64_t> arrivals{0};
+    std::atomic<bool> stopping{false};
     std::thread worker;
 };
 
@@ -210,6 +223,19 @@ Buffer* acquire(rbl_server* S, int64_t B) {
     return allocate_buffer(S, cap);
 }
 
+// A free buffer for a merged launch of B chains without releasing any: a free one of
+// B's class or larger, else a new one of its class within the budget.  nullptr: the
+// launch goes ahead with the head request alone.
+Buffer* acquire_no_evict(rbl_server* S, int64_t B) {
+    const int64_t cap = class_of(B);
+    Buffer* best = nullptr;
+    for (auto& b : S->bufs)
+        if (!b->busy && b->cap >= cap && (!best || b->cap < best->cap)) best = b.get();
+    if (best) return best;
+    if (S->resident + S->buffer_bytes + BufLayout(cap).total <= S->budget) return allocate_buffer(S, cap);
+    return nullptr;
+}
+
 // ---- launches ----------------------------------------------------------------------------
 
 hipError_t enqueue(const Request* r, const Buffer* b, hipStream_t s) {
@@ -258,17 +284,29 @@ void complete(rbl_server* S, Request* r, int status) {
     S->st.completed++;
 }
 
-void launch(rbl_server* S, Request* r, Buffer* b, int si) {
+// Launch a group of requests of one event, precision and gradient flag as one batch of
+// `total` chains in buffer b (their theta back to back, in group order).  A group of one
+// replays its graph when there is one.  Called with the mutex held (lk); the copy of theta
+// into the pinned staging and the launches run with it released, so that submitters are
+// not held off.  The slot, the buffer and the group's requests are the worker's alone
+// meanwhile: a running request cannot be waited for, and its event cannot be removed.
+void launch(rbl_server* S, std::unique_lock<std::mutex>& lk, const std::vector<Request*>& group, int64_t total,
+            Buffer* b, int si) {
     Slot& sl = S->slots[si];
-    std::memcpy(b->h_theta, r->theta, (size_t)(r->B * 13 * sizeof(double)));
-    r->buf = b;
-    r->state = 1;
-    r->info.stream = si;
-    r->info.t_admit_ns = now_ns();
+    Request* r = group.front();
+    const int64_t t_admit = now_ns();
+    int64_t off = 0;
+    for (Request* q : group) {
+        q->off = off;
+        q->buf = b;
+        q->state = 1;
+        q->info.stream = si;
+        q->info.t_admit_ns = t_admit;
+        off += q->B;
+    }
     b->busy = true;
-    hipError_t e = hipSuccess;
     hipGraphExec_t ex = nullptr;
-    if (!(S->flags & RBL_SERVE_NO_GRAPHS)) {
+    if (group.size() == 1 && !(S->flags & RBL_SERVE_NO_GRAPHS)) {
         const GraphKey k{b->id, r->event, r->B, r->precision, r->grad ? 1 : 0};
         auto it = S->graphs.find(k);
         if (it != S->graphs.end()) {
@@ -278,23 +316,38 @@ void launch(rbl_server* S, Request* r, Buffer* b, int si) {
             S->pending.push_back(PendingCapture{k, r->ev, b});
         }
     }
+    lk.unlock();
+    for (Request* q : group)
+        std::memcpy(b->h_theta + q->off * 13, q->theta, (size_t)(q->B * 13 * sizeof(double)));
+    hipError_t e;
     if (ex) {
         e = hipGraphLaunch(ex, sl.s);
-        S->st.graph_launches++;
     } else {
-        e = enqueue(r, b, sl.s);
-        S->st.plain_launches++;
+        Request m = *r;  // the batch: the head's event, precision and gradient flag
+        m.B = total;
+        e = enqueue(&m, b, sl.s);
     }
     if (e == hipSuccess) e = hipEventRecord(sl.done, sl.s);
+    if (e != hipSuccess) (void)hipStreamSynchronize(sl.s);
+    lk.lock();
+    if (ex) {
+        S->st.graph_launches++;
+    } else {
+        S->st.plain_launches++;
+        if (group.size() > 1) {
+            S->st.merged_launches++;
+            S->st.merged_requests += (int64_t)group.size();
+        }
+    }
     if (e != hipSuccess) {
-        (void)hipStreamSynchronize(sl.s);
         b->busy = false;
-        complete(S, r, hip_fail(e, "rbl_server: launch"));
+        const int rc = hip_fail(e, "rbl_server: launch");
+        for (Request* q : group) complete(S, q, rc);
         S->cv_done.notify_all();
         return;
     }
-    sl.cur = r;
-    S->st.in_flight++;
+    sl.cur = group;
+    S->st.in_flight += (int64_t)group.size();
     S->st.max_in_flight = std::max(S->st.max_in_flight, S->st.in_flight);
 }
 
@@ -315,43 +368,68 @@ void capture_one(rbl_server* S) {
     }
 }
 
-bool reap(rbl_server* S) {
-    bool any = false;
+// Finished launches: their results are copied to the callers' buffers with the mutex
+// released (lk held on entry and on return), then their requests complete.
+bool reap(rbl_server* S, std::unique_lock<std::mutex>& lk) {
+    std::vector<std::pair<Slot*, int>> fin;
     for (auto& sl : S->slots) {
-        if (!sl.cur) continue;
+        if (sl.cur.empty()) continue;
         const hipError_t q = hipEventQuery(sl.done);
         if (q == hipErrorNotReady) continue;
-        Request* r = sl.cur;
-        Buffer* b = r->buf;
-        int status = RBL_OK;
-        if (q == hipSuccess) {
-            std::memcpy(r->lnl, b->h_out, (size_t)(r->B * sizeof(double)));
-            if (r->grad) std::memcpy(r->gout, b->h_out + b->cap, (size_t)(r->B * 13 * sizeof(double)));
-        } else {
-            status = hip_fail(q, "rbl_server: request");
+        fin.emplace_back(&sl, q == hipSuccess ? RBL_OK : hip_fail(q, "rbl_server: request"));
+    }
+    if (fin.empty()) return false;
+    lk.unlock();
+    for (auto& [sl, status] : fin) {
+        if (status != RBL_OK) continue;
+        const Buffer* b = sl->cur.front()->buf;
+        for (Request* r : sl->cur) {
+            std::memcpy(r->lnl, b->h_out + r->off, (size_t)(r->B * sizeof(double)));
+            if (r->grad)
+                std::memcpy(r->gout, b->h_out + b->cap + r->off * 13, (size_t)(r->B * 13 * sizeof(double)));
         }
+    }
+    lk.lock();
+    for (auto& [sl, status] : fin) {
+        Buffer* b = sl->cur.front()->buf;
+        for (Request* r : sl->cur) complete(S, r, status);
         b->busy = false;
         b->last_use = now_ns();
-        sl.cur = nullptr;
-        S->st.in_flight--;
-        complete(S, r, status);
-        any = true;
+        S->st.in_flight -= (int64_t)sl->cur.size();
+        sl->cur.clear();
     }
-    if (any) S->cv_done.notify_all();
-    return any;
+    S->cv_done.notify_all();
+    return true;
 }
 
-void admit(rbl_server* S) {
+void admit(rbl_server* S, std::unique_lock<std::mutex>& lk) {
     while (!S->queue.empty()) {
         int si = -1;
         for (int i = 0; i < (int)S->slots.size(); ++i)
-            if (!S->slots[i].cur) {
+            if (S->slots[i].cur.empty()) {
                 si = i;
                 break;
             }
         if (si < 0) return;
         Request* r = S->queue.front();
-        Buffer* b = acquire(S, r->B);
+        std::vector<Request*> group{r};
+        int64_t total = r->B;
+        if (!(S->flags & RBL_SERVE_NO_MERGE)) {
+            for (auto it = std::next(S->queue.begin()); it != S->queue.end(); ++it) {
+                Request* q = *it;
+                if (q->event == r->event && q->precision == r->precision && q->grad == r->grad &&
+                    total + q->B <= kMergeMaxChains) {
+                    group.push_back(q);
+                    total += q->B;
+                }
+            }
+        }
+        Buffer* b = group.size() > 1 ? acquire_no_evict(S, total) : nullptr;
+        if (!b) {  // the head alone
+            group.resize(1);
+            total = r->B;
+            b = acquire(S, total);
+        }
         if (!b) {
             if (!r->counted_wait) {
                 r->counted_wait = true;
@@ -359,8 +437,16 @@ void admit(rbl_server* S) {
             }
             return;
         }
-        S->queue.pop_front();
-        launch(S, r, b, si);
+        if (group.size() == 1) {
+            S->queue.pop_front();
+        } else {
+            S->queue.erase(std::remove_if(S->queue.begin(), S->queue.end(),
+                                          [&](Request* q) {
+                                              return std::find(group.begin(), group.end(), q) != group.end();
+                                          }),
+                           S->queue.end());
+        }
+        launch(S, lk, group, total, b, si);
     }
 }
 
@@ -368,11 +454,19 @@ void worker_main(rbl_server* S) {
     (void)hipSetDevice(S->device);
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
-        reap(S);
-        admit(S);
+        reap(S, lk);
+        admit(S, lk);
         if (S->st.in_flight > 0) {
+            // Poll the launches in flight with the mutex released (the slots belong to this
+            // thread), until one finishes or a new request arrives.
+            const uint64_t seen = S->arrivals.load(std::memory_order_acquire);
             lk.unlock();
-            std::this_thread::yield();
+            for (bool done = false; !done;) {
+                for (auto& sl : S->slots)
+                    if (!sl.cur.empty() && hipEventQuery(sl.done) != hipErrorNotReady) done = true;
+                if (!done && S->arrivals.load(std::memory_order_acquire) == seen) std::this_thread::yield();
+                else done = true;
+            }
             lk.lock();
             continue;
         }
@@ -390,8 +484,10 @@ void worker_main(rbl_server* S) {
         }
         if (S->stop) break;
         if (S->flags & RBL_SERVE_SPIN) {
+            const uint64_t seen = S->arrivals.load(std::memory_order_acquire);
             lk.unlock();
-            std::this_thread::yield();
+            while (S->arrivals.load(std::memory_order_acquire) == seen && !S->stopping.load(std::memory_order_acquire))
+                std::this_thread::yield();
             lk.lock();
             continue;
         }
@@ -493,6 +589,7 @@ extern "C" int rbl_server_submit(rbl_server* S, int32_t event_id, const double* 
         return RBL_OK;
     }
     S->queue.push_back(r);
+    S->arrivals.fetch_add(1, std::memory_order_release);
     S->cv_work.notify_one();
     return RBL_OK;
 }
@@ -529,6 +626,7 @@ extern "C" void rbl_server_destroy(rbl_server* S) {
     {
         std::lock_guard<std::mutex> lk(S->mu);
         S->stop = true;
+        S->stopping.store(true, std::memory_order_release);
     }
     S->cv_work.notify_all();
     if (S->worker.joinable()) S->worker.join();

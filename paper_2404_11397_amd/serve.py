@@ -30,9 +30,10 @@ class Ticket:
 
 
 class Server:
-    def __init__(self, hbm_budget_bytes, n_streams=4, graphs=True, spin=False):
+    def __init__(self, hbm_budget_bytes, n_streams=4, graphs=True, spin=False, merge=True):
         h = ctypes.c_void_p()
-        flags = (0 if graphs else _lib.RBL_SERVE_NO_GRAPHS) | (_lib.RBL_SERVE_SPIN if spin else 0)
+        flags = ((0 if graphs else _lib.RBL_SERVE_NO_GRAPHS) | (_lib.RBL_SERVE_SPIN if spin else 0)
+                 | (0 if merge else _lib.RBL_SERVE_NO_MERGE))
         check(_lib.lib().rbl_server_create(int(hbm_budget_bytes), int(n_streams), flags, ctypes.byref(h)))
         self._h = h
         self._events = {}

@@ -1,6 +1,7 @@
 """Request server on the GPU: every request's result is bitwise the same served alone
-(a direct library call) and in a concurrent mix; admission by HBM footprint queues
-requests that do not fit and rejects those that never can."""
+(a direct library call), in a concurrent mix and in a launch merged with other requests of
+its event; admission by HBM footprint queues requests that do not fit and rejects those
+that never can."""
 import time
 
 import numpy as np
@@ -60,11 +61,49 @@ def test_alone_equals_mix(events, graphs, spin):
         say("stats", st)
         assert st["completed"] == 2 * len(plan) and st["in_flight"] == 0 and st["queued"] == 0
         assert st["max_in_flight"] > 1
-        assert st["graph_launches"] + st["plain_launches"] == 2 * len(plan)
+        # a merged launch serves merged_requests / merged_launches requests at once
+        served = st["graph_launches"] + st["plain_launches"] + st["merged_requests"] - st["merged_launches"]
+        assert served == 2 * len(plan)
         if graphs:
             assert st["graphs"] > 0 and st["graph_launches"] > 0
         else:
-            assert st["plain_launches"] == 2 * len(plan) and st["graphs"] == 0
+            assert st["graph_launches"] == 0 and st["graphs"] == 0
+
+
+@pytest.mark.parametrize("merge", [True, False])
+def test_merged_launches_equal_alone(events, merge):
+    """Requests queued behind a long one are taken into one launch per (event, precision,
+    gradient flag), up to 8192 chains, and each gets bitwise the results of its own call."""
+    from paper_2404_11397_amd import Server
+    rng = np.random.default_rng(12)
+    gev_n, th_n = events[2]  # IMRPhenomD_NRTidalv2, 1100 chains: keeps the stream busy
+    cuts = [(1, 0), (17, 3), (64, 40), (100, 7), (256, 1), (3, 250), (700, 0), (33, 600)]
+    with Server(4 << 30, n_streams=1, graphs=False, merge=merge) as srv:
+        ids = [srv.add_event(gev) for gev, _ in events]
+        plan = [(2, th_n, "fp64", True)] * 3
+        for n, at in cuts:
+            e = int(rng.integers(2))  # the two TaylorF2 events with 300 and 700 chains
+            th = events[e][1]
+            n = min(n, len(th) - at % len(th))
+            plan.append((e, th[at % len(th):at % len(th) + n], str(rng.choice(["fp64", "mixed"])),
+                         bool(rng.integers(2))))
+        plan += [(1, events[1][1], "mixed", True)] * 14  # 9800 chains of one kind: over one launch's 8192
+        tickets = [(srv.submit(ids[e], th, precision=p, grad=g), e, th, p, g) for e, th, p, g in plan]
+        for t, e, th, p, g in tickets:
+            lnl, grad, info = srv.wait(t)
+            want_l, want_g = _alone(events[e][0], th, p, g)
+            assert np.array_equal(lnl, want_l, equal_nan=True), (e, len(th), p, g)
+            if g:
+                assert np.array_equal(grad, want_g, equal_nan=True), (e, len(th), p, g)
+        st = srv.stats()
+        say("merge", merge, "stats", st)
+        assert st["completed"] == len(plan)
+        assert st["plain_launches"] + st["merged_requests"] - st["merged_launches"] == len(plan)
+        if merge:
+            assert st["merged_launches"] >= 2 and st["merged_requests"] >= 5
+            assert st["plain_launches"] < len(plan)
+        else:
+            assert st["merged_launches"] == 0 and st["plain_launches"] == len(plan)
 
 
 def test_small_budget_queues_and_rejects(events):

@@ -440,10 +440,8 @@ void admit(rbl_server* S, std::unique_lock<std::mutex>& lk) {
         if (group.size() == 1) {
             S->queue.pop_front();
         } else {
-            S->queue.erase(std::remove_if(S->queue.begin(), S->queue.end(),
-                                          [&](Request* q) {
-                                              return std::find(group.begin(), group.end(), q) != group.end();
-                                          }),
+            for (Request* q : group) q->state = 1;  // running from here on
+            S->queue.erase(std::remove_if(S->queue.begin(), S->queue.end(), [](Request* q) { return q->state == 1; }),
                            S->queue.end());
         }
         launch(S, lk, group, total, b, si);

@@ -159,9 +159,67 @@ __global__ __launch_bounds__(64) void k_chain_setup(const double* __restrict__ t
 constexpr int kIntLanes = 8;
 constexpr int kExtLanes = 4;
 
-// PROP: the chain's theta is the MALA proposal theta(z'), z' = z + (s/2) gz + sqrt(s) xi (a NaN
-// row outside the prior box); lane 0 of each intrinsic group writes z' for the gradient
-// kernel's accept epilogue.
+// The MALA proposal z' = z + (s/2) gz + sqrt(s) xi of chain b, formed by the chain's L lanes
+// together (lane r of the group, the groups aligned in the wavefront): lane r loads and forms
+// components r, r + L, ...; every lane then receives all 13 components by lane permutes.
+// theta is z', or NaN in every component outside the prior box.
+//
+// With `write` (the intrinsic groups, L = 8) the lanes also fill the chain's accept record for
+// the gradient kernel's epilogue (kMalaRec* rows of 16): with h = s/2, k = 1/sqrt(2 s) and f
+// the factor from d lnL/dtheta to d lnL/dz (1, or -1/sin iota and 1/cos dec), component i's
+// term of log q(z|z') - log q(z'|z) is rq_i - u_i^2 with u_i = dq_i - aq_i g_i(theta'), where
+//   rq = ((z' - z - h gz) k)^2,  dq = (z - z') k,  aq = h k f,
+// and the spare slots of the rq row hold lnL(z) + log u and the two factors f.
+template <int L>
+__device__ inline void mala_proposal(const MalaProp& mp, int64_t b, int r, bool write, double (&t)[13]) {
+    constexpr int S = (13 + L - 1) / L;
+    double q[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const int i0 = k * L, i = i0 + r;
+        double s = mp.s[i0], sq = mp.sq[i0], kk = mp.k[i0], hk = mp.hk[i0];
+#pragma unroll
+        for (int rr = 1; rr < L && i0 + rr < 13; ++rr) {
+            s = r == rr ? mp.s[i0 + rr] : s;
+            sq = r == rr ? mp.sq[i0 + rr] : sq;
+            kk = r == rr ? mp.k[i0 + rr] : kk;
+            hk = r == rr ? mp.hk[i0 + rr] : hk;
+        }
+        q[k] = 0.0;
+        if (i < 13) {
+            const int64_t o = b * 13 + i;
+            const double z = mp.z[o], gz = mp.gz[o];
+            q[k] = fma(sq, mp.xi[o], fma(0.5 * s, gz, z));
+            if (write) {
+                double* rec = mp.rec + b * kMalaRecStride;
+                double f = 1.0;
+                if (i == kMalaIota || i == kMalaDec)
+                    f = (i == kMalaIota ? -1.0 : 1.0) / sqrt(fma(-q[k], q[k], 1.0));
+                const double rf = (q[k] - z - 0.5 * s * gz) * kk;
+                rec[kMalaRecZp + i] = q[k];
+                rec[kMalaRecDq + i] = (z - q[k]) * kk;
+                rec[kMalaRecAq + i] = hk * f;
+                rec[kMalaRecRq + i] = rf * rf;
+                if (i == kMalaIota) rec[kMalaRecFIota] = f;
+                if (i == kMalaDec) rec[kMalaRecFDec] = f;
+            }
+        }
+    }
+    if (write && r == L - 1) mp.rec[b * kMalaRecStride + kMalaRecThr] = mp.lnl[b] + mp.logu[b];
+    const int base = (int)(threadIdx.x & 63) & ~(L - 1);
+    bool in = true;
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+        t[i] = lane_permute(q[i / L], base + i % L);
+        in = in && t[i] >= mp.lo[i] && t[i] <= mp.hi[i];
+    }
+    if (!in)
+#pragma unroll
+        for (int i = 0; i < 13; ++i) t[i] = __builtin_nan("");
+}
+
+// PROP: the chain's theta is the MALA proposal theta(z') (mala_proposal); the intrinsic
+// groups write the chain's accept record.
 template <bool PROP>
 __global__ __launch_bounds__(64) void k_chain_setup_grad(const double* __restrict__ theta, int64_t B, Network net,
                                                           RefConsts ref, double* __restrict__ rec,
@@ -174,22 +232,14 @@ __global__ __launch_bounds__(64) void k_chain_setup_grad(const double* __restric
     if (b >= B) return;
     double t[13];
     if constexpr (PROP) {
-        double q[13];
-        bool in = true;
-#pragma unroll
-        for (int i = 0; i < 13; ++i) {
-            q[i] = fma(mp.sq[i], mp.xi[b * 13 + i], fma(0.5 * mp.s[i], mp.gz[b * 13 + i], mp.z[b * 13 + i]));
-            in = in && q[i] >= mp.lo[i] && q[i] <= mp.hi[i];
-        }
-#pragma unroll
-        for (int i = 0; i < 13; ++i) t[i] = in ? q[i] : __builtin_nan("");
-        if (in && !intrinsic) {  // the intrinsic lanes use neither angle (only its finiteness)
-            t[9] = acos(fmin(fmax(q[9], -1.0), 1.0));
-            t[12] = asin(fmin(fmax(q[12], -1.0), 1.0));
-        }
-        if (intrinsic && tg == 0) {
-#pragma unroll
-            for (int i = 0; i < 13; ++i) mp.zp[b * 13 + i] = q[i];
+        if (intrinsic) {
+            mala_proposal<kIntLanes>(mp, b, tg, true, t);
+        } else {
+            mala_proposal<kExtLanes>(mp, b, tg, false, t);
+            if (!isnan(t[0])) {  // the intrinsic lanes use neither angle (only its finiteness)
+                t[9] = acos(fmin(fmax(t[9], -1.0), 1.0));
+                t[12] = asin(fmin(fmax(t[12], -1.0), 1.0));
+            }
         }
     } else {
 #pragma unroll

@@ -590,49 +590,44 @@ __device__ inline void grad_walk_nrt(const EventDev& ev, const ChainVals<ND>& cv
 }
 
 // The end of a fused MALA step for one chain (lanes 0..12 hold d lnL'/dtheta_i, all lanes
-// active): gz' = d lnL'/dz (d/dcos iota = -(d/diota)/sin iota and d/dsin dec = (d/ddec)/cos dec,
-// with sin iota = cos dec = sqrt(1 - z'^2) on [0, pi] and [-pi/2, pi/2]),
-// log alpha = lnL' - lnL + log q(z|z') - log q(z'|z) with log q(b|a) = -sum (b - a - s g(a)/2)^2
-// / (2 s), accepted when log u < log alpha; then (z, lnL, gz) <- (z', lnL', gz').  The chain's
-// state (z, z', gz on lanes 0..12; lnL and log u) was loaded by the caller before the walk.
+// active): with the chain's accept record (written by the proposal in the setup kernel),
+//   log q(z|z') - log q(z'|z) = sum_i (rq_i - u_i^2),  u_i = dq_i - aq_i d lnL'/dtheta_i,
+// the step is accepted when lnL(z) + log u < lnL' + sum_i (rq_i - u_i^2), and then (z, lnL, gz)
+// <- (z', lnL', gz') with gz' = f d lnL'/dtheta (f = 1, or -1/sin iota and 1/cos dec).  The
+// record is loaded before the walk (lanes 0..15, one row each), so the epilogue, which the
+// wavefronts of a generation run at the same time, is two fmas, a 16-lane sum and the stores.
 struct MalaState {
-    double z = 0.0, zp = 0.0, gz = 0.0, lnl = 0.0, logu = 0.0;
+    double zp, dq, aq, rq;  // lanes 0..15: slot `lane` of each row
 };
 
 __device__ inline MalaState mala_load(const MalaEpi& me, int64_t chain, int lane) {
     MalaState m;
-    if (lane < 13) {
-        const int64_t o = chain * 13 + lane;
-        m.z = me.z[o];
-        m.zp = me.zp[o];
-        m.gz = me.gz[o];
+    if (lane < 16) {
+        const double* r = me.rec + chain * kMalaRecStride + lane;
+        m.zp = r[kMalaRecZp];
+        m.dq = r[kMalaRecDq];
+        m.aq = r[kMalaRecAq];
+        m.rq = r[kMalaRecRq];
     }
-    m.lnl = me.lnl[chain];
-    m.logu = me.logu[chain];
     return m;
 }
 
 __device__ inline void mala_accept(const MalaEpi& me, const MalaState& m, int64_t chain, int lane, double lnl_new,
                                    double g) {
     const bool c = lane < 13;
-    const int64_t o = chain * 13 + (c ? lane : 0);
-    double si = me.s[0];
-#pragma unroll
-    for (int i = 1; i < 13; ++i) si = lane == i ? me.s[i] : si;
-    double gzp = g;
-    if (lane == 9 || lane == 12) gzp = (lane == 9 ? -g : g) / sqrt(fma(-m.zp, m.zp, 1.0));
     double term = 0.0;
     if (c) {
-        const double rb = m.z - m.zp - 0.5 * si * gzp;   // z - z' - s g(z')/2
-        const double rf = m.zp - m.z - 0.5 * si * m.gz;  // z' - z - s g(z)/2
-        term = (rf * rf - rb * rb) / (2.0 * si);
+        const double u = fma(-m.aq, g, m.dq);
+        term = fma(-u, u, m.rq);
     }
-    term = wave_sum(term);
-    const double log_alpha = lnl_new - m.lnl + term;
-    const bool accept = isfinite(lnl_new) && m.logu < log_alpha;
+    term = row0_sum(term);
+    const double thr = lane_read(m.rq, kMalaRecThr - kMalaRecRq);
+    const double fi = lane_read(m.rq, kMalaRecFIota - kMalaRecRq), fd = lane_read(m.rq, kMalaRecFDec - kMalaRecRq);
+    const bool accept = isfinite(lnl_new) && thr < lnl_new + term;
     if (accept && c) {
+        const int64_t o = chain * 13 + lane;
         me.z[o] = m.zp;
-        me.gz[o] = gzp;
+        me.gz[o] = g * (lane == kMalaIota ? fi : (lane == kMalaDec ? fd : 1.0));
     }
     if (lane == 0) {
         if (accept) me.lnl[chain] = lnl_new;

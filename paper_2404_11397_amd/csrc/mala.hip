@@ -60,8 +60,11 @@ __global__ void k_mala_gradz(const double* __restrict__ theta, const double* __r
     for (int i = 0; i < 13; ++i) gz[b * 13 + i] = out[i];
 }
 
+// Workspace: theta(z) and d lnL/dtheta (initialisation), the accept records (steps), then the
+// likelihood workspace (records and Jacobians).
 struct MalaWs {
-    double *thp, *zp, *lnlp, *gthp;
+    double *thp, *gthp;  // [B][13]
+    double* mrec;        // [B][kMalaRecStride]
     void* lws;
 };
 
@@ -70,10 +73,9 @@ MalaWs carve(void* ws, int64_t B) {
     MalaWs w;
     const int64_t row = align_up(B * 13 * (int64_t)sizeof(double));
     w.thp = (double*)p;
-    w.zp = (double*)(p + row);
-    w.gthp = (double*)(p + 2 * row);
-    w.lnlp = (double*)(p + 3 * row);
-    w.lws = p + 3 * row + align_up(B * (int64_t)sizeof(double));
+    w.gthp = (double*)(p + row);
+    w.mrec = (double*)(p + 2 * row);
+    w.lws = p + 2 * row + align_up(B * kMalaRecStride * (int64_t)sizeof(double));
     return w;
 }
 
@@ -90,7 +92,7 @@ int check_mala(const char* who, const rbl_event* ev, const void* z, int64_t B, i
 
 extern "C" int64_t rbl_mala_workspace_bytes(const rbl_event* ev, int64_t B) {
     if (!ev || B < 0) return 0;
-    return 3 * align_up(B * 13 * (int64_t)sizeof(double)) + align_up(B * (int64_t)sizeof(double)) +
+    return 2 * align_up(B * 13 * (int64_t)sizeof(double)) + align_up(B * kMalaRecStride * (int64_t)sizeof(double)) +
            workspace_bytes(B, true);
 }
 
@@ -138,10 +140,11 @@ extern "C" int rbl_mala_step(const rbl_event* ev, double* z_dev, double* lnl_dev
     mp.z = z_dev;
     mp.gz = gz_dev;
     mp.xi = xi_dev;
-    mp.zp = w.zp;
+    mp.lnl = lnl_dev;
+    mp.logu = logu_dev;
+    mp.rec = w.mrec;
     MalaEpi me{};
-    me.zp = w.zp;
-    me.logu = logu_dev;
+    me.rec = w.mrec;
     me.z = z_dev;
     me.gz = gz_dev;
     me.lnl = lnl_dev;
@@ -151,7 +154,8 @@ extern "C" int rbl_mala_step(const rbl_event* ev, double* z_dev, double* lnl_dev
         mp.sq[i] = m.sq[i];
         mp.lo[i] = m.lo[i];
         mp.hi[i] = m.hi[i];
-        me.s[i] = m.s[i];
+        mp.k[i] = 1.0 / std::sqrt(2.0 * m.s[i]);
+        mp.hk[i] = 0.5 * m.s[i] * mp.k[i];
     }
     double* rec = (double*)w.lws;
     double* jac = (double*)((char*)w.lws + align_up(B * kRecStride * (int64_t)sizeof(double)));

@@ -107,16 +107,26 @@ inline void launch_k_lds(F kernel, dim3 grid, dim3 block, size_t lds_bytes, hipS
 // a NaN row outside the prior box, made by the gradient setup kernel; the Metropolis
 // decision on log u < lnL' - lnL + log q(z|z') - log q(z'|z) and the in-place update of
 // (z, lnL, gz), made by the gradient kernel's epilogue.
+// The per-chain accept record of a MALA step, written by the proposal (setup kernel) and read
+// by the accept epilogue (gradient kernel): four rows of 16 doubles, z', dq, aq and rq of each
+// of the 13 components (lane-contiguous for the epilogue's loads), with lnL(z) + log u and the
+// factors from d lnL/dtheta to d lnL/dz of iota and dec in the spare slots of the rq row.
+constexpr int kMalaIota = 9, kMalaDec = 12;
+constexpr int kMalaRecZp = 0, kMalaRecDq = 16, kMalaRecAq = 32, kMalaRecRq = 48;
+constexpr int kMalaRecThr = kMalaRecRq + 13, kMalaRecFIota = kMalaRecRq + 14, kMalaRecFDec = kMalaRecRq + 15;
+constexpr int kMalaRecStride = 64;
+
 struct MalaProp {
     const double *z, *gz, *xi;  // [B][13]
-    double* zp;                 // [B][13] proposals written for the epilogue
+    const double *lnl, *logu;   // [B]
+    double* rec;                // [B][kMalaRecStride] accept records
     double s[13], sq[13], lo[13], hi[13];
+    double k[13], hk[13];       // 1/sqrt(2 s) and (s/2)/sqrt(2 s)
 };
 struct MalaEpi {
-    const double *zp, *logu;
+    const double* rec;     // [B][kMalaRecStride]
     double *z, *gz, *lnl;  // updated in place where accepted
     int32_t* accepted;
-    double s[13];
 };
 
 hipError_t launch_ref_setup(const double* theta_host, const Network& net, int32_t waveform, RefConsts* out_dev,

@@ -33,6 +33,12 @@ __device__ inline double wave_sum(double v) {
     const int hi = __builtin_amdgcn_readlane(__double2hiint(s), 63);
     return __hiloint2double(hi, lo);
 }
+// The value of lane src, per lane (src may differ between lanes; two 32-bit lane permutes).
+__device__ inline double lane_permute(double v, int src) {
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
 // The value of one lane, wave-uniform.
 __device__ inline double lane_read(double v, int src) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
@@ -85,6 +91,16 @@ __device__ inline void wave_sum_n(const double (&v)[N], double (&out)[N]) {
         out[4 * j + 2] = lane_read(r, 16);
         out[4 * j + 3] = lane_read(r, 48);
     }
+}
+
+// Sum over the 16 lanes of the first row (lanes 0..15; all lanes active), wave-uniform:
+// the row reduction of wave_sum_n, fixed order.
+__device__ inline double row0_sum(double v) {
+    v += dpp_rot<0x128>(v);  // row_ror:8
+    v += dpp_rot<0x124>(v);  // row_ror:4
+    v += dpp_rot<0x122>(v);  // row_ror:2
+    v += dpp_rot<0x121>(v);  // row_ror:1
+    return lane_read(v, 0);
 }
 
 // Whole-wave shifts by one lane (DPP wave_shr:1 / wave_shl:1).  The lane without a

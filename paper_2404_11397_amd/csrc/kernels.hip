@@ -164,15 +164,30 @@ constexpr int kExtLanes = 4;
 // components r, r + L, ...; every lane then receives all 13 components by lane permutes.
 // theta is z', or NaN in every component outside the prior box.
 //
-// With `write` (the intrinsic groups, L = 8) the lanes also fill the chain's accept record for
+// With WRITE (the intrinsic groups, L = 8) the lanes also fill the chain's accept record for
 // the gradient kernel's epilogue (kMalaRec* rows of 16): with h = s/2, k = 1/sqrt(2 s) and f
 // the factor from d lnL/dtheta to d lnL/dz (1, or -1/sin iota and 1/cos dec), component i's
 // term of log q(z|z') - log q(z'|z) is rq_i - u_i^2 with u_i = dq_i - aq_i g_i(theta'), where
 //   rq = ((z' - z - h gz) k)^2,  dq = (z - z') k,  aq = h k f,
 // and the spare slots of the rq row hold lnL(z) + log u and the two factors f.
-template <int L>
-__device__ inline void mala_proposal(const MalaProp& mp, int64_t b, int r, bool write, double (&t)[13]) {
+template <int L, bool WRITE>
+__device__ inline void mala_proposal(const MalaProp& mp, int64_t b, int r, double (&t)[13]) {
     constexpr int S = (13 + L - 1) / L;
+    // Every load first, unconditionally (a slot past component 12 reads component 12 and is
+    // not used), so that they are in flight together: one memory round trip.
+    double z[S], gz[S], xi[S], lnl = 0.0, logu = 0.0;
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const int64_t o = b * 13 + min(k * L + r, 12);
+        z[k] = mp.z[o];
+        gz[k] = mp.gz[o];
+        xi[k] = mp.xi[o];
+    }
+    if (WRITE) {
+        lnl = mp.lnl[b];
+        logu = mp.logu[b];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of their first use
     double q[S];
 #pragma unroll
     for (int k = 0; k < S; ++k) {
@@ -185,27 +200,22 @@ __device__ inline void mala_proposal(const MalaProp& mp, int64_t b, int r, bool 
             kk = r == rr ? mp.k[i0 + rr] : kk;
             hk = r == rr ? mp.hk[i0 + rr] : hk;
         }
-        q[k] = 0.0;
-        if (i < 13) {
-            const int64_t o = b * 13 + i;
-            const double z = mp.z[o], gz = mp.gz[o];
-            q[k] = fma(sq, mp.xi[o], fma(0.5 * s, gz, z));
-            if (write) {
-                double* rec = mp.rec + b * kMalaRecStride;
-                double f = 1.0;
-                if (i == kMalaIota || i == kMalaDec)
-                    f = (i == kMalaIota ? -1.0 : 1.0) / sqrt(fma(-q[k], q[k], 1.0));
-                const double rf = (q[k] - z - 0.5 * s * gz) * kk;
-                rec[kMalaRecZp + i] = q[k];
-                rec[kMalaRecDq + i] = (z - q[k]) * kk;
-                rec[kMalaRecAq + i] = hk * f;
-                rec[kMalaRecRq + i] = rf * rf;
-                if (i == kMalaIota) rec[kMalaRecFIota] = f;
-                if (i == kMalaDec) rec[kMalaRecFDec] = f;
+        q[k] = fma(sq, xi[k], fma(0.5 * s, gz[k], z[k]));
+        if (WRITE && i < 13) {
+            double* rec = mp.rec + b * kMalaRecStride;
+            double f = 1.0;
+            if (i == kMalaIota || i == kMalaDec) {
+                f = (i == kMalaIota ? -1.0 : 1.0) / sqrt(fma(-q[k], q[k], 1.0));
+                rec[i == kMalaIota ? kMalaRecFIota : kMalaRecFDec] = f;
             }
+            const double rf = (q[k] - z[k] - 0.5 * s * gz[k]) * kk;
+            rec[kMalaRecZp + i] = q[k];
+            rec[kMalaRecDq + i] = (z[k] - q[k]) * kk;
+            rec[kMalaRecAq + i] = hk * f;
+            rec[kMalaRecRq + i] = rf * rf;
         }
     }
-    if (write && r == L - 1) mp.rec[b * kMalaRecStride + kMalaRecThr] = mp.lnl[b] + mp.logu[b];
+    if (WRITE && r == L - 1) mp.rec[b * kMalaRecStride + kMalaRecThr] = lnl + logu;
     const int base = (int)(threadIdx.x & 63) & ~(L - 1);
     bool in = true;
 #pragma unroll
@@ -233,9 +243,9 @@ __global__ __launch_bounds__(64) void k_chain_setup_grad(const double* __restric
     double t[13];
     if constexpr (PROP) {
         if (intrinsic) {
-            mala_proposal<kIntLanes>(mp, b, tg, true, t);
+            mala_proposal<kIntLanes, true>(mp, b, tg, t);
         } else {
-            mala_proposal<kExtLanes>(mp, b, tg, false, t);
+            mala_proposal<kExtLanes, false>(mp, b, tg, t);
             if (!isnan(t[0])) {  // the intrinsic lanes use neither angle (only its finiteness)
                 t[9] = acos(fmin(fmax(t[9], -1.0), 1.0));
                 t[12] = asin(fmin(fmax(t[12], -1.0), 1.0));

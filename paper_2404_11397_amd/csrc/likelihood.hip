@@ -348,14 +348,125 @@ inline size_t staged_table_bytes(int nd, int np) { return sizeof(double) * (size
 constexpr size_t kStageMaxBytes = 56 * 1024;  // with the 8 KB phasor table: two workgroups per CU
 constexpr int kStageChains = 8;               // chains (wavefronts) per workgroup sharing the staged tables
 
+// Jacobian entries the TaylorF2 gradient epilogue reads per chain: the intrinsic block
+// (12 rows of 6) and the extrinsic block (9 rows of 4).
+constexpr int kJacTf2Int = 12 * 6, kJacTf2 = kJacTf2Int + 36;
+
+// The LDS staging of an 8-chain TaylorF2 workgroup in one memory round trip: every thread
+// first issues all of its loads -- the unit-phasor table, the node pairs, the gamma pairs and
+// x_L, with NJ > 0 the Jacobian entries of the workgroup's chains (NJ per chain, to sj) and
+// with NR > 0 the first NR entries of their records (to sr) -- and only then writes them to
+// LDS, followed by one barrier.  A loop that loads and stores
+// each element in turn waits one round trip per iteration; the workgroups of a CU run one
+// after another, so each of those waits is exposed.  The per-thread counts are bounded by
+// the staging limit (npad (4 + 3 ND) doubles <= kStageMaxBytes).  ev's pointers are
+// redirected to LDS.
+template <int ND, int NJ, int NR = 0>
+__device__ inline void stage_tf2_workgroup(EventDev& ev, double2* tab, double* lds, const double* __restrict__ jac,
+                                           int64_t chain0, int64_t B, double* sj, const double* __restrict__ recs = nullptr,
+                                           double* sr = nullptr) {
+    constexpr int T = 64 * kStageChains;
+    static_assert(kStageChains * NR <= T, "one record entry per thread");
+    constexpr int NPMAX = (int)(kStageMaxBytes / (sizeof(double) * (4 + 3 * ND))) / kNodeTile * kNodeTile;
+    constexpr int NT = (kPhasorN + T - 1) / T, NF = (NPMAX + T - 1) / T, NG = (ND * NPMAX + T - 1) / T;
+    constexpr int NJT = NJ > 0 ? (kStageChains * NJ + T - 1) / T : 1;
+    const int t = threadIdx.x, np = ev.n_nodes_pad;
+    const double2* sph = reinterpret_cast<const double2*>(ev.phasor);
+    const double2* sfx = reinterpret_cast<const double2*>(ev.node_fx);
+    const double2* sil = reinterpret_cast<const double2*>(ev.node_il);
+    const double2* sg = reinterpret_cast<const double2*>(ev.g);
+    // Loads are unconditional, at indices clamped into the arrays (a clamped element is loaded
+    // and not stored), and pairs are held as separate x / y doubles: a load under a branch, or
+    // into a vector-typed array, makes the compiler wait for it before the next one.
+    double phx[NT], phy[NT], fxx[NF], fxy[NF], ilx[NF], ily[NF], gx[NG], gy[NG], vxl[NG], vj[NJT], vr = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        const double2 v = sph[min(k * T + t, kPhasorN - 1)];
+        phx[k] = v.x;
+        phy[k] = v.y;
+    }
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+        const int i = min(k * T + t, np - 1);
+        const double2 u = sfx[i], v = sil[i];
+        fxx[k] = u.x;
+        fxy[k] = u.y;
+        ilx[k] = v.x;
+        ily[k] = v.y;
+    }
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+        const int i = min(k * T + t, ND * np - 1);
+        const double2 v = sg[i];
+        gx[k] = v.x;
+        gy[k] = v.y;
+        vxl[k] = ev.xL[i];
+    }
+    if constexpr (NJ > 0) {
+#pragma unroll
+        for (int k = 0; k < NJT; ++k) {
+            const int e = min(k * T + t, kStageChains * NJ - 1), c = e / NJ, j = e - c * NJ;
+            const int64_t ch = min(chain0 + c, B - 1);
+            vj[k] = jac[ch * kJacStride + (j < kJacTf2Int ? kJacInt + j : kJacExt + (j - kJacTf2Int))];
+        }
+    }
+    if constexpr (NR > 0) {
+        const int e = min(t, kStageChains * NR - 1), c = e / NR;
+        vr = recs[min(chain0 + c, B - 1) * kRecStride + (e - c * NR)];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // every load above is issued before the first store
+    double* fx = lds;
+    double* il = fx + 2 * np;
+    double* g = il + 2 * np;
+    double* xl = g + 2 * ND * np;
+#pragma unroll
+    for (int k = 0; k < NT; ++k)
+        if (k * T + t < kPhasorN) tab[k * T + t] = double2{phx[k], phy[k]};
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+        const int i = k * T + t;
+        if (i < np) {
+            reinterpret_cast<double2*>(fx)[i] = double2{fxx[k], fxy[k]};
+            reinterpret_cast<double2*>(il)[i] = double2{ilx[k], ily[k]};
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+        const int i = k * T + t;
+        if (i < ND * np) {
+            reinterpret_cast<double2*>(g)[i] = double2{gx[k], gy[k]};
+            xl[i] = vxl[k];
+        }
+    }
+    if constexpr (NJ > 0) {
+#pragma unroll
+        for (int k = 0; k < NJT; ++k) {
+            const int e = k * T + t, c = e / NJ;
+            if (e < kStageChains * NJ && chain0 + c < B) sj[e] = vj[k];
+        }
+    }
+    if constexpr (NR > 0)
+        if (t < kStageChains * NR) sr[t] = vr;
+    __syncthreads();
+    ev.node_fx = fx;
+    ev.node_il = il;
+    ev.g = g;
+    ev.xL = xl;
+}
+
 template <int ND, bool MIXED, int WF, bool LT = false>
 __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) void k_loglike_fwd(EventDev ev, const double* __restrict__ recs, int64_t B,
                                                      double* __restrict__ lnl) {
     __shared__ double2 tab[kPhasorN];
-    load_phasor_table(ev, tab);
-    if constexpr (LT) {
+    if constexpr (LT && WF == kWfTaylorF2) {
         extern __shared__ double lds_tables[];
-        stage_edge_tables<ND>(ev, lds_tables);
+        stage_tf2_workgroup<ND, 0>(ev, tab, lds_tables, nullptr, 0, 0, nullptr);
+    } else {
+        load_phasor_table(ev, tab);
+        if constexpr (LT) {
+            extern __shared__ double lds_tables[];
+            stage_edge_tables<ND>(ev, lds_tables);
+        }
     }
     const int lane = threadIdx.x & 63;
     const int64_t chain = (int64_t)blockIdx.x * (LT ? kStageChains : 4) + wave_id();
@@ -645,15 +756,34 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
     EventDev ev, const double* __restrict__ recs, const double* __restrict__ jac, int64_t B,
     double* __restrict__ lnl, double* __restrict__ grad, MalaEpi me) {
     __shared__ double2 tab[kPhasorN];
-    load_phasor_table(ev, tab);
-    if constexpr (LT) {
+    // TaylorF2 with LDS tables: the chains' Jacobian entries are staged too (sj), so that the
+    // epilogue reads them from LDS rather than waiting a memory round trip after the walk.
+    // and so are the chains' record entries [0, kRecDl] (sr), read back into scalar registers.
+    constexpr bool JL = LT && WF == kWfTaylorF2;
+    constexpr int NR = JL ? kRecDl + 1 : 1;
+    double* sj = nullptr;
+    double rv[NR];
+    if constexpr (JL) {
         extern __shared__ double lds_tables[];
-        if constexpr (WF == kWfNrtv2 && MIXED)
-            stage_nrt_tables32<ND>(ev, lds_tables);
-        else if constexpr (WF == kWfNrtv2)
-            stage_nrt_tables<ND>(ev, lds_tables);
-        else
-            stage_edge_tables<ND>(ev, lds_tables);
+        sj = lds_tables + (size_t)ev.n_nodes_pad * (4 + 3 * ND);  // after the staged tables
+        double* sr = sj + kStageChains * kJacTf2;
+        stage_tf2_workgroup<ND, kJacTf2, NR>(ev, tab, lds_tables, jac, (int64_t)blockIdx.x * kStageChains, B, sj,
+                                             recs, sr);
+        double tmp[NR];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) tmp[i] = sr[wave_id() * NR + i];
+        __builtin_amdgcn_sched_barrier(0);  // all LDS reads in flight before the first use
+#pragma unroll
+        for (int i = 0; i < NR; ++i) rv[i] = uniform(tmp[i]);
+    } else {
+        load_phasor_table(ev, tab);
+        if constexpr (LT) {
+            extern __shared__ double lds_tables[];
+            if constexpr (WF == kWfNrtv2 && MIXED)
+                stage_nrt_tables32<ND>(ev, lds_tables);
+            else
+                stage_nrt_tables<ND>(ev, lds_tables);
+        }
     }
     const int lane = threadIdx.x & 63;
     const int64_t chain = (int64_t)blockIdx.x * (LT ? kStageChains : 4) + wave_id();
@@ -661,7 +791,8 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
     MalaState ms;
     if constexpr (MALA) ms = mala_load(me, chain, lane);  // in flight during the walk
     const double* rec = recs + chain * kRecStride;
-    const double status = rec[kRecStatus];
+    auto rd = [&](int i) { return JL ? rv[i < NR ? i : 0] : rec[i]; };  // record entries up to kRecDl
+    const double status = rd(kRecStatus);
     if (!(status == 1.0)) {
         if constexpr (MALA) {
             if (lane == 0) me.accepted[chain] = 0;  // a proposal outside the prior box, or not physical
@@ -684,20 +815,20 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
     constexpr int NA = WF == kWfNrtv2 ? kNrtAdj : kTf2Basis;
     ChainVals<ND> cv;
 #pragma unroll
-    for (int j = 0; j < kTf2Basis; ++j) cv.dc[j] = rec[kRecDc + j];
+    for (int j = 0; j < kTf2Basis; ++j) cv.dc[j] = rd(kRecDc + j);
     if (WF == kWfNrtv2) {
         double* dst = reinterpret_cast<double*>(&cv.np);
 #pragma unroll
         for (int i = 0; i < kNrtParams; ++i) dst[i] = rec[kRecNrt + i];
     }
-    const double g_re = rec[kRecG], g_im = rec[kRecG + 1];
+    const double g_re = rd(kRecG), g_im = rd(kRecG + 1);
     bool zero_k = false;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
-        const double pr = rec[kRecK + 2 * d], pi = rec[kRecK + 2 * d + 1];
+        const double pr = rd(kRecK + 2 * d), pi = rd(kRecK + 2 * d + 1);
         cv.kre[d] = pr * g_re - pi * g_im;  // K_d = P_d G
         cv.kim[d] = pr * g_im + pi * g_re;
-        cv.dtau[d] = rec[kRecTau + d];
+        cv.dtau[d] = rd(kRecTau + d);
         zero_k = zero_k || !(cv.kre[d] * cv.kre[d] + cv.kim[d] * cv.kim[d] > 1e-280);
     }
     // Z'_d = Z_d / K_d is the gradient with respect to K_d.
@@ -811,6 +942,9 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
     double g = 0.0;
     if (lane < 13) {
         const double* J = jac + chain * kJacStride;
+        const double* Jl = JL ? sj + wave_id() * kJacTf2 : nullptr;  // staged: [intrinsic | extrinsic]
+        auto jint = [&](int i) { return JL ? Jl[i - kJacInt] : J[i]; };
+        auto jext = [&](int i) { return JL ? Jl[kJacTf2Int + (i - kJacExt)] : J[i]; };
         if (lane < 6 && WF == kWfNrtv2) {
 #pragma unroll
             for (int b = 0; b < NA; ++b) g = fma(A[b], J[kJacInt + b * 6 + lane], g);
@@ -819,9 +953,9 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
             for (int d = 0; d < ND; ++d) g = fma(ZR[d] * cv.kre[d] - ZI[d] * cv.kim[d], dre, g);
         } else if (lane < 6) {
 #pragma unroll
-            for (int b = 0; b < NA; ++b) g = fma(A[b], J[kJacInt + b * 6 + lane], g);
-            const double dre = J[kJacInt + kJacAmpTf2 * 6 + lane];
-            const double dim = -2.0 * kPi * J[kJacInt + 10 * 6 + lane];
+            for (int b = 0; b < NA; ++b) g = fma(A[b], jint(kJacInt + b * 6 + lane), g);
+            const double dre = jint(kJacInt + kJacAmpTf2 * 6 + lane);
+            const double dim = -2.0 * kPi * jint(kJacInt + 10 * 6 + lane);
 #pragma unroll
             for (int d = 0; d < ND; ++d) {
                 const double wr = ZR[d] * cv.kre[d] - ZI[d] * cv.kim[d], wi = ZR[d] * cv.kim[d] + ZI[d] * cv.kre[d];
@@ -834,7 +968,7 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
                 sr += ZR[d] * cv.kre[d] - ZI[d] * cv.kim[d];
                 si += ZR[d] * cv.kim[d] + ZI[d] * cv.kre[d];
             }
-            g = (lane == 6) ? -sr / rec[kRecDl] : -2.0 * si;
+            g = (lane == 6) ? -sr / rd(kRecDl) : -2.0 * si;
         } else if (lane == 7) {
 #pragma unroll
             for (int d = 0; d < ND; ++d) g += Tt[d];
@@ -842,9 +976,9 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
             const int a = lane - 9;
 #pragma unroll
             for (int d = 0; d < ND; ++d) {
-                const double pr = J[kJacExt + (d * 3 + 0) * 4 + a], pi = J[kJacExt + (d * 3 + 1) * 4 + a];
+                const double pr = jext(kJacExt + (d * 3 + 0) * 4 + a), pi = jext(kJacExt + (d * 3 + 1) * 4 + a);
                 const double kr = g_re * pr - g_im * pi, ki = g_re * pi + g_im * pr;  // dK_d
-                g += ZR[d] * kr - ZI[d] * ki + Tt[d] * J[kJacExt + (d * 3 + 2) * 4 + a];
+                g += ZR[d] * kr - ZI[d] * ki + Tt[d] * jext(kJacExt + (d * 3 + 2) * 4 + a);
             }
         }
     }
@@ -918,8 +1052,9 @@ static void grad_nd(const EventDev& ev, const double* rec, const double* jac, in
             launch_k(k_loglike_grad<ND, true, kWfTaylorF2, false, MALA>, dim3(grid), blk, s, kt, ev, rec, jac, B, lnl,
                      grad, me);
         else if (lb <= kStageMaxBytes)
-            launch_k_lds(k_loglike_grad<ND, false, kWfTaylorF2, true, MALA>, dim3(grid_lt), blk_lt, lb, s, kt, ev,
-                         rec, jac, B, lnl, grad, me);
+            launch_k_lds(k_loglike_grad<ND, false, kWfTaylorF2, true, MALA>, dim3(grid_lt), blk_lt,
+                         lb + sizeof(double) * kStageChains * (kJacTf2 + kRecDl + 1), s, kt, ev, rec, jac, B, lnl,
+                         grad, me);
         else
             launch_k(k_loglike_grad<ND, false, kWfTaylorF2, false, MALA>, dim3(grid), blk, s, kt, ev, rec, jac, B,
                      lnl, grad, me);

@@ -39,6 +39,11 @@ __device__ inline double lane_permute(double v, int src) {
     const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
     return __hiloint2double(hi, lo);
 }
+// A value that is the same in every lane, moved to scalar registers.
+__device__ inline double uniform(double v) {
+    return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                            __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
 // The value of one lane, wave-uniform.
 __device__ inline double lane_read(double v, int src) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);

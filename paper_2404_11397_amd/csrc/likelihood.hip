@@ -245,6 +245,10 @@ __device__ inline double fwd_walk_natural(const EventDev& ev, const ChainVals<ND
     return acc;
 }
 
+// LDS staging limits and the workgroup shape of the LDS-table kernels.
+constexpr size_t kStageMaxBytes = 56 * 1024;  // with the 8 KB phasor table: two workgroups per CU
+constexpr int kStageChains = 8;               // chains (wavefronts) per workgroup sharing the staged tables
+constexpr size_t kNrtStageMaxBytes = 144 * 1024;  // with the phasor table and node parameters: one workgroup per CU
 // TaylorF2 edge tables staged in LDS, shared by the workgroup's chains: the node pairs, the
 // gamma pairs and x_L of the first ND detectors (npad (4 + 3 ND) doubles); the walk then
 // reads them with LDS loads instead of vector-memory loads.  ev's pointers are redirected.
@@ -275,8 +279,13 @@ __device__ inline void stage_edge_tables(EventDev& ev, double* lds) {
 // IMRPhenomD_NRTidalv2 edge tables staged in LDS for the gradient walk: the gamma pairs,
 // mu, x_L and x_R of the first ND detectors (5 ND npad doubles), natural order.
 template <int ND>
-__device__ inline void stage_nrt_tables(EventDev& ev, double* lds) {
-    const int np = ev.n_nodes_pad;
+__device__ inline void stage_nrt_tables(EventDev& ev, double2* tab, double* lds) {
+    // One memory round trip, as in stage_tf2_workgroup: every load (the unit-phasor table
+    // too) is issued, at an index clamped into its array, before the first LDS write.
+    constexpr int T = 64 * kStageChains;
+    constexpr int NPMAX = (int)(kNrtStageMaxBytes / (sizeof(double) * (5 * ND + 3))) / kNodeTile * kNodeTile;
+    constexpr int NT = (kPhasorN + T - 1) / T, NA = (ND * NPMAX + T - 1) / T, NB = (NPMAX + T - 1) / T;
+    const int t = threadIdx.x, np = ev.n_nodes_pad;
     double* g = lds;
     double* mu = g + 2 * ND * np;
     double* xl = mu + ND * np;
@@ -284,17 +293,54 @@ __device__ inline void stage_nrt_tables(EventDev& ev, double* lds) {
     double* p0 = xr + ND * np;
     double* a0 = p0 + np;
     double* x5 = a0 + np;
+    const double2* sph = reinterpret_cast<const double2*>(ev.phasor);
     const double2* sg = reinterpret_cast<const double2*>(ev.g);
-    for (int i = threadIdx.x; i < ND * np; i += blockDim.x) {
-        reinterpret_cast<double2*>(g)[i] = sg[i];
-        mu[i] = ev.mu[i];
-        xl[i] = ev.xL[i];
-        xr[i] = ev.xR[i];
+    double phx[NT], phy[NT], gx[NA], gy[NA], vmu[NA], vxl[NA], vxr[NA], vp0[NB], va0[NB], vx5[NB];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        const double2 v = sph[min(k * T + t, kPhasorN - 1)];
+        phx[k] = v.x;
+        phy[k] = v.y;
     }
-    for (int i = threadIdx.x; i < np; i += blockDim.x) {
-        p0[i] = ev.phi0[i];
-        a0[i] = ev.ia0[i];
-        x5[i] = ev.node_x578[i];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        const int i = min(k * T + t, ND * np - 1);
+        const double2 v = sg[i];
+        gx[k] = v.x;
+        gy[k] = v.y;
+        vmu[k] = ev.mu[i];
+        vxl[k] = ev.xL[i];
+        vxr[k] = ev.xR[i];
+    }
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int i = min(k * T + t, np - 1);
+        vp0[k] = ev.phi0[i];
+        va0[k] = ev.ia0[i];
+        vx5[k] = ev.node_x578[i];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // every load above is issued before the first store
+#pragma unroll
+    for (int k = 0; k < NT; ++k)
+        if (k * T + t < kPhasorN) tab[k * T + t] = double2{phx[k], phy[k]};
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        const int i = k * T + t;
+        if (i < ND * np) {
+            reinterpret_cast<double2*>(g)[i] = double2{gx[k], gy[k]};
+            mu[i] = vmu[k];
+            xl[i] = vxl[k];
+            xr[i] = vxr[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int i = k * T + t;
+        if (i < np) {
+            p0[i] = vp0[k];
+            a0[i] = va0[k];
+            x5[i] = vx5[k];
+        }
     }
     __syncthreads();
     ev.phi0 = p0;
@@ -310,8 +356,12 @@ inline size_t staged_nrt_table_bytes(int nd, int np) { return sizeof(double) * (
 // phase, inverse amplitude and x^5.78; a chain that takes the FP64 branch reads the FP64
 // tables from global memory.
 template <int ND>
-__device__ inline void stage_nrt_tables32(EventDev& ev, double* lds) {
-    const int np = ev.n_nodes_pad;
+__device__ inline void stage_nrt_tables32(EventDev& ev, double2* tab, double* lds) {
+    // One memory round trip, as in stage_nrt_tables.
+    constexpr int T = 64 * kStageChains;
+    constexpr int NPMAX = (int)(kNrtStageMaxBytes / (20 * ND + 24)) / kNodeTile * kNodeTile;
+    constexpr int NT = (kPhasorN + T - 1) / T, NA = (ND * NPMAX + T - 1) / T, NB = (NPMAX + T - 1) / T;
+    const int t = threadIdx.x, np = ev.n_nodes_pad;
     double* p0 = lds;
     double* a0 = p0 + np;
     double* x5 = a0 + np;
@@ -319,17 +369,55 @@ __device__ inline void stage_nrt_tables32(EventDev& ev, double* lds) {
     float* mu = g + 2 * ND * np;
     float* xl = mu + ND * np;
     float* xr = xl + ND * np;
+    const double2* sph = reinterpret_cast<const double2*>(ev.phasor);
     const float2* sg = reinterpret_cast<const float2*>(ev.g32);
-    for (int i = threadIdx.x; i < ND * np; i += blockDim.x) {
-        reinterpret_cast<float2*>(g)[i] = sg[i];
-        mu[i] = ev.mu32[i];
-        xl[i] = ev.xL32[i];
-        xr[i] = ev.xR32[i];
+    double phx[NT], phy[NT], vp0[NB], va0[NB], vx5[NB];
+    float gx[NA], gy[NA], vmu[NA], vxl[NA], vxr[NA];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        const double2 v = sph[min(k * T + t, kPhasorN - 1)];
+        phx[k] = v.x;
+        phy[k] = v.y;
     }
-    for (int i = threadIdx.x; i < np; i += blockDim.x) {
-        p0[i] = ev.phi0[i];
-        a0[i] = ev.ia0[i];
-        x5[i] = ev.node_x578[i];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        const int i = min(k * T + t, ND * np - 1);
+        const float2 v = sg[i];
+        gx[k] = v.x;
+        gy[k] = v.y;
+        vmu[k] = ev.mu32[i];
+        vxl[k] = ev.xL32[i];
+        vxr[k] = ev.xR32[i];
+    }
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int i = min(k * T + t, np - 1);
+        vp0[k] = ev.phi0[i];
+        va0[k] = ev.ia0[i];
+        vx5[k] = ev.node_x578[i];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // every load above is issued before the first store
+#pragma unroll
+    for (int k = 0; k < NT; ++k)
+        if (k * T + t < kPhasorN) tab[k * T + t] = double2{phx[k], phy[k]};
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        const int i = k * T + t;
+        if (i < ND * np) {
+            reinterpret_cast<float2*>(g)[i] = float2{gx[k], gy[k]};
+            mu[i] = vmu[k];
+            xl[i] = vxl[k];
+            xr[i] = vxr[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int i = k * T + t;
+        if (i < np) {
+            p0[i] = vp0[k];
+            a0[i] = va0[k];
+            x5[i] = vx5[k];
+        }
     }
     __syncthreads();
     ev.phi0 = p0;
@@ -341,12 +429,9 @@ __device__ inline void stage_nrt_tables32(EventDev& ev, double* lds) {
     ev.xR32 = xr;
 }
 inline size_t staged_nrt_table32_bytes(int nd, int np) { return (size_t)np * (20 * (size_t)nd + 24); }
-constexpr size_t kNrtStageMaxBytes = 144 * 1024;  // with the phasor table and node parameters: one workgroup per CU
 
 // LDS bytes of the staged tables.
 inline size_t staged_table_bytes(int nd, int np) { return sizeof(double) * (size_t)np * (4 + 3 * (size_t)nd); }
-constexpr size_t kStageMaxBytes = 56 * 1024;  // with the 8 KB phasor table: two workgroups per CU
-constexpr int kStageChains = 8;               // chains (wavefronts) per workgroup sharing the staged tables
 
 // Jacobian entries the TaylorF2 gradient epilogue reads per chain: the intrinsic block
 // (12 rows of 6) and the extrinsic block (9 rows of 4).
@@ -775,15 +860,14 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
         __builtin_amdgcn_sched_barrier(0);  // all LDS reads in flight before the first use
 #pragma unroll
         for (int i = 0; i < NR; ++i) rv[i] = uniform(tmp[i]);
+    } else if constexpr (LT) {
+        extern __shared__ double lds_tables[];
+        if constexpr (WF == kWfNrtv2 && MIXED)
+            stage_nrt_tables32<ND>(ev, tab, lds_tables);
+        else
+            stage_nrt_tables<ND>(ev, tab, lds_tables);
     } else {
         load_phasor_table(ev, tab);
-        if constexpr (LT) {
-            extern __shared__ double lds_tables[];
-            if constexpr (WF == kWfNrtv2 && MIXED)
-                stage_nrt_tables32<ND>(ev, lds_tables);
-            else
-                stage_nrt_tables<ND>(ev, lds_tables);
-        }
     }
     const int lane = threadIdx.x & 63;
     const int64_t chain = (int64_t)blockIdx.x * (LT ? kStageChains : 4) + wave_id();

@@ -835,7 +835,7 @@ def main():
                          "frac_of_hbm_peak": summ_bytes / (summ_us * 1e-6) / 1e9 / PEAK_HBM_GBS},
     }
     progress("forms and summary pass done")
-    out["mala"] = mala_rate(torch, ev, w, max(20, args.steps // 4))
+    out["mala"] = mala_rate(torch, ev, w, max(20, args.steps))
     progress("MALA done")
     out["full_band"] = full_band(torch, max(10, args.steps // 10))
     out["reference_search"] = reference_search(torch)

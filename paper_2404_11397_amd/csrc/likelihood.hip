@@ -14,6 +14,11 @@
 // FP64 unit phasors come from a kPhasorN-entry table in LDS and a short Taylor
 // rotation (unit_phasor, rbl_phasor.h).
 //
+// The FP64 TaylorF2 kernels and the IMRPhenomD_NRTidalv2 gradient kernels stage the
+// event's edge tables in LDS per workgroup of kStageChains chains, in one memory round
+// trip (stage_tf2_workgroup, stage_nrt_tables); the TaylorF2 gradient kernel stages its
+// chains' Jacobian entries and records with them.
+//
 // Mixed precision: the phase is accumulated in FP64 and reduced to (-1/2, 1/2]
 // revolutions in FP64; sin/cos (hardware, revolution argument), the ratio and the
 // per-edge products are FP32; every per-edge term is added to an FP64 accumulator.

@@ -25,9 +25,13 @@ def _cuda(a):
 # 500 bins with 3 detectors: the TaylorF2 FP64 gradient stages the edge tables in LDS
 # (512 padded edges); 700 bins: too large for LDS, the global-table kernel.  The
 # IMRPhenomD_NRTidalv2 FP64 gradient stages its tables up to 1024 padded edges at 3
-# detectors; 1100 bins take its global-table kernel.
+# detectors; 1100 bins take its global-table kernel.  511 / 703 / 1023 bins with 3 / 2 / 1
+# detectors are the largest TaylorF2 tables staged in LDS for each detector count (512, 704
+# and 1024 padded edges: full and partial staging rounds per thread), 1024 bins with one
+# detector the first that is not; the ragged batches leave the last 8-chain workgroup part
+# empty.
 @pytest.mark.parametrize("n_bins,n_det,B", [(1, 1, 1), (63, 2, 5), (64, 3, 64), (65, 2, 257), (500, 3, 9), (700, 3, 17),
-                                            (1100, 3, 5)])
+                                            (1100, 3, 5), (511, 3, 13), (703, 2, 13), (1023, 1, 13), (1024, 1, 3)])
 def test_edge_shapes(approximant, n_bins, n_det, B):
     ev = small_event(approximant=approximant, n_det=n_det, duration=4.0, f_high=512.0, n_bins=n_bins)
     L.prepare(ev)

@@ -235,10 +235,22 @@ __global__ __launch_bounds__(64) void k_chain_setup_grad(const double* __restric
                                                           RefConsts ref, double* __restrict__ rec,
                                                           double* __restrict__ jac, int64_t n_int_blocks, MalaProp mp) {
     const bool intrinsic = (int64_t)blockIdx.x < n_int_blocks;
-    const int64_t gid = ((int64_t)blockIdx.x - (intrinsic ? 0 : n_int_blocks)) * blockDim.x + threadIdx.x;
-    const int lanes = intrinsic ? kIntLanes : kExtLanes;
-    const int64_t b = gid / lanes;
-    const int tg = (int)(gid % lanes);
+    int64_t b;
+    int tg;
+    if (intrinsic) {  // workgroup w: the 8-chain block w
+        const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        b = gid / kIntLanes;
+        tg = (int)(gid % kIntLanes);
+    } else {
+        // XCD-aware: workgroups are dispatched to the 8 XCDs in turn, so block w's intrinsic
+        // workgroup and the likelihood kernel's workgroup of the same 8 chains share XCD w % 8.
+        // Extrinsic workgroup p (n_int_blocks is a multiple of 8) takes blocks
+        // 16 (p / 8) + p % 8 and that + 8, both of its own XCD, in lanes 0-31 and 32-63.
+        const int64_t p = (int64_t)blockIdx.x - n_int_blocks;
+        const int64_t blk = 16 * (p / 8) + p % 8 + (threadIdx.x >= 32 ? 8 : 0);
+        b = blk * 8 + (threadIdx.x & 31) / kExtLanes;
+        tg = (int)(threadIdx.x % kExtLanes);
+    }
     if (b >= B) return;
     double t[13];
     if constexpr (PROP) {
@@ -721,8 +733,11 @@ hipError_t launch_ref_setup(const double* theta, const Network& net, int32_t wav
 hipError_t launch_chain_setup(const double* theta, int64_t B, const Network& net, const RefConsts& ref,
                               double* rec, double* jac, hipStream_t s, KTime kt, const MalaProp* prop) {
     if (jac) {
-        const int64_t n_int = (B * kIntLanes + 63) / 64;
-        const int64_t n_ext = (B * kExtLanes + 63) / 64;
+        // intrinsic workgroups: one per 8-chain block, padded to a multiple of 8; extrinsic: two
+        // blocks each, in groups of 8 workgroups covering 16 blocks (k_chain_setup_grad)
+        const int64_t blocks = (B + 7) / 8;
+        const int64_t n_int = (blocks + 7) / 8 * 8;
+        const int64_t n_ext = (blocks + 15) / 16 * 8;
         if (prop)
             launch_k(k_chain_setup_grad<true>, dim3((unsigned)(n_int + n_ext)), dim3(64), s, kt, theta, B, net, ref,
                      rec, jac, n_int, *prop);

@@ -717,7 +717,9 @@ def mala_rate(torch, ev, w, steps):
         a = float(ch.step((f * sigma) ** 2, lo, hi, xi, logu).double().mean())
         f *= 1.3 if a > 0.6 else 0.7
     step = (f * sigma) ** 2
-    n_rand = 8
+    # a fresh set of random numbers for every step (timed, stamped and acceptance steps), drawn
+    # before the timed region: reused sets would replay a rejected proposal until a chain sticks
+    n_rand = 2 * steps + KERNEL_PASS_CALLS + 8
     xi = torch.randn((n_rand, B, 13), dtype=torch.float64, device="cuda:0", generator=gen)
     logu = torch.log(torch.rand((n_rand, B), dtype=torch.float64, device="cuda:0", generator=gen))
     xis, logus = list(xi), list(logu)
@@ -737,14 +739,15 @@ def mala_rate(torch, ev, w, steps):
                             ramp_fn=lambda: ev.loglike_grad(th_r, out=out_r, workspace=ws_r))
     acc = torch.zeros(B, dtype=torch.int64, device="cuda:0")  # acceptance, outside the timed region
     for j in range(steps):
-        acc += ch.step(step, lo, hi, xi[j % n_rand], logu[j % n_rand])
+        acc += ch.step(step, lo, hi, xis[k[0] % n_rand], logus[k[0] % n_rand])
+        k[0] += 1
     return {"chain_steps_per_s": B * steps / el, "us_per_step": el / steps * 1e6, "kernel_us": ku, "setup_us": su,
             "chains": B, "steps": steps, "acceptance": float(acc.sum()) / (B * steps), "step_factor": f,
             "precision": "fp64",
             "what": "rbl_mala_step on the headline event: two kernels, the gradient setup with the Langevin "
                     "proposal in its prologue and the lnL+grad kernel with the Metropolis decision in its "
                     "epilogue; chains around the injection, preconditioned by the diagonal observed information, "
-                    "step adapted in warm-up; random numbers cycled from 8 pre-drawn sets"}
+                    "step adapted in warm-up; a fresh pre-drawn set of random numbers for every step"}
 
 
 def progress(msg):

@@ -84,7 +84,12 @@ __device__ inline int theta_status(const double* t) {
 __global__ __launch_bounds__(64) void k_chain_setup(const double* __restrict__ theta, int64_t B, Network net,
                                                     RefConsts ref, double* __restrict__ rec, int64_t n_int_blocks) {
     const bool intrinsic = (int64_t)blockIdx.x < n_int_blocks;
-    const int64_t b = ((int64_t)blockIdx.x - (intrinsic ? 0 : n_int_blocks)) * blockDim.x + threadIdx.x;
+    // XCD-aware, as in k_chain_setup_grad: workgroup i of each half (n_int_blocks a multiple of
+    // 8) takes the 8-chain blocks 64 (i / 8) + i % 8 + 8 j, j = 0..7, which the likelihood
+    // kernels' 8-chain workgroups read on the same XCD.
+    const int64_t wi = (int64_t)blockIdx.x - (intrinsic ? 0 : n_int_blocks);
+    const int64_t blk = 64 * (wi / 8) + wi % 8 + 8 * (threadIdx.x / 8);
+    const int64_t b = blk * 8 + threadIdx.x % 8;
     if (b >= B) return;
     double t[13];
 #pragma unroll
@@ -745,7 +750,7 @@ hipError_t launch_chain_setup(const double* theta, int64_t B, const Network& net
             launch_k(k_chain_setup_grad<false>, dim3((unsigned)(n_int + n_ext)), dim3(64), s, kt, theta, B, net, ref,
                      rec, jac, n_int, MalaProp{});
     } else {
-        const int64_t n_half = (B + 63) / 64;
+        const int64_t n_half = ((B + 7) / 8 + 63) / 64 * 8;  // groups of 8 workgroups, 64 blocks
         launch_k(k_chain_setup, dim3((unsigned)(2 * n_half)), dim3(64), s, kt, theta, B, net, ref, rec, n_half);
     }
     return hipGetLastError();

@@ -544,6 +544,20 @@ __device__ inline void stage_tf2_workgroup(EventDev& ev, double2* tab, double* l
     ev.xL = xl;
 }
 
+// Chain of wavefront w in workgroup g.  LDS-table kernels: 8-chain workgroups, chain 8 g + w.
+// Others: 4-chain workgroups taking half (g / 8) % 2 of the 8-chain block 8 (g / 16) + g % 8,
+// which is on the XCD of workgroup g (workgroups are dispatched to the 8 XCDs in turn), as are
+// the setup kernels' workgroups that wrote the block's records.  Grids of 16 (g / 16 + 1)
+// workgroups cover the blocks of 8 (g / 16 + 1) groups.
+template <bool LT>
+__device__ inline int64_t chain_of(unsigned g, int w) {
+    if constexpr (LT) return (int64_t)g * kStageChains + w;
+    const int64_t blk = 8 * (int64_t)(g / 16) + g % 8;
+    return blk * 8 + 4 * ((g / 8) % 2) + w;
+}
+// Workgroups of the 4-chain kernels for B chains (whole groups of 16).
+inline unsigned grid4(int64_t B) { return (unsigned)(((B + 7) / 8 + 7) / 8 * 16); }
+
 template <int ND, bool MIXED, int WF, bool LT = false>
 __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) void k_loglike_fwd(EventDev ev, const double* __restrict__ recs, int64_t B,
                                                      double* __restrict__ lnl) {
@@ -559,7 +573,7 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) void k_loglike_fwd(Ev
         }
     }
     const int lane = threadIdx.x & 63;
-    const int64_t chain = (int64_t)blockIdx.x * (LT ? kStageChains : 4) + wave_id();
+    const int64_t chain = chain_of<LT>(blockIdx.x, wave_id());
     if (chain >= B) return;
     const double* rec = recs + chain * kRecStride;
     const double status = rec[kRecStatus];
@@ -875,7 +889,7 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
         load_phasor_table(ev, tab);
     }
     const int lane = threadIdx.x & 63;
-    const int64_t chain = (int64_t)blockIdx.x * (LT ? kStageChains : 4) + wave_id();
+    const int64_t chain = chain_of<LT>(blockIdx.x, wave_id());
     if (chain >= B) return;
     MalaState ms;
     if constexpr (MALA) ms = mala_load(me, chain, lane);  // in flight during the walk
@@ -1085,7 +1099,7 @@ __global__ __launch_bounds__(LT ? 64 * kStageChains : 256) __attribute__((amdgpu
 template <int ND>
 static void fwd_nd(const EventDev& ev, const double* rec, int64_t B, int mixed, double* lnl, hipStream_t s,
                    KTime kt) {
-    const unsigned grid = (unsigned)((B + 3) / 4);
+    const unsigned grid = grid4(B);
     if (ev.waveform == kWfNrtv2) {
         if (mixed)
             launch_k(k_loglike_fwd<ND, true, kWfNrtv2>, dim3(grid), dim3(256), s, kt, ev, rec, B, lnl);
@@ -1117,7 +1131,7 @@ hipError_t launch_loglike(const EventDev& ev, const double* rec, int64_t B, int 
 template <int ND, bool MALA>
 static void grad_nd(const EventDev& ev, const double* rec, const double* jac, int64_t B, int mixed, double* lnl,
                     double* grad, hipStream_t s, KTime kt, const MalaEpi& me) {
-    const unsigned grid = (unsigned)((B + 3) / 4);
+    const unsigned grid = grid4(B);
     const unsigned grid_lt = (unsigned)((B + kStageChains - 1) / kStageChains);
     const dim3 blk(256), blk_lt(64 * kStageChains);
     if (ev.waveform == kWfNrtv2) {
